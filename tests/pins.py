@@ -1,0 +1,337 @@
+"""Independent checks that pin the FP64 oracle to the paper and to mathematics.
+
+Each function returns a discrepancy (max relative or absolute error) so the
+tests can assert thresholds and the mutation tests can show that a planted
+mistake in the oracle makes at least one of them fail. Nothing here reuses
+the oracle's arithmetic: transforms are explicit DFT matrices, the quadratic
+term is the literal double sum of Eq. (1), growth factors are integrated by
+hand or by scipy's ODE solver.
+"""
+
+import numpy as np
+from scipy.integrate import solve_ivp
+
+import oracle
+
+GAMMA = 0.8
+
+
+# ----------------------------------------------------------------- helpers
+
+def box_modes(n1, n2):
+    K1, K2 = (n1 - 1) // 4, (n2 - 1) // 4
+    return [(a, b) for a in range(-K1, K1 + 1) for b in range(-K2, K2 + 1)]
+
+
+def random_hermitian(n1, n2, rng, scale=1.0):
+    """Random Hermitian coefficients on the box as a dict {k: value}."""
+    K1, K2 = (n1 - 1) // 4, (n2 - 1) // 4
+    coef = {}
+    for a in range(-K1, K1 + 1):
+        for b in range(-K2, K2 + 1):
+            if (b > 0) or (b == 0 and a > 0):
+                v = scale * (rng.standard_normal() + 1j * rng.standard_normal())
+                coef[(a, b)] = v
+                coef[(-a, -b)] = np.conj(v)
+    coef[(0, 0)] = scale * rng.standard_normal() + 0j
+    return coef
+
+
+def dict_to_full(coef, n1, n2):
+    full = np.zeros((n1, n2), dtype=np.complex128)
+    for (a, b), v in coef.items():
+        full[a % n1, b % n2] = v
+    return full
+
+
+def dft_synthesis(coef, n1, n2):
+    """Phi(x_j) = sum_k c_k exp(i k.x_j) by an explicit double loop over modes."""
+    j1 = np.arange(n1)[:, None]
+    j2 = np.arange(n2)[None, :]
+    out = np.zeros((n1, n2), dtype=np.complex128)
+    for (a, b), v in coef.items():
+        out += v * np.exp(2j * np.pi * (a * j1 / n1 + b * j2 / n2))
+    return out
+
+
+def direct_convolution(coef, n1, n2, s=(1.0, 1.0)):
+    """Literal Eq. (1) sum: sum_l kappa_l . kappa_{k-l} c_l c_{k-l} for k in the box."""
+    K1, K2 = (n1 - 1) // 4, (n2 - 1) // 4
+    out = {}
+    for k in box_modes(n1, n2):
+        acc = 0j
+        for l, cl in coef.items():
+            m = (k[0] - l[0], k[1] - l[1])
+            if abs(m[0]) > K1 or abs(m[1]) > K2 or m not in coef:
+                continue
+            dot = s[0] * l[0] * s[0] * m[0] + s[1] * l[1] * s[1] * m[1]
+            acc += dot * cl * coef[m]
+        out[k] = acc
+    return out
+
+
+def eq1_rhs_direct(coef_vec, keys, t, s=(1.0, 1.0), gamma=GAMMA):
+    """Eq. (1) right-hand side with the literal sum, r0 = t, f = 0."""
+    coef = dict(zip(keys, coef_vec))
+    n1 = 4 * max(abs(k[0]) for k in keys) + 1
+    n2 = 4 * max(abs(k[1]) for k in keys) + 1
+    conv = direct_convolution(coef, n1, n2, s)
+    out = np.empty(len(keys), dtype=np.complex128)
+    for i, k in enumerate(keys):
+        kap = np.hypot(s[0] * k[0], s[1] * k[1])
+        sigma = -kap * kap / t ** 2 + gamma * kap / (2 * t)
+        out[i] = sigma * coef[k] - conv[k] / (2 * t ** 2)
+    return out
+
+
+# -------------------------------------------------------------------- pins
+
+def pin_transform_bruteforce(n1=12, n2=20, seed=0):
+    rng = np.random.default_rng(seed)
+    coef = random_hermitian(n1, n2, rng)
+    full = dict_to_full(coef, n1, n2)
+    ref = dft_synthesis(coef, n1, n2)
+    e1 = np.abs(oracle.synthesize(full) - ref).max() / np.abs(ref).max()
+    back = oracle.analyse(ref)
+    e2 = np.abs(back - full).max() / np.abs(full).max()
+    return max(e1, e2)
+
+
+def pin_convolution_direct(n1=13, n2=17, seed=1, s=(1.0, 1.0), hermitian=True):
+    rng = np.random.default_rng(seed)
+    if hermitian:
+        coef = random_hermitian(n1, n2, rng)
+    else:
+        coef = {k: rng.standard_normal() + 1j * rng.standard_normal() for k in box_modes(n1, n2)}
+    full = dict_to_full(coef, n1, n2)
+    p = oracle.Params(n1, n2, axis_scale=s)
+    got = oracle.convolution_sum(full, p)
+    ref = direct_convolution(coef, n1, n2, s)
+    scale = max(abs(v) for v in ref.values())
+    err = max(abs(got[k[0] % n1, k[1] % n2] - v) for k, v in ref.items())
+    outside = np.abs(got * ~oracle.box_mask(n1, n2)).max()
+    return max(err, outside) / scale
+
+
+def pin_single_cosine(n1=32, n2=48, k=(3, 4), a=0.7, psi=0.3, s=(1.0, 1.0)):
+    coef = {k: 0.5 * a * np.exp(1j * psi), (-k[0], -k[1]): 0.5 * a * np.exp(-1j * psi)}
+    full = dict_to_full(coef, n1, n2)
+    p = oracle.Params(n1, n2, axis_scale=s)
+    got = oracle.convolution_sum(full, p)
+    kap2 = (s[0] * k[0]) ** 2 + (s[1] * k[1]) ** 2
+    ref = np.zeros_like(got)
+    ref[0, 0] = -a * a * kap2 / 2
+    ref[(2 * k[0]) % n1, (2 * k[1]) % n2] = a * a * kap2 / 4 * np.exp(2j * psi)
+    ref[(-2 * k[0]) % n1, (-2 * k[1]) % n2] = a * a * kap2 / 4 * np.exp(-2j * psi)
+    return np.abs(got - ref).max() / (a * a * kap2)
+
+
+def pin_two_cosines(n1=48, n2=48, k=(2, 5), l=(3, -1), a=0.4, b=0.9, p1=0.2, p2=1.1):
+    coef = {}
+    for kk, amp, ph in ((k, a, p1), (l, b, p2)):
+        coef[kk] = 0.5 * amp * np.exp(1j * ph)
+        coef[(-kk[0], -kk[1])] = 0.5 * amp * np.exp(-1j * ph)
+    full = dict_to_full(coef, n1, n2)
+    p = oracle.Params(n1, n2)
+    got = oracle.convolution_sum(full, p)
+    dot = k[0] * l[0] + k[1] * l[1]
+    kk2, ll2 = k[0] ** 2 + k[1] ** 2, l[0] ** 2 + l[1] ** 2
+    ref = {}
+
+    def put(m, v):
+        ref[m] = ref.get(m, 0) + v
+
+    put((0, 0), -(a * a * kk2 + b * b * ll2) / 2)
+    for sgn in (1, -1):
+        put((sgn * 2 * k[0], sgn * 2 * k[1]), a * a * kk2 / 4 * np.exp(sgn * 2j * p1))
+        put((sgn * 2 * l[0], sgn * 2 * l[1]), b * b * ll2 / 4 * np.exp(sgn * 2j * p2))
+        put((sgn * (k[0] + l[0]), sgn * (k[1] + l[1])), a * b * dot / 2 * np.exp(sgn * 1j * (p1 + p2)))
+        put((sgn * (k[0] - l[0]), sgn * (k[1] - l[1])), -a * b * dot / 2 * np.exp(sgn * 1j * (p1 - p2)))
+    refarr = np.zeros_like(got)
+    for m, v in ref.items():
+        refarr[m[0] % n1, m[1] % n2] += v
+    return np.abs(got - refarr).max() / (a * b * abs(dot))
+
+
+def hand_growth(kap, t, t0, gamma=GAMMA):
+    """exp of int_{t0}^{t} (-kap^2/s^2 + gamma kap/(2 s)) ds, integrated by hand."""
+    return np.exp(kap * kap * (1.0 / t - 1.0 / t0) + 0.5 * gamma * kap * np.log(t / t0))
+
+
+def pin_linear_growth(dt=1.0, nsteps=50, t0=200.0, amp=1e-30):
+    modes = [(1, 0), (3, 4), (6, 8), (0, 13), (24, 32), (48, 64), (72, 96)]
+    n1, n2 = 300, 400
+    coef = {}
+    for m in modes:
+        coef[m] = amp
+        coef[(-m[0], -m[1])] = amp
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    out = oracle.run(dict_to_full(coef, n1, n2), p, nsteps)
+    t = t0 + nsteps * dt
+    err = 0.0
+    for m in modes:
+        g = hand_growth(np.hypot(*m), t, t0)
+        err = max(err, abs(out[m[0] % n1, m[1] % n2] / amp - g) / g)
+    return err
+
+
+def pin_linear_growth_ode(kap=37.0, t0=200.0, t1=260.0):
+    """scipy DOP853 on dy/dt = sigma(t) y against the oracle's step factors."""
+    sol = solve_ivp(lambda t, y: (-kap * kap / t ** 2 + GAMMA * kap / (2 * t)) * y,
+                    (t0, t1), [1.0], method="DOP853", rtol=1e-12, atol=1e-14)
+    ref = sol.y[0, -1]
+    n1 = n2 = 4 * 40 + 4
+    p = oracle.Params(n1, n2, t0=t0, dt=(t1 - t0) / 12)
+    acc = 1.0
+    k1 = oracle.wavenumbers(n1)
+    i = int(np.nonzero(k1 == 37)[0][0])
+    for n in range(12):
+        acc *= np.exp(oracle.growth_exponent(p, n))[i, 0]
+    return abs(acc - ref) / abs(ref)
+
+
+def pin_first_step_worked_example():
+    """One step from a single mode k = (3, 4), a = 1e-3, psi = 0, dt = 0.25, t0 = 200."""
+    n1 = n2 = 64
+    a = 1e-3
+    coef = {(3, 4): a / 2, (-3, -4): a / 2}
+    p = oracle.Params(n1, n2, t0=200.0, dt=0.25)
+    out = oracle.step(dict_to_full(coef, n1, n2), p, 0)
+    # mode 0: E_0 = 1, N_0 = c * a^2 |k|^2 / 2 with c = 1/(2*200^2)
+    e0 = abs(out[0, 0] - 3.90625e-11) / 3.90625e-11
+    e10 = hand_growth(10.0, 200.25, 200.0)
+    ref = e10 * (-1.953125e-11)
+    e1 = abs(out[6, 8] - ref) / abs(ref)
+    return max(e0, e1)
+
+
+def pin_k0_parseval(n1=24, n2=40, seed=3):
+    rng = np.random.default_rng(seed)
+    coef = random_hermitian(n1, n2, rng, scale=0.3)
+    full = oracle.symmetrise(dict_to_full(coef, n1, n2))
+    p = oracle.Params(n1, n2, t0=50.0, dt=0.5)
+    out = oracle.step(full, p, 3)
+    t = 50.0 + 3 * 0.5
+    kap2 = 0.0
+    for (a, b), v in coef.items():
+        kap2 += (a * a + b * b) * abs(v) ** 2
+    ref = 0.5 * kap2 / (2 * t * t)
+    return abs((out[0, 0] - full[0, 0]) - ref) / abs(ref)
+
+
+def reference_trajectory(n=13, t0=5.0, t1=7.0, seed=4, amp=0.5):
+    rng = np.random.default_rng(seed)
+    coef = random_hermitian(n, n, rng, scale=amp)
+    keys = list(coef.keys())
+    y0 = np.array([coef[k] for k in keys])
+
+    def f(t, y):
+        c = y[: len(keys)] + 1j * y[len(keys):]
+        r = eq1_rhs_direct(c, keys, t)
+        return np.concatenate([r.real, r.imag])
+
+    sol = solve_ivp(f, (t0, t1), np.concatenate([y0.real, y0.imag]), method="DOP853",
+                    rtol=1e-11, atol=1e-13)
+    yT = sol.y[: len(keys), -1] + 1j * sol.y[len(keys):, -1]
+    return coef, keys, yT
+
+
+def pin_convergence(n=13, t0=5.0, t1=7.0, steps=(20, 40, 80)):
+    coef, keys, yT = reference_trajectory(n, t0, t1)
+    full = dict_to_full(coef, n, n)
+    errs = []
+    for ns in steps:
+        p = oracle.Params(n, n, t0=t0, dt=(t1 - t0) / ns)
+        out = oracle.run(full, p, ns)
+        got = np.array([out[k[0] % n, k[1] % n] for k in keys])
+        errs.append(np.linalg.norm(got - yT) / np.linalg.norm(yT))
+    return errs
+
+
+def area_series(b, terms=60):
+    """(1/2pi) int_0^{2pi} sqrt(1 + b sin^2 u) du - 1 as a power series in b (b < 1)."""
+    total = 0.0
+    binom = 1.0
+    central = 1.0
+    for j in range(1, terms):
+        binom *= (0.5 - (j - 1)) / j        # C(1/2, j)
+        central *= (2 * j) * (2 * j - 1) / (j * j) / 4.0   # C(2j, j) / 4^j
+        total += binom * central * b ** j
+    return total
+
+
+def pin_diagnostics_single_cosine(n1=32, n2=64, k=(2, 3), a=0.5, psi=0.4, mean=0.05, n=0):
+    p = oracle.Params(n1, n2, t0=3.0, dt=0.1)
+    coef = {k: 0.5 * a * np.exp(1j * psi), (-k[0], -k[1]): 0.5 * a * np.exp(-1j * psi),
+            (0, 0): mean + 0j}
+    full = dict_to_full(coef, n1, n2)
+    rbar, vel, area = oracle.diagnostics(full, p, n)
+    r = 3.0 + n * 0.1
+    kap2 = k[0] ** 2 + k[1] ** 2
+    e_r = abs(rbar - (r + mean)) / (r + mean)
+    e_v = abs(vel - a * a * kap2 / 2 / (2 * r * r)) / (a * a * kap2 / 2 / (2 * r * r))
+    b = a * a * kap2 / (r * r)
+    ref_area = area_series(b)
+    e_a = abs(area - ref_area) / ref_area
+    return max(e_r, e_v, e_a)
+
+
+def real_inner(a, b):
+    """Grid inner product of two band-limited real fields from their coefficients."""
+    return float(a.size * np.real(np.vdot(a, b)))
+
+
+def pin_adjoint_dot_product(n1=16, n2=24, seed=5, t0=5.0, dt=0.3):
+    """<lambda, J d> = <J^T lambda, d> for one step; J d by central differences,
+    which are exact up to rounding because the step is quadratic in Phi."""
+    rng = np.random.default_rng(seed)
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    phi = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, 0.4), n1, n2))
+    d = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, 1.0), n1, n2))
+    lam = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, 1.0), n1, n2))
+    eps = 1e-3
+    jd = (oracle.step(phi + eps * d, p, 2) - oracle.step(phi - eps * d, p, 2)) / (2 * eps)
+    lhs = real_inner(lam, jd)
+    rhs = real_inner(oracle.step_adjoint(phi, lam, p, 2), d)
+    return abs(lhs - rhs) / abs(lhs)
+
+
+def pin_area_gradient_fd(n1=16, n2=24, seed=6, t0=2.0, amp=0.6):
+    """dJ/dPhi against central differences of J at one state."""
+    rng = np.random.default_rng(seed)
+    p = oracle.Params(n1, n2, t0=t0, dt=0.1)
+    phi = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, amp), n1, n2))
+    g = oracle.area_gradient(phi, p, 0)
+    worst = 0.0
+    for _ in range(4):
+        v = oracle.project(rng.standard_normal((n1, n2)))
+        eps = 1e-5
+        fd = (oracle.area_excess(phi + eps * v, p, 0) - oracle.area_excess(phi - eps * v, p, 0)) / (2 * eps)
+        worst = max(worst, abs(fd - real_inner(g, v)) / abs(fd))
+    return worst
+
+
+def pin_trajectory_gradient_fd(n1=16, n2=24, seed=7, t0=3.0, dt=0.2, nsteps=10, amp=0.5):
+    """Gradient of J(Phi^T) with respect to a projected physical initial field
+    against central differences along random grid directions."""
+    rng = np.random.default_rng(seed)
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    phi0 = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, amp), n1, n2))
+    _, lam = oracle.trajectory_gradient(phi0, p, nsteps)
+    grad_grid = oracle.synthesize(lam).real
+    worst = 0.0
+    for _ in range(4):
+        v = rng.standard_normal((n1, n2))
+        vp = oracle.project(v)
+        eps = 1e-5
+
+        def J(x):
+            return oracle.area_excess(oracle.run(x, p, nsteps), p, nsteps)
+
+        fd = (J(phi0 + eps * vp) - J(phi0 - eps * vp)) / (2 * eps)
+        worst = max(worst, abs(fd - float((grad_grid * v).sum())) / abs(fd))
+    return worst
+
+
+def pin_convolution_direct_anisotropic():
+    return pin_convolution_direct(16, 24, seed=40, s=(2.0, 0.5))
