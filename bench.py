@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the spectral flame step on one MI355X.
+
+One bench step is one integrating-factor Euler step of Eq. (1) for the
+2048 x 4096 flame (row kernel + column kernel), with the FP64 diagnostic
+reductions every 50 steps as in that workload. Inputs are resident in HBM
+before the timed region starts. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
+                  "paper_0911_2889_amd/csrc/flame_dev.hpp")
+
+
+def algorithmic_bytes(n1, n2):
+    """Bytes each kernel of one step must move (FP32 complex = 8 bytes).
+
+    row: read the column-transformed gradient spectrum N1 x (2K2+1), write
+         the row transform of |grad Phi|^2, N1 x (K2+1);
+    col: read that N1 x (K2+1), read and write the state (2K1+1) x (K2+1),
+         write the next gradient spectrum N1 x (2K2+1).
+    """
+    k1, k2 = (n1 - 1) // 4, (n2 - 1) // 4
+    row = 8 * (n1 * (2 * k2 + 1) + n1 * (k2 + 1))
+    col = 8 * (n1 * (k2 + 1) + 2 * (2 * k1 + 1) * (k2 + 1) + n1 * (2 * k2 + 1))
+    return {"row": row, "col": col}
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_oracle_baseline(w, half, seconds):
+    """Time the FP64 oracle on the host on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+
+    p = oracle.Params(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
+    cur = oracle.run(oracle.half_to_full(half.astype(np.complex128), w.n1, w.n2), p, 0)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        cur = oracle.step(cur, p, steps)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= w.steps:
+            break
+    return {
+        "value": w.points * steps / el,
+        "unit": "point-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"first {steps} steps of {w.name} from its initial condition, FP64 numpy "
+                  f"(single-threaded pocketfft), {el:.1f} s",
+    }, steps, oracle.full_to_half(cur, w.n1, w.n2)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="flame2048x4096")
+    ap.add_argument("--diag-every", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU slab decomposition is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0911_2889_amd import FlameSim
+
+    w = synth.WORKLOADS[args.workload]
+    half = synth.workload_spectrum(w)
+    sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
+    diag_buf = torch.zeros((max(1, args.steps // max(1, args.diag_every)) + 1, 4), dtype=torch.float64,
+                           device=sim.device)
+
+    def run_steps(k, time_kernels):
+        if time_kernels:
+            sim.timing_begin()
+        done, d = 0, 0
+        while done < k:
+            chunk = min(args.diag_every - (done % args.diag_every), k - done)
+            sim.step(chunk)
+            done += chunk
+            if done % args.diag_every == 0:
+                sim.diagnostics(out=diag_buf[d % diag_buf.shape[0]])
+                d += 1
+        return sim.timing_end() if time_kernels else None
+
+    # warm-up from the initial condition
+    sim.set_spectrum(half)
+    run_steps(args.warmup, False)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    # timed region 1: plain launches -> value
+    sim.set_spectrum(half)
+    sim.step(0)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    run_steps(args.steps, False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+
+    # timed region 2: the same steps with HIP events around every kernel -> roofline
+    sim.set_spectrum(half)
+    sim.step(0)
+    torch.cuda.synchronize()
+    kt = run_steps(args.steps, True)
+    torch.cuda.synchronize()
+    final_diag = diag_buf[0].cpu().tolist()
+
+    nbytes = algorithmic_bytes(w.n1, w.n2)
+    per_launch = {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")}
+    dom = max(per_launch, key=per_launch.get)
+    achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, w.name)
+    result = {
+        "metric": "flame point-steps/s (forward step, FP32 vs FP64 oracle at 1e-5; % HBM roofline)",
+        "value": w.points * args.steps / (ms * 1e-3),
+        "unit": "point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
+                   "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dom}_kernel",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": nbytes[dom],
+            "ms_per_launch": per_launch[dom],
+        },
+        "kernels_ms_per_step": {k: kt[k][0] / max(1, args.steps) for k in ("row", "col", "diag")},
+        "step_bytes": nbytes["row"] + nbytes["col"],
+        "step_hbm_frac": (nbytes["row"] + nbytes["col"]) / (ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "diagnostics_at_first_checkpoint": final_diag,
+    }
+
+    if not args.no_cpu:
+        base, nref, ref = cpu_oracle_baseline(w, half, args.cpu_seconds)
+        result["cpu_baseline"] = base
+        sim.set_spectrum(half)
+        sim.step(nref)
+        got = sim.spectrum().cpu().numpy().astype(np.complex128)
+        wgt = np.full(ref.shape, 2.0)
+        wgt[:, 0] = 1.0
+        err = float(np.sqrt((wgt * np.abs(got - ref) ** 2).sum() / (wgt * np.abs(ref) ** 2).sum()))
+        result["parity"] = {"rel_l2_vs_oracle": err, "steps": nref, "tolerance": 1e-5}
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

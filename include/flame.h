@@ -1,0 +1,152 @@
+/*
+ * flame.h - C ABI of the MI355X (gfx950) spectral flame-front stepper.
+ *
+ * The library advances the Fourier coefficients of the flame perturbation
+ * Phi(theta, phi, t) of an expanding sphere of radius r0(t) = t under Eq. (1)
+ * of V. Karlin, "Global communications in multiprocessor simulations of
+ * flames" (Section 2):
+ *
+ *   dPhi~_k/dt = (-|kappa|^2/r0^2 + gamma |kappa|/(2 r0)) Phi~_k
+ *                - 1/(2 r0^2) sum_l kappa_l . kappa_{k-l} Phi~_l Phi~_{k-l},
+ *
+ * kappa = (s1 k1, s2 k2) with s1 = s2 = theta_pi for the literal equation, no
+ * forcing. The quadratic term is evaluated on the padded N1 x N2 grid the way
+ * Section 3 describes (transforms of the gradient components, pointwise
+ * product, inverse transforms); the retained box is |k_i| <= K_i with
+ * K_i = N_i/4 - 1 (the augmented-array size rule of Section 3 with k0 = 3).
+ * Time integration is integrating-factor Euler: the linear operator is
+ * integrated exactly over each step, the quadratic term is explicit.
+ *
+ * Conventions for every entry point:
+ *  - All calls return 0 (FLAME_OK) or a negative FLAME_ERR_* code; the text of
+ *    the last error of the calling thread is returned by flame_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Every pointer named "dev" is device memory on the device that was current
+ *    at flame_init. The caller owns all device memory (states, workspace,
+ *    input and output buffers); the plan owns only host-side metadata.
+ *  - Work is queued asynchronously on the stream given to flame_init
+ *    (a hipStream_t passed as void*, 0 for the null stream). Calls that only
+ *    queue device work do not synchronise.
+ *  - A plan is not thread-safe; use one plan per stream.
+ *
+ * Supported grids: N1 and N2 powers of two with 16 <= N_i <= 4096.
+ *
+ * State layout (internal to the stepper but documented for checkpointing):
+ * complex64 S[m][s], m = k2 in [0, N2/4), s in [0, N1/2) with k1 = s - N1/4;
+ * entries with s = 0 (k1 = -N1/4, outside the box) are zero. The k2 < 0
+ * half follows from Phi~(-k) = conj(Phi~(k)). Size: N1*N2 bytes.
+ *
+ * Canonical spectrum layout (flame_set_spectrum / flame_get_spectrum):
+ * complex64 half[k1 + K1][k2], shape (2 K1 + 1) x (K2 + 1), row-major;
+ * the k2 = 0 column holds both signs of k1.
+ */
+#ifndef FLAME_H
+#define FLAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLAME_OK 0
+#define FLAME_ERR_INVALID_ARG (-1)
+#define FLAME_ERR_WORKSPACE_TOO_SMALL (-2)
+#define FLAME_ERR_HIP (-3)
+#define FLAME_ERR_UNSUPPORTED_SIZE (-4)
+#define FLAME_ERR_NONFINITE (-5)
+
+typedef struct flame_plan_s* flame_plan;
+
+/* Problem description of one flame (Section 2: gamma = 0.8, t0 = 200 in the
+ * paper's runs; theta_pi is the segment integer; dt is the fixed step). */
+typedef struct {
+  int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 4096] */
+  double gamma;           /* density contrast 1 - rho_b/rho_u, >= 0 */
+  double theta_pi;        /* segment integer theta_pi, > 0 */
+  double t0;              /* time of step index 0, > 0 (r0(t) = t) */
+  double dt;              /* time step, > 0 */
+  double axis_scale[2];   /* wavenumber scale per axis; {0, 0} means {theta_pi, theta_pi} */
+} flame_desc;
+
+/* Bytes of one flame's state buffer (complex64 S, see the layout above). */
+int flame_state_bytes(const flame_desc* desc, size_t* bytes);
+
+/* Bytes of workspace that flame_init needs for n_flames flames described by
+ * descs[0..n_flames-1]. */
+int flame_workspace_bytes(const flame_desc* descs, int32_t n_flames, size_t* bytes);
+
+/* Create a plan for n_flames flames. states[f] (dev, flame_state_bytes each)
+ * and ws (dev, ws_bytes >= flame_workspace_bytes) stay bound to the plan until
+ * flame_destroy. Builds twiddle tables on the host (double precision, rounded
+ * once to float) and copies them into ws on the stream. The states are not
+ * initialised: call flame_set_spectrum or flame_set_state next. */
+int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, void* ws, size_t ws_bytes,
+               void* hip_stream, flame_plan* out);
+
+/* Load flame `flame` from the canonical half spectrum (dev, complex64, see
+ * above) and set the plan's step index to n (time t0 + n dt). The k2 = 0
+ * column is symmetrised: entries with k1 > 0 are copied conjugated onto
+ * k1 < 0 and Im Phi~_0 is set to 0 (Section 3, symmetrisation). */
+int flame_set_spectrum(flame_plan plan, int32_t flame, const void* half, int64_t n);
+
+/* Write flame `flame`'s state in the canonical half layout (dev, complex64). */
+int flame_get_spectrum(flame_plan plan, int32_t flame, void* half);
+
+/* Project a physical field phi (dev, float32, n1 x n2 row-major, phi fastest)
+ * onto the retained box: Phi~ = (1/P) DFT(phi) for |k_i| <= K_i, then
+ * symmetrise. Sets the step index to n. */
+int flame_set_state(flame_plan plan, int32_t flame, const float* phi, int64_t n);
+
+/* Synthesize flame `flame`'s field on the grid into phi (dev, float32,
+ * n1 x n2 row-major): Phi(x_j) = sum_k Phi~_k exp(i k.x_j). */
+int flame_get_state(flame_plan plan, int32_t flame, float* phi);
+
+/* The caller wrote the state buffers directly (e.g. restored a checkpoint
+ * with a device copy): set the step index to n and mark the plan's
+ * intermediate arrays stale so the next step rebuilds them. */
+int flame_state_modified(flame_plan plan, int64_t n);
+
+/* Step index of the plan (time of flame f is t0_f + index * dt_f). */
+int flame_step_index(flame_plan plan, int64_t* n);
+
+/* Advance every bound flame by nsteps integrating-factor Euler steps of
+ * Eq. (1): Phi~ <- E_k (Phi~ + dt N_k), E_k = exp(int sigma_k dt) over the
+ * step, N_k = (1/(2 r0(t_n)^2)) DFT_k[|grad Phi|^2] / P on the box, followed by
+ * the symmetrisation of Section 3. nsteps >= 0. */
+int flame_step(flame_plan plan, int32_t nsteps);
+
+/* Integral diagnostics of flame `flame` at the current step (the averages of
+ * Section 3; <Phi_t> as plotted in Section 2), accumulated in double:
+ *   out4[0] = mean radius r0(t) + Re Phi~_0,
+ *   out4[1] = averaged velocity <Phi_t> = dPhi~_0/dt = sum_k |kappa|^2 |Phi~_k|^2 / (2 r0^2),
+ *   out4[2] = area excess J = mean over the grid of sqrt(1 + x) - 1,
+ *             x = |grad Phi|^2 / r0^2, evaluated as x / (1 + sqrt(1 + x)),
+ *   out4[3] = 1 if every state entry is finite, else 0.
+ * out4 is dev memory (4 doubles), written on the stream. */
+int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
+
+/* Start timing every kernel launch that flame_step and flame_diagnostics
+ * queue from now on: each launch is bracketed by a pair of HIP events
+ * recorded on the plan's stream (benchmarking aid; adds two event records per
+ * launch). */
+int flame_timing_begin(flame_plan plan);
+
+/* Stop timing, synchronise the plan's stream and report the summed kernel
+ * durations in milliseconds and the launch counts, per kind:
+ * [0] row kernels, [1] column kernels, [2] diagnostics kernels.
+ * ms3 and counts3 are host arrays of 3 entries. */
+int flame_timing_end(flame_plan plan, double* ms3, int64_t* counts3);
+
+/* Release the plan's host metadata (device buffers stay the caller's). */
+int flame_destroy(flame_plan plan);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* flame_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLAME_H */

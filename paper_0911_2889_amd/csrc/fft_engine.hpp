@@ -1,0 +1,277 @@
+// Register/LDS Stockham FFT engine for gfx950 (wave64).
+//
+// One length-N transform (N = 2^LOGN, 16 <= N <= 8192) is owned by a group
+// of G = N/16 threads. Thread t holds the 16 points x[t + G*i], i = 0..15,
+// in registers. A pass of radix R (16, or the 2/4/8 remainder in the last
+// pass) lets each thread run 16/R butterflies on its own registers; between
+// passes the group exchanges data through LDS (Stockham autosort ordering,
+// so input and output both come out in natural order with the same
+// "t + G*i" register map). Global loads and stores therefore stay coalesced:
+// consecutive threads touch consecutive positions.
+//
+// Several groups share a workgroup by interleaving: group g of B stores
+// element idx at lds[pad(idx) * B + g]; pad() inserts one slot every 16
+// entries to break the power-of-two bank strides of the first passes.
+//
+// Twiddles come from a table built on the host in double precision and
+// rounded once to float: pass p >= 1 with Ns = 16^p and radix R stores
+// w(k, r) = exp(-2 pi i r k / (Ns R)) at [k * R + r], k < Ns, r < R.
+//
+// The pass functions are __host__ __device__ so the same code can be
+// driven thread by thread on the CPU to check the index maps.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace ff {
+
+constexpr int kPts = 16;  // points per thread
+
+struct PassPlan {
+  int logn, n, g, npass;
+  int radix[4];
+  int ns[4];
+  int tw_off[4];
+  int tw_size;
+};
+
+constexpr PassPlan make_pass_plan(int logn) {
+  PassPlan p{};
+  p.logn = logn;
+  p.n = 1 << logn;
+  p.g = p.n / kPts;
+  const int full = logn / 4, rem = logn % 4;
+  p.npass = full + (rem ? 1 : 0);
+  int ns = 1, off = 0;
+  for (int q = 0; q < p.npass; ++q) {
+    p.radix[q] = q < full ? 16 : (1 << rem);
+    p.ns[q] = ns;
+    p.tw_off[q] = off;
+    if (q > 0) off += ns * p.radix[q];
+    ns *= p.radix[q];
+  }
+  for (int q = p.npass; q < 4; ++q) {
+    p.radix[q] = 1;
+    p.ns[q] = ns;
+    p.tw_off[q] = off;
+  }
+  p.tw_size = off;
+  return p;
+}
+
+__host__ __device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
+
+template <int LOGN>
+struct Shape {
+  static constexpr PassPlan plan = make_pass_plan(LOGN);
+  static constexpr int N = 1 << LOGN;
+  static constexpr int G = N / kPts;
+  static constexpr int NPASS = plan.npass;
+  static constexpr int LDS = N + N / 16;  // padded slots per transform
+  static constexpr int radix(int p) { return plan.radix[p]; }
+  static constexpr int ns(int p) { return plan.ns[p]; }
+  static constexpr int tw_off(int p) { return plan.tw_off[p]; }
+  static_assert(LOGN >= 4 && LOGN <= 13, "transform length must be 16..8192");
+};
+
+// ---------------------------------------------------------------- complex
+
+__host__ __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// multiply by the quarter-turn root: -i for the forward transform, +i for the inverse
+template <bool INV>
+__host__ __device__ __forceinline__ float2 mul_q(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// multiply by exp(-+ i pi/4) (the eighth root of the transform's direction)
+template <bool INV>
+__host__ __device__ __forceinline__ float2 mul_e1(float2 a) {
+  constexpr float c = 0.70710678118654752440f;
+  return INV ? make_float2(c * (a.x - a.y), c * (a.x + a.y)) : make_float2(c * (a.x + a.y), c * (a.y - a.x));
+}
+
+// multiply by exp(-+ 3 i pi/4)
+template <bool INV>
+__host__ __device__ __forceinline__ float2 mul_e3(float2 a) {
+  constexpr float c = 0.70710678118654752440f;
+  return INV ? make_float2(-c * (a.x + a.y), c * (a.x - a.y)) : make_float2(c * (a.y - a.x), -c * (a.x + a.y));
+}
+
+// multiply by exp(s * i * theta) with (cos, sin) given for the forward sign convention
+template <bool INV>
+__host__ __device__ __forceinline__ float2 mul_root(float2 a, float c, float s) {
+  // forward root: c - i s ; inverse: c + i s
+  return INV ? make_float2(a.x * c - a.y * s, a.x * s + a.y * c) : make_float2(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// ------------------------------------------------------- small DFTs in registers
+// X[m] = sum_r x[r] w^(r m), w = exp(-2 pi i / R) (forward) or exp(+2 pi i / R) (inverse)
+
+template <bool INV>
+__host__ __device__ __forceinline__ void dft2(float2& a, float2& b) {
+  const float2 s = cadd(a, b), d = csub(a, b);
+  a = s;
+  b = d;
+}
+
+template <bool INV>
+__host__ __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3), a3 = mul_q<INV>(csub(x1, x3));
+  x0 = cadd(a0, a2);
+  x2 = csub(a0, a2);
+  x1 = cadd(a1, a3);
+  x3 = csub(a1, a3);
+}
+
+template <bool INV>
+__host__ __device__ __forceinline__ void dft8(float2* x) {
+  float2 e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  float2 o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  o1 = mul_e1<INV>(o1);
+  o2 = mul_q<INV>(o2);
+  o3 = mul_e3<INV>(o3);
+  x[0] = cadd(e0, o0);
+  x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1);
+  x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2);
+  x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3);
+  x[7] = csub(e3, o3);
+}
+
+template <bool INV>
+__host__ __device__ __forceinline__ void dft16(float2* x) {
+  // r = 4 r1 + r2, m = m1 + 4 m2: length-4 transforms over r1, inner roots, length-4 over r2
+  constexpr float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  float2 y[16];
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) {
+    float2 a = x[r2], b = x[r2 + 4], c = x[r2 + 8], d = x[r2 + 12];
+    dft4<INV>(a, b, c, d);
+    y[4 * r2 + 0] = a;
+    y[4 * r2 + 1] = b;
+    y[4 * r2 + 2] = c;
+    y[4 * r2 + 3] = d;
+  }
+  // y[4 r2 + m1] *= w16^(r2 m1)
+  y[5] = mul_root<INV>(y[5], c1, s1);    // w^1
+  y[6] = mul_e1<INV>(y[6]);              // w^2
+  y[7] = mul_root<INV>(y[7], s1, c1);    // w^3: cos(3pi/8) = sin(pi/8)
+  y[9] = mul_e1<INV>(y[9]);              // w^2
+  y[10] = mul_q<INV>(y[10]);             // w^4
+  y[11] = mul_e3<INV>(y[11]);            // w^6
+  y[13] = mul_root<INV>(y[13], s1, c1);  // w^3
+  y[14] = mul_e3<INV>(y[14]);            // w^6
+  y[15] = mul_root<INV>(y[15], -c1, -s1);  // w^9: cos(9pi/8) = -cos(pi/8), sin(9pi/8) = -sin(pi/8)
+#pragma unroll
+  for (int m1 = 0; m1 < 4; ++m1) {
+    float2 a = y[m1], b = y[4 + m1], c = y[8 + m1], d = y[12 + m1];
+    dft4<INV>(a, b, c, d);
+    x[m1] = a;
+    x[m1 + 4] = b;
+    x[m1 + 8] = c;
+    x[m1 + 12] = d;
+  }
+}
+
+template <int R, bool INV>
+__host__ __device__ __forceinline__ void dft(float2* x) {
+  if constexpr (R == 2) {
+    dft2<INV>(x[0], x[1]);
+  } else if constexpr (R == 4) {
+    dft4<INV>(x[0], x[1], x[2], x[3]);
+  } else if constexpr (R == 8) {
+    dft8<INV>(x);
+  } else {
+    static_assert(R == 16, "radix");
+    dft16<INV>(x);
+  }
+}
+
+// ------------------------------------------------------------ Stockham passes
+
+template <int LOGN, bool INV>
+struct Fft {
+  using S = Shape<LOGN>;
+
+  // Pass P: thread t runs 16/R butterflies on its registers. Butterfly b has
+  // global index j = t + b*G and inputs x[j + r*N/R] = v[b + r*16/R]; it
+  // applies the twiddles w(j mod Ns, r), the radix-R DFT, and sends output r
+  // to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns: into LDS, or, in the
+  // last pass (Ns * R = N), back into the same registers.
+  template <int P>
+  static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[kPts], int t, float2* lds, int stride,
+                                                              const float2* __restrict__ tw) {
+    constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
+    constexpr bool LAST = (P + 1 == S::NPASS);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      float2 x[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
+      const int j = t + b * S::G;
+      const int k = j & (NS - 1);
+      if constexpr (P > 0) {
+        const float2* w = tw + S::tw_off(P) + k * R;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 wr = w[r];
+          if (INV) wr.y = -wr.y;
+          x[r] = cmul(x[r], wr);
+        }
+      }
+      dft<R, INV>(x);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];
+      } else {
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS) * stride] = x[r];
+      }
+    }
+  }
+
+  static __host__ __device__ __forceinline__ void gather(float2 (&v)[kPts], int t, const float2* lds, int stride) {
+#pragma unroll
+    for (int i = 0; i < kPts; ++i) v[i] = lds[lds_pad(t + S::G * i) * stride];
+  }
+
+  static __host__ __device__ __forceinline__ void scatter(const float2 (&v)[kPts], int t, float2* lds, int stride) {
+#pragma unroll
+    for (int i = 0; i < kPts; ++i) lds[lds_pad(t + S::G * i) * stride] = v[i];
+  }
+};
+
+// Host: fill the twiddle table of a length 2^logn transform (tw_size entries).
+inline void build_twiddles(int logn, float2* out) {
+  const PassPlan p = make_pass_plan(logn);
+  for (int q = 1; q < p.npass; ++q) {
+    const int ns = p.ns[q], r = p.radix[q];
+    const double span = double(ns) * double(r);
+    for (int k = 0; k < ns; ++k)
+      for (int m = 0; m < r; ++m) {
+        // reduce r*k modulo span exactly in integers before the angle
+        const long long e = (long long)k * m % (long long)(ns * r);
+        const double ang = -2.0 * M_PI * double(e) / span;
+        out[p.tw_off[q] + k * r + m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+  }
+}
+
+}  // namespace ff

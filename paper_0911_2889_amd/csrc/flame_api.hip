@@ -1,0 +1,517 @@
+// C ABI of the flame stepper: plan construction, workspace layout, launches.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fft_engine.hpp"
+#include "flame.h"
+#include "flame_dev.hpp"
+#include "flame_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FLAME_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ilog2_exact(int n) {
+  if (n <= 0 || (n & (n - 1))) return -1;
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+struct Sizes {
+  int logn1, logn2;
+  int tcol, tiles;       // column tile width and tile count
+  int rpairs, rgroups;   // row pairs per workgroup and row workgroups
+  size_t wq_elems;       // elements of each of Wp, Wm, Q
+  int n_spec;            // diag spectral workgroups
+  size_t part_elems;     // doubles of the partial-sum buffer
+};
+
+int check_desc(const flame_desc* d, Sizes* s) {
+  if (!d) return fail(FLAME_ERR_INVALID_ARG, "null flame_desc");
+  const int l1 = ilog2_exact(d->n1), l2 = ilog2_exact(d->n2);
+  if (l1 < 0 || l2 < 0) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must be powers of two", d->n1, d->n2);
+  if (l1 < flame::kMinLog || l1 > flame::kMaxLog || l2 < flame::kMinLog || l2 > flame::kMaxLog)
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must lie in [16, 4096]", d->n1, d->n2);
+  if (!(std::isfinite(d->gamma) && d->gamma >= 0.0)) return fail(FLAME_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+  if (!(std::isfinite(d->theta_pi) && d->theta_pi > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "theta_pi must be > 0");
+  if (!(std::isfinite(d->t0) && d->t0 > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "t0 must be > 0");
+  if (!(std::isfinite(d->dt) && d->dt > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "dt must be > 0");
+  for (int a = 0; a < 2; ++a)
+    if (!(std::isfinite(d->axis_scale[a]) && d->axis_scale[a] >= 0.0))
+      return fail(FLAME_ERR_INVALID_ARG, "axis_scale must be finite and >= 0");
+  if ((d->axis_scale[0] == 0.0) != (d->axis_scale[1] == 0.0))
+    return fail(FLAME_ERR_INVALID_ARG, "axis_scale must be both zero (use theta_pi) or both positive");
+  if (s) {
+    s->logn1 = l1;
+    s->logn2 = l2;
+    const int m = d->n2 / 4;
+    s->tcol = flame::col_tile(l1);
+    s->tiles = (m + s->tcol - 1) / s->tcol;
+    s->rpairs = flame::row_pairs(l2);
+    s->rgroups = (d->n1 / 2 + s->rpairs - 1) / s->rpairs;
+    s->wq_elems = (size_t)s->tiles * s->tcol * d->n1;
+    const long long spec = (long long)m * (d->n1 / 2);
+    s->n_spec = (int)std::min<long long>(1024, (spec + flame::kDiagThreads - 1) / flame::kDiagThreads);
+    s->part_elems = (size_t)s->rgroups + 2 * (size_t)s->n_spec;
+  }
+  return FLAME_OK;
+}
+
+struct Layout {
+  std::vector<Sizes> sizes;
+  std::vector<size_t> off_wp, off_wm, off_q, off_part;
+  size_t off_tw[flame::kMaxLog + 1];
+  size_t off_dev;
+  size_t total;
+};
+
+int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
+  if (!descs || nfl <= 0) return fail(FLAME_ERR_INVALID_ARG, "need at least one flame descriptor");
+  L->sizes.resize(nfl);
+  size_t off = 0;
+  bool need_tw[flame::kMaxLog + 1] = {};
+  for (int f = 0; f < nfl; ++f) {
+    int rc = check_desc(&descs[f], &L->sizes[f]);
+    if (rc) return rc;
+    need_tw[L->sizes[f].logn1] = need_tw[L->sizes[f].logn2] = true;
+  }
+  for (int f = 0; f < nfl; ++f) {
+    const Sizes& s = L->sizes[f];
+    L->off_wp.push_back(off);
+    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_wm.push_back(off);
+    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_q.push_back(off);
+    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_part.push_back(off);
+    off = align_up(off + s.part_elems * sizeof(double));
+  }
+  for (int l = 0; l <= flame::kMaxLog; ++l) {
+    L->off_tw[l] = off;
+    if (need_tw[l]) {
+      const ff::PassPlan pp = ff::make_pass_plan(l);
+      off = align_up(off + (size_t)(pp.tw_size > 0 ? pp.tw_size : 1) * sizeof(float2));
+    }
+  }
+  L->off_dev = off;
+  off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
+  L->total = off;
+  return FLAME_OK;
+}
+
+struct Group {
+  int logn1, logn2, first, count, tiles, rgroups;
+};
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev) {
+      if (hipSetDevice(dev) == hipSuccess) switched_ = true;
+    }
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1;
+  bool switched_ = false;
+};
+
+}  // namespace
+
+struct flame_plan_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int nfl = 0;
+  std::vector<flame_desc> descs;
+  Layout layout;
+  std::vector<flame::FlameDev> hdev;
+  std::vector<std::vector<float2>> tw_host;
+  flame::FlameDev* ddev = nullptr;
+  std::vector<Group> groups;
+  std::vector<char> w_valid;
+  long long n = 0;
+  // per-kernel timing (flame_timing_begin / flame_timing_end)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<hipEvent_t> ev_used[3];
+  ~flame_plan_s() {
+    for (auto& v : ev_used)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int check_plan(flame_plan p, int flame = 0) {
+  if (!p) return fail(FLAME_ERR_INVALID_ARG, "null plan");
+  if (flame < 0 || flame >= p->nfl) return fail(FLAME_ERR_INVALID_ARG, "flame index %d out of range [0, %d)", flame, p->nfl);
+  return FLAME_OK;
+}
+
+int last_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return FLAME_OK;
+}
+
+enum TimedKind { KIND_ROW = 0, KIND_COL = 1, KIND_OTHER = 2 };
+
+hipEvent_t take_event(flame_plan p) {
+  if (!p->ev_pool.empty()) {
+    hipEvent_t e = p->ev_pool.back();
+    p->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events on the plan's stream when timing is on.
+class Timed {
+ public:
+  Timed(flame_plan p, int kind) : p_(p), kind_(kind) {
+    if (p_->timing) {
+      start_ = take_event(p_);
+      if (start_) (void)hipEventRecord(start_, p_->stream);
+    }
+  }
+  ~Timed() {
+    if (p_->timing && start_) {
+      hipEvent_t stop = take_event(p_);
+      if (stop) {
+        (void)hipEventRecord(stop, p_->stream);
+        p_->ev_used[kind_].push_back(start_);
+        p_->ev_used[kind_].push_back(stop);
+      } else {
+        p_->ev_pool.push_back(start_);
+      }
+    }
+  }
+
+ private:
+  flame_plan p_;
+  int kind_;
+  hipEvent_t start_ = nullptr;
+};
+
+int rebuild_w(flame_plan p, int flame) {
+  const Sizes& s = p->layout.sizes[flame];
+  {
+    Timed tm(p, KIND_COL);
+    flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+  }
+  p->w_valid[flame] = 1;
+  return last_launch("column transform launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* flame_last_error(void) { return g_last_error.c_str(); }
+
+int flame_state_bytes(const flame_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  int rc = check_desc(desc, nullptr);
+  if (rc) return rc;
+  *bytes = (size_t)(desc->n2 / 4) * (size_t)(desc->n1 / 2) * sizeof(float2);
+  return FLAME_OK;
+}
+
+int flame_workspace_bytes(const flame_desc* descs, int32_t n_flames, size_t* bytes) {
+  if (!bytes) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  Layout L;
+  int rc = plan_layout(descs, n_flames, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return FLAME_OK;
+}
+
+int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, void* ws, size_t ws_bytes,
+               void* hip_stream, flame_plan* out) {
+  if (!out) return fail(FLAME_ERR_INVALID_ARG, "null plan output pointer");
+  *out = nullptr;
+  if (!states) return fail(FLAME_ERR_INVALID_ARG, "null state array");
+  if (!ws) return fail(FLAME_ERR_INVALID_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(FLAME_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  flame_plan p = new (std::nothrow) flame_plan_s();
+  if (!p) return fail(FLAME_ERR_INVALID_ARG, "out of host memory");
+  int rc = plan_layout(descs, n_flames, &p->layout);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  if (ws_bytes < p->layout.total) {
+    const size_t need = p->layout.total;
+    delete p;
+    return fail(FLAME_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, need %zu", ws_bytes, need);
+  }
+  for (int f = 0; f < n_flames; ++f) {
+    if (!states[f]) {
+      delete p;
+      return fail(FLAME_ERR_INVALID_ARG, "null state pointer for flame %d", f);
+    }
+    if (reinterpret_cast<uintptr_t>(states[f]) % 16) {
+      delete p;
+      return fail(FLAME_ERR_INVALID_ARG, "state of flame %d must be 16-byte aligned", f);
+    }
+  }
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->nfl = n_flames;
+  p->descs.assign(descs, descs + n_flames);
+  p->w_valid.assign(n_flames, 0);
+  char* base = static_cast<char*>(ws);
+  const Layout& L = p->layout;
+  // twiddle tables, built in double precision and rounded once
+  p->tw_host.resize(flame::kMaxLog + 1);
+  for (int l = flame::kMinLog; l <= flame::kMaxLog; ++l) {
+    bool used = false;
+    for (const Sizes& s : L.sizes) used |= (s.logn1 == l || s.logn2 == l);
+    if (!used) continue;
+    const ff::PassPlan pp = ff::make_pass_plan(l);
+    p->tw_host[l].assign(pp.tw_size > 0 ? pp.tw_size : 1, make_float2(1.f, 0.f));
+    ff::build_twiddles(l, p->tw_host[l].data());
+    e = hipMemcpyAsync(base + L.off_tw[l], p->tw_host[l].data(), p->tw_host[l].size() * sizeof(float2),
+                       hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "twiddle upload");
+    }
+  }
+  // device flame table, ordered so that flames of one grid size are contiguous
+  p->hdev.resize(n_flames);
+  for (int f = 0; f < n_flames; ++f) {
+    const flame_desc& d = descs[f];
+    const Sizes& s = L.sizes[f];
+    flame::FlameDev& fd = p->hdev[f];
+    std::memset(&fd, 0, sizeof fd);
+    fd.S = static_cast<float2*>(states[f]);
+    fd.Wp = reinterpret_cast<float2*>(base + L.off_wp[f]);
+    fd.Wm = reinterpret_cast<float2*>(base + L.off_wm[f]);
+    fd.Q = reinterpret_cast<float2*>(base + L.off_q[f]);
+    fd.part = reinterpret_cast<double*>(base + L.off_part[f]);
+    fd.tw1 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn1]);
+    fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
+    fd.n1 = d.n1;
+    fd.n2 = d.n2;
+    fd.m = d.n2 / 4;
+    fd.h1 = d.n1 / 2;
+    fd.tshift = ilog2_exact(s.tcol);
+    const bool lit = d.axis_scale[0] == 0.0;
+    fd.s1 = (float)(lit ? d.theta_pi : d.axis_scale[0]);
+    fd.s2 = (float)(lit ? d.theta_pi : d.axis_scale[1]);
+    fd.gamma = (float)d.gamma;
+    fd.t0 = d.t0;
+    fd.dt = d.dt;
+  }
+  // groups of consecutive flames with equal grids (one launch per group)
+  for (int f = 0; f < n_flames; ++f) {
+    const Sizes& s = L.sizes[f];
+    if (!p->groups.empty() && p->groups.back().logn1 == s.logn1 && p->groups.back().logn2 == s.logn2) {
+      p->groups.back().count++;
+    } else {
+      p->groups.push_back(Group{s.logn1, s.logn2, f, 1, s.tiles, s.rgroups});
+    }
+  }
+  p->ddev = reinterpret_cast<flame::FlameDev*>(base + L.off_dev);
+  e = hipMemcpyAsync(p->ddev, p->hdev.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "flame table upload");
+  }
+  // the host copies must outlive the asynchronous uploads
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "init synchronise");
+  }
+  *out = p;
+  return FLAME_OK;
+}
+
+int flame_set_spectrum(flame_plan p, int32_t flame, const void* half, int64_t n) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!half) return fail(FLAME_ERR_INVALID_ARG, "null spectrum pointer");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  const int total = (p->descs[flame].n2 / 4) * (p->descs[flame].n1 / 2);
+  (void)s;
+  flame::launch_set_spectrum(p->stream, p->ddev, flame, total, half);
+  p->n = n;
+  p->w_valid[flame] = 0;
+  return last_launch("set_spectrum launch");
+}
+
+int flame_get_spectrum(flame_plan p, int32_t flame, void* half) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!half) return fail(FLAME_ERR_INVALID_ARG, "null spectrum pointer");
+  DeviceGuard g(p->device);
+  const int total = (p->descs[flame].n1 / 2 - 1) * (p->descs[flame].n2 / 4);
+  flame::launch_get_spectrum(p->stream, p->ddev, flame, total, half);
+  return last_launch("get_spectrum launch");
+}
+
+int flame_set_state(flame_plan p, int32_t flame, const float* phi, int64_t n) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!phi) return fail(FLAME_ERR_INVALID_ARG, "null field pointer");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  p->n = n;
+  flame::launch_row(s.logn2, flame::ROW_FORWARD, s.rgroups, 1, p->stream, p->ddev + flame, p->n, phi, nullptr);
+  flame::launch_col(s.logn1, flame::COL_PROJECT, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+  p->w_valid[flame] = 1;
+  return last_launch("set_state launch");
+}
+
+int flame_get_state(flame_plan p, int32_t flame, float* phi) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!phi) return fail(FLAME_ERR_INVALID_ARG, "null field pointer");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  flame::launch_col(s.logn1, flame::COL_SYNTH, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+  flame::launch_row(s.logn2, flame::ROW_SYNTH, s.rgroups, 1, p->stream, p->ddev + flame, p->n, nullptr, phi);
+  return last_launch("get_state launch");
+}
+
+int flame_state_modified(flame_plan p, int64_t n) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  p->n = n;
+  for (auto& v : p->w_valid) v = 0;
+  return FLAME_OK;
+}
+
+int flame_step_index(flame_plan p, int64_t* n) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!n) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  *n = p->n;
+  return FLAME_OK;
+}
+
+int flame_step(flame_plan p, int32_t nsteps) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(FLAME_ERR_INVALID_ARG, "nsteps must be >= 0");
+  DeviceGuard g(p->device);
+  for (int f = 0; f < p->nfl; ++f)
+    if (!p->w_valid[f]) {
+      rc = rebuild_w(p, f);
+      if (rc) return rc;
+    }
+  for (int s = 0; s < nsteps; ++s) {
+    for (const Group& gr : p->groups) {
+      Timed tm(p, KIND_ROW);
+      flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
+                        nullptr);
+    }
+    for (const Group& gr : p->groups) {
+      Timed tm(p, KIND_COL);
+      flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, p->n);
+    }
+    p->n += 1;
+  }
+  return last_launch("step launch");
+}
+
+int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  if (!p->w_valid[flame]) {
+    rc = rebuild_w(p, flame);
+    if (rc) return rc;
+  }
+  {
+    Timed tm(p, KIND_OTHER);
+    flame::launch_row(s.logn2, flame::ROW_DIAG, s.rgroups, 1, p->stream, p->ddev + flame, p->n, nullptr, nullptr);
+    double* part = p->hdev[flame].part;
+    flame::launch_diag_spectral(p->stream, p->ddev, flame, s.n_spec, part + s.rgroups);
+    flame::launch_diag_final(p->stream, p->ddev, flame, p->n, s.rgroups, s.n_spec, out4);
+  }
+  return last_launch("diagnostics launch");
+}
+
+int flame_timing_begin(flame_plan p) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  for (auto& v : p->ev_used) {
+    p->ev_pool.insert(p->ev_pool.end(), v.begin(), v.end());
+    v.clear();
+  }
+  p->timing = true;
+  return FLAME_OK;
+}
+
+int flame_timing_end(flame_plan p, double* ms3, int64_t* counts3) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!ms3 || !counts3) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  DeviceGuard g(p->device);
+  p->timing = false;
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "timing synchronise");
+  for (int k = 0; k < 3; ++k) {
+    double total = 0.0;
+    const auto& v = p->ev_used[k];
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, v[i], v[i + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      total += ms;
+    }
+    ms3[k] = total;
+    counts3[k] = (int64_t)(v.size() / 2);
+  }
+  return FLAME_OK;
+}
+
+int flame_destroy(flame_plan p) {
+  if (!p) return fail(FLAME_ERR_INVALID_ARG, "null plan");
+  delete p;
+  return FLAME_OK;
+}
+
+}  // extern "C"

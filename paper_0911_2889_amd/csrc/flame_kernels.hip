@@ -1,0 +1,512 @@
+// HIP kernels of the spectral flame step (gfx950).
+//
+// One step of Eq. (1) is two kernels:
+//  * row_kernel<ROW_STEP>: for each pair of grid rows j1, load the column-
+//    transformed gradient spectrum Z(j1, k2) (k2 in [-K2, K2]), inverse
+//    transform along phi to z = g1 + i g2 (the two gradient components packed
+//    into one complex field), form q = |z|^2 = |grad Phi|^2, and transform the
+//    two real rows back with one complex forward transform, keeping
+//    k2 in [0, K2] -> Q. (Section 3: row transform, pointwise product, row
+//    inverse transform.)
+//  * col_kernel<COL_STEP>: for each stored column k2 = m, forward transform Q
+//    along theta, keep |k1| <= K1, apply the integrating-factor Euler update
+//    with the exact linear propagator, symmetrise the k2 = 0 column (Section 3),
+//    store the state, then immediately form the next step's column transforms
+//    of (i kappa1 -+ kappa2) Phi~ -> Wp, Wm. (Section 3: column transforms of
+//    k1 Psi and k2 Psi; the inverse column transform of the product.)
+// The global transposes of Section 3 are the tiled layout of Wp/Wm/Q in HBM:
+// the column kernel writes whole tiles, the row kernel reads row segments.
+
+#include <hip/hip_runtime.h>
+
+#include "fft_engine.hpp"
+#include "flame_dev.hpp"
+#include "flame_kernels.hpp"
+
+namespace flame {
+
+namespace {
+
+template <int LOGN, bool INV, int P = 0>
+__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride,
+                                           const float2* __restrict__ tw) {
+  using S = ff::Shape<LOGN>;
+  if constexpr (P < S::NPASS) {
+    ff::Fft<LOGN, INV>::template butterflies<P>(v, t, lds, stride, tw);
+    if constexpr (P + 1 < S::NPASS) {
+      __syncthreads();
+      ff::Fft<LOGN, INV>::gather(v, t, lds, stride);
+      __syncthreads();
+    }
+    fft_passes<LOGN, INV, P + 1>(v, t, lds, stride, tw);
+  }
+}
+
+// Transform the 16 registers of every group of the workgroup (all threads
+// must call it: it contains workgroup barriers). On entry v[i] holds the
+// input at position t + G*i, on exit the output at the same position.
+template <int LOGN, bool INV>
+__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride,
+                                    const float2* __restrict__ tw) {
+  fft_passes<LOGN, INV, 0>(v, t, lds, stride, tw);
+}
+
+struct StepScalars {
+  float a;    // dt * c_n / P, multiplies the raw transform of |grad Phi|^2
+  float i1;   // int_{t_n}^{t_{n+1}} dt / r0
+  float i2;   // int_{t_n}^{t_{n+1}} dt / r0^2
+  float r0;
+};
+
+// r0(t) = t (Section 2). Computed in double, rounded once.
+__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n) {
+  const double t = f.t0 + (double)n * f.dt;
+  const double t1 = t + f.dt;
+  const double c = 0.5 / (t * t);
+  StepScalars s;
+  s.a = (float)(f.dt * c / ((double)f.n1 * (double)f.n2));
+  s.i1 = (float)log1p(f.dt / t);
+  s.i2 = (float)(f.dt / (t * t1));
+  s.r0 = (float)t;
+  return s;
+}
+
+__device__ __forceinline__ size_t tiled(int j1, int m, int n1, int tshift) {
+  return ((size_t)(m >> tshift) * (size_t)n1 + (size_t)j1) * ((size_t)1 << tshift) + (size_t)(m & ((1 << tshift) - 1));
+}
+
+// Register slot kk (0..7) of the kept spectral positions: registers 0..3 hold
+// k1 = t + G*i >= 0, registers 12..15 hold k1 = t + G*i - N1 < 0.
+__device__ __forceinline__ constexpr int kept_reg(int kk) { return kk < 4 ? kk : kk + 8; }
+
+}  // namespace
+
+template <int LOGN1, int MODE>
+__global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
+    col_kernel(const FlameDev* __restrict__ fls, long long n) {
+  using S = ff::Shape<LOGN1>;
+  constexpr int G = S::G, T = ColCfg<LOGN1>::T, N1 = S::N;
+  extern __shared__ float2 lds[];
+  const FlameDev f = fls[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int c = tid % T, t = tid / T;
+  const int m = blockIdx.x * T + c;
+  const bool live = m < f.m;
+  float2* my = lds + c;
+  const size_t tile_base = (size_t)blockIdx.x * N1 * T;
+  const int h1 = f.h1;
+
+  float2 v[ff::kPts];
+  float2 st[8];
+
+  if constexpr (MODE == COL_STEP || MODE == COL_PROJECT) {
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i)
+      v[i] = live ? f.Q[tile_base + (size_t)(t + G * i) * T + c] : make_float2(0.f, 0.f);
+    fft<LOGN1, false>(v, t, my, T, f.tw1);
+    StepScalars sc{};
+    if constexpr (MODE == COL_STEP) sc = step_scalars(f, n);
+    const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
+    const float kap2c = f.s2 * (float)m;
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int i = kept_reg(kk);
+      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+      const int s = k1 + N1 / 4;
+      float2 val;
+      if constexpr (MODE == COL_STEP) {
+        const float2 old = live ? f.S[(size_t)m * h1 + s] : make_float2(0.f, 0.f);
+        const float kap1 = f.s1 * (float)k1;
+        const float kk2 = kap1 * kap1 + kap2c * kap2c;
+        const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
+        val = make_float2(e * (old.x + sc.a * v[i].x), e * (old.y + sc.a * v[i].y));
+      } else {
+        val = ff::cscale(v[i], inv_p);
+      }
+      if (s == 0) val = make_float2(0.f, 0.f);
+      st[kk] = val;
+    }
+    if (blockIdx.x == 0) {
+      // symmetrise column k2 = 0 (group c == 0): copy k1 > 0 conjugated onto -k1
+      if (c == 0) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int k1 = t + G * kk;
+          lds[k1] = st[kk];
+        }
+      }
+      __syncthreads();
+      if (c == 0) {
+#pragma unroll
+        for (int kk = 4; kk < 8; ++kk) {
+          const int k1 = t + G * kept_reg(kk) - N1;
+          if (k1 > -N1 / 4) st[kk] = ff::cconj(lds[-k1]);
+        }
+        if (t == 0) st[0].y = 0.f;
+      }
+      __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int i = kept_reg(kk);
+        const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+        f.S[(size_t)m * h1 + k1 + N1 / 4] = st[kk];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int i = kept_reg(kk);
+      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+      st[kk] = live ? f.S[(size_t)m * h1 + k1 + N1 / 4] : make_float2(0.f, 0.f);
+    }
+  }
+
+  if constexpr (MODE == COL_SYNTH) {
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) v[kept_reg(kk)] = st[kk];
+    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) f.Q[tile_base + (size_t)(t + G * i) * T + c] = v[i];
+    }
+  } else {
+    const float kap2 = f.s2 * (float)m;
+    // Z+ = IFFT_k1((i kappa1 - kappa2) Phi~), stored as is
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int i = kept_reg(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
+      v[i] = make_float2(-kap1 * st[kk].y - kap2 * st[kk].x, kap1 * st[kk].x - kap2 * st[kk].y);
+    }
+    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) f.Wp[tile_base + (size_t)(t + G * i) * T + c] = v[i];
+    }
+    // Z- column for k2 = -m: conj(IFFT_k1((i kappa1 + kappa2) Phi~))
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int i = kept_reg(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
+      v[i] = make_float2(-kap1 * st[kk].y + kap2 * st[kk].x, kap1 * st[kk].x + kap2 * st[kk].y);
+    }
+    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) f.Wm[tile_base + (size_t)(t + G * i) * T + c] = ff::cconj(v[i]);
+    }
+  }
+}
+
+template <int LOGN2, int MODE>
+__global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
+    row_kernel(const FlameDev* __restrict__ fls, long long n, const float* __restrict__ phys_in,
+               float* __restrict__ phys_out) {
+  using S = ff::Shape<LOGN2>;
+  constexpr int G = S::G, B = RowCfg<LOGN2>::B, N2 = S::N;
+  extern __shared__ float2 lds[];
+  const FlameDev f = fls[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int p = tid % B, t = tid / B;
+  const int pair = blockIdx.x * B + p;
+  const bool live = pair < f.n1 / 2;
+  const int ja = 2 * pair, jb = 2 * pair + 1;
+  const int n1 = f.n1, ts = f.tshift, mcols = f.m;
+  float2* my = lds + p;
+
+  float2 y[ff::kPts];
+
+  if constexpr (MODE == ROW_STEP || MODE == ROW_DIAG) {
+    float qa[ff::kPts];
+    double area = 0.0;
+    const float inv_r2 = [&] {
+      const double t0 = f.t0 + (double)n * f.dt;
+      return (float)(1.0 / (t0 * t0));
+    }();
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const int row = half ? jb : ja;
+      float2 v[ff::kPts];
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) {
+        const int idx = t + G * i;
+        float2 val = make_float2(0.f, 0.f);
+        if (live) {
+          if (i < 4) {
+            val = f.Wp[tiled(row, idx, n1, ts)];
+          } else if (i >= 12) {
+            const int mm = N2 - idx;
+            if (mm < mcols) val = f.Wm[tiled(row, mm, n1, ts)];
+          }
+        }
+        v[i] = val;
+      }
+      fft<LOGN2, true>(v, t, my, B, f.tw2);
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) {
+        const float q = v[i].x * v[i].x + v[i].y * v[i].y;
+        if constexpr (MODE == ROW_DIAG) {
+          const double x = (double)q * (double)inv_r2;
+          area += x / (1.0 + sqrt(1.0 + x));
+        } else {
+          if (half == 0)
+            qa[i] = q;
+          else
+            y[i] = make_float2(qa[i], q);
+        }
+      }
+    }
+    if constexpr (MODE == ROW_DIAG) {
+      // deterministic workgroup reduction of the area sums
+      __syncthreads();
+      double* red = reinterpret_cast<double*>(lds);
+      red[tid] = live ? area : 0.0;
+      __syncthreads();
+      for (int w = RowCfg<LOGN2>::THREADS / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) f.part[blockIdx.x] = red[0];
+      return;
+    }
+  } else if constexpr (MODE == ROW_FORWARD) {
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) {
+      const int idx = t + G * i;
+      y[i] = live ? make_float2(phys_in[(size_t)ja * N2 + idx], phys_in[(size_t)jb * N2 + idx])
+                  : make_float2(0.f, 0.f);
+    }
+  } else {  // ROW_SYNTH: Y = X_a + i X_b with X(k2) = A(m) for k2 = m >= 0, conj(A(m)) for k2 = -m
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) {
+      const int idx = t + G * i;
+      float2 val = make_float2(0.f, 0.f);
+      if (live) {
+        if (i < 4) {
+          const float2 a = f.Q[tiled(ja, idx, n1, ts)], b = f.Q[tiled(jb, idx, n1, ts)];
+          val = make_float2(a.x - b.y, a.y + b.x);
+        } else if (i >= 12) {
+          const int mm = N2 - idx;
+          if (mm < mcols) {
+            const float2 a = f.Q[tiled(ja, mm, n1, ts)], b = f.Q[tiled(jb, mm, n1, ts)];
+            // conj(a) + i conj(b)
+            val = make_float2(a.x + b.y, -a.y + b.x);
+          }
+        }
+      }
+      y[i] = val;
+    }
+    fft<LOGN2, true>(y, t, my, B, f.tw2);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < ff::kPts; ++i) {
+        const int idx = t + G * i;
+        phys_out[(size_t)ja * N2 + idx] = y[i].x;
+        phys_out[(size_t)jb * N2 + idx] = y[i].y;
+      }
+    }
+    return;
+  }
+
+  // forward transform of the two packed real rows, then split:
+  // Q_a(k) = (Y(k) + conj(Y(-k)))/2, Q_b(k) = (Y(k) - conj(Y(-k)))/(2i), k in [0, K2]
+  fft<LOGN2, false>(y, t, my, B, f.tw2);
+  __syncthreads();
+  ff::Fft<LOGN2, false>::scatter(y, t, my, B);
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = t + G * i;
+      const float2 yk = my[ff::lds_pad(k) * B];
+      const float2 ym = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
+      const float2 qa = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
+      const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
+      f.Q[tiled(ja, k, n1, ts)] = qa;
+      f.Q[tiled(jb, k, n1, ts)] = qb;
+    }
+  }
+}
+
+// Canonical half spectrum -> state, with the k2 = 0 symmetrisation.
+__global__ void set_spectrum_kernel(const FlameDev* __restrict__ fls, int flame, const float2* __restrict__ half) {
+  const FlameDev f = fls[flame];
+  const int total = f.m * f.h1;
+  const int k1max = f.n1 / 4 - 1;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int m = e / f.h1, s = e % f.h1;
+    const int k1 = s - f.n1 / 4;
+    float2 val = make_float2(0.f, 0.f);
+    if (s > 0) {
+      if (m == 0 && k1 < 0) {
+        val = ff::cconj(half[(size_t)(-k1 + k1max) * f.m]);
+      } else {
+        val = half[(size_t)(k1 + k1max) * f.m + m];
+        if (m == 0 && k1 == 0) val.y = 0.f;
+      }
+    }
+    f.S[e] = val;
+  }
+}
+
+__global__ void get_spectrum_kernel(const FlameDev* __restrict__ fls, int flame, float2* __restrict__ half) {
+  const FlameDev f = fls[flame];
+  const int rows = f.n1 / 2 - 1;
+  const int total = rows * f.m;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int r = e / f.m, m = e % f.m;
+    half[e] = f.S[(size_t)m * f.h1 + r + 1];
+  }
+}
+
+// Spectral sums: per workgroup partial of sum_k w_k |kappa|^2 |Phi~_k|^2 (w = 1 on
+// k2 = 0, 2 elsewhere) and a count of non-finite entries.
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_spectral_kernel(const FlameDev* __restrict__ fls, int flame, double* __restrict__ part) {
+  const FlameDev f = fls[flame];
+  __shared__ double red[kDiagThreads];
+  __shared__ double bad[kDiagThreads];
+  const int total = f.m * f.h1;
+  double acc = 0.0, nb = 0.0;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    const int m = e / f.h1, s = e % f.h1;
+    const float2 v = f.S[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) {
+      nb += 1.0;
+      continue;
+    }
+    const double k1 = (double)f.s1 * (double)(s - f.n1 / 4), k2 = (double)f.s2 * (double)m;
+    const double w = m == 0 ? 1.0 : 2.0;
+    acc += w * (k1 * k1 + k2 * k2) * ((double)v.x * v.x + (double)v.y * v.y);
+  }
+  red[threadIdx.x] = acc;
+  bad[threadIdx.x] = nb;
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      bad[threadIdx.x] += bad[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0];
+    part[2 * blockIdx.x + 1] = bad[0];
+  }
+}
+
+__global__ void __launch_bounds__(kDiagThreads)
+    diag_final_kernel(const FlameDev* __restrict__ fls, int flame, long long n, int n_area, int n_spec,
+                      double* __restrict__ out) {
+  const FlameDev f = fls[flame];
+  __shared__ double ra[kDiagThreads], rs[kDiagThreads], rb[kDiagThreads];
+  double a = 0.0, s = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n_area; i += blockDim.x) a += f.part[i];
+  const double* sp = f.part + n_area;
+  for (int i = threadIdx.x; i < n_spec; i += blockDim.x) {
+    s += sp[2 * i];
+    b += sp[2 * i + 1];
+  }
+  ra[threadIdx.x] = a;
+  rs[threadIdx.x] = s;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kDiagThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ra[threadIdx.x] += ra[threadIdx.x + w];
+      rs[threadIdx.x] += rs[threadIdx.x + w];
+      rb[threadIdx.x] += rb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double t = f.t0 + (double)n * f.dt;
+    const float2 s00 = f.S[f.n1 / 4];
+    out[0] = t + (double)s00.x;
+    out[1] = rs[0] / (2.0 * t * t);
+    out[2] = ra[0] / ((double)f.n1 * (double)f.n2);
+    out[3] = (rb[0] == 0.0 && isfinite(out[2])) ? 1.0 : 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+namespace {
+
+template <int LOGN>
+struct ColTable {
+  static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n) {
+    constexpr int th = ColCfg<LOGN>::THREADS, lds = ColCfg<LOGN>::LDS_BYTES;
+    switch (mode) {
+      case COL_STEP: hipLaunchKernelGGL((col_kernel<LOGN, COL_STEP>), grid, dim3(th), lds, st, fl, n); break;
+      case COL_FIRST: hipLaunchKernelGGL((col_kernel<LOGN, COL_FIRST>), grid, dim3(th), lds, st, fl, n); break;
+      case COL_PROJECT: hipLaunchKernelGGL((col_kernel<LOGN, COL_PROJECT>), grid, dim3(th), lds, st, fl, n); break;
+      default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n); break;
+    }
+  }
+};
+
+template <int LOGN>
+struct RowTable {
+  static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n, const float* in,
+                     float* out) {
+    constexpr int th = RowCfg<LOGN>::THREADS, lds = RowCfg<LOGN>::LDS_BYTES;
+    switch (mode) {
+      case ROW_STEP: hipLaunchKernelGGL((row_kernel<LOGN, ROW_STEP>), grid, dim3(th), lds, st, fl, n, in, out); break;
+      case ROW_FORWARD: hipLaunchKernelGGL((row_kernel<LOGN, ROW_FORWARD>), grid, dim3(th), lds, st, fl, n, in, out); break;
+      case ROW_SYNTH: hipLaunchKernelGGL((row_kernel<LOGN, ROW_SYNTH>), grid, dim3(th), lds, st, fl, n, in, out); break;
+      default: hipLaunchKernelGGL((row_kernel<LOGN, ROW_DIAG>), grid, dim3(th), lds, st, fl, n, in, out); break;
+    }
+  }
+};
+
+template <template <int> class Tab, int L, class... A>
+void dispatch_log(int logn, A... args) {
+  if constexpr (L <= kMaxLog) {
+    if (logn == L)
+      Tab<L>::launch(args...);
+    else
+      dispatch_log<Tab, L + 1>(logn, args...);
+  }
+}
+
+}  // namespace
+
+void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n) {
+  dispatch_log<ColTable, kMinLog>(logn1, mode, dim3(tiles, nfl), st, fl, n);
+}
+
+void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
+                const float* in, float* out) {
+  dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
+}
+
+void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half) {
+  const int blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+  hipLaunchKernelGGL(set_spectrum_kernel, dim3(blocks), dim3(256), 0, st, fl, flame,
+                     static_cast<const float2*>(half));
+}
+
+void launch_get_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, void* half) {
+  const int blocks = (total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096;
+  hipLaunchKernelGGL(get_spectrum_kernel, dim3(blocks), dim3(256), 0, st, fl, flame, static_cast<float2*>(half));
+}
+
+void launch_diag_spectral(hipStream_t st, const FlameDev* fl, int flame, int blocks, double* part) {
+  hipLaunchKernelGGL(diag_spectral_kernel, dim3(blocks), dim3(kDiagThreads), 0, st, fl, flame, part);
+}
+
+void launch_diag_final(hipStream_t st, const FlameDev* fl, int flame, long long n, int n_area, int n_spec,
+                       double* out) {
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(kDiagThreads), 0, st, fl, flame, n, n_area, n_spec, out);
+}
+
+}  // namespace flame

@@ -1,0 +1,25 @@
+// Launchers of the flame kernels (defined in flame_kernels.hip).
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "flame_dev.hpp"
+
+namespace flame {
+
+// Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
+// (fl points at their consecutive FlameDev entries in device memory).
+void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n);
+
+// Row kernel over `groups` groups of B row pairs for `nfl` flames of one size.
+void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
+                const float* in, float* out);
+
+void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half);
+void launch_get_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, void* half);
+void launch_diag_spectral(hipStream_t st, const FlameDev* fl, int flame, int blocks, double* part);
+void launch_diag_final(hipStream_t st, const FlameDev* fl, int flame, long long n, int n_area, int n_spec,
+                       double* out);
+
+}  // namespace flame

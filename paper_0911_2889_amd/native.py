@@ -1,0 +1,112 @@
+"""ctypes binding of libflamefront.so (argument marshalling only).
+
+The library is built in-tree by ``paper_0911_2889_amd.build``. Importing this
+module without the built library raises: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libflamefront.so")
+
+FLAME_OK = 0
+FLAME_ERR_INVALID_ARG = -1
+FLAME_ERR_WORKSPACE_TOO_SMALL = -2
+FLAME_ERR_HIP = -3
+FLAME_ERR_UNSUPPORTED_SIZE = -4
+FLAME_ERR_NONFINITE = -5
+
+# every symbol the C header declares
+EXPORTS = (
+    "flame_state_bytes", "flame_workspace_bytes", "flame_init", "flame_set_spectrum",
+    "flame_get_spectrum", "flame_set_state", "flame_get_state", "flame_state_modified",
+    "flame_step_index", "flame_step", "flame_diagnostics", "flame_timing_begin", "flame_timing_end",
+    "flame_destroy", "flame_last_error",
+)
+
+
+class FlameDesc(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int32),
+        ("n2", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("theta_pi", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("axis_scale", ctypes.c_double * 2),
+    ]
+
+
+class FlameError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"flame error {code}: {message}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load the shared library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_0911_2889_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    desc_p = ctypes.POINTER(FlameDesc)
+    sig = {
+        "flame_state_bytes": [desc_p, ctypes.POINTER(sz)],
+        "flame_workspace_bytes": [desc_p, i32, ctypes.POINTER(sz)],
+        "flame_init": [desc_p, i32, ctypes.POINTER(P), P, sz, P, ctypes.POINTER(P)],
+        "flame_set_spectrum": [P, i32, P, i64],
+        "flame_get_spectrum": [P, i32, P],
+        "flame_set_state": [P, i32, P, i64],
+        "flame_get_state": [P, i32, P],
+        "flame_state_modified": [P, i64],
+        "flame_step_index": [P, ctypes.POINTER(i64)],
+        "flame_step": [P, i32],
+        "flame_diagnostics": [P, i32, P],
+        "flame_timing_begin": [P],
+        "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
+        "flame_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.flame_last_error.argtypes = []
+    lib.flame_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(rc):
+    if rc != FLAME_OK:
+        msg = load().flame_last_error().decode("utf-8", "replace")
+        raise FlameError(rc, msg)
+    return rc
+
+
+def make_desc(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25, axis_scale=None):
+    d = FlameDesc()
+    d.n1, d.n2 = int(n1), int(n2)
+    d.gamma, d.theta_pi, d.t0, d.dt = float(gamma), float(theta_pi), float(t0), float(dt)
+    sc = (0.0, 0.0) if axis_scale is None else (float(axis_scale[0]), float(axis_scale[1]))
+    d.axis_scale[0], d.axis_scale[1] = sc
+    return d
+
+
+def state_bytes(desc):
+    out = ctypes.c_size_t()
+    check(load().flame_state_bytes(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+def workspace_bytes(descs):
+    arr = (FlameDesc * len(descs))(*descs)
+    out = ctypes.c_size_t()
+    check(load().flame_workspace_bytes(arr, len(descs), ctypes.byref(out)))
+    return out.value

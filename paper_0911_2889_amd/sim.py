@@ -1,0 +1,146 @@
+"""Python surface of the flame stepper: device memory and streams from torch,
+every step of the computation in the HIP library (libflamefront.so)."""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native
+
+
+def _dev_tensor(x, dtype, device):
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x))
+    return x.to(device=device, dtype=dtype).contiguous()
+
+
+class FlameEnsemble:
+    """A plan over one or more flames (possibly of different grids).
+
+    descs: list of dicts with keys n1, n2 and optionally gamma, theta_pi, t0,
+    dt, axis_scale. The plan is bound to the current torch stream of `device`.
+    """
+
+    def __init__(self, descs, device="cuda", ws_fill=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the flame stepper needs a ROCm GPU (torch.cuda is unavailable)")
+        self.lib = native.load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.params = [dict(d) for d in descs]
+        self.descs = [native.make_desc(**d) for d in self.params]
+        self.states = []
+        with torch.cuda.device(self.device):
+            for d in self.descs:
+                nb = native.state_bytes(d)
+                self.states.append(torch.zeros(nb // 8, dtype=torch.complex64, device=self.device))
+            ws_bytes = native.workspace_bytes(self.descs)
+            self.ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            if ws_fill is not None:
+                self.ws.fill_(int(ws_fill))
+            off = (-self.ws.data_ptr()) % 256
+            self.ws_ptr = self.ws.data_ptr() + off
+            self.stream = torch.cuda.current_stream(self.device)
+            arr = (native.FlameDesc * len(self.descs))(*self.descs)
+            ptrs = (ctypes.c_void_p * len(self.states))(*[s.data_ptr() for s in self.states])
+            plan = ctypes.c_void_p()
+            native.check(self.lib.flame_init(arr, len(self.descs), ptrs, ctypes.c_void_p(self.ws_ptr),
+                                             ws_bytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(plan)))
+        self.plan = plan
+
+    # ------------------------------------------------------------ helpers
+    def _check_flame(self, f):
+        if not 0 <= f < len(self.descs):
+            raise IndexError(f"flame index {f} out of range")
+
+    def half_shape(self, f=0):
+        d = self.descs[f]
+        return (d.n1 // 2 - 1, d.n2 // 4)
+
+    # ------------------------------------------------------------ state I/O
+    def set_spectrum(self, half, n=0, flame=0):
+        """Load the canonical half spectrum (complex64, shape (2K1+1, K2+1))."""
+        self._check_flame(flame)
+        h = _dev_tensor(half, torch.complex64, self.device)
+        if tuple(h.shape) != self.half_shape(flame):
+            raise ValueError(f"half spectrum has shape {tuple(h.shape)}, expected {self.half_shape(flame)}")
+        native.check(self.lib.flame_set_spectrum(self.plan, flame, ctypes.c_void_p(h.data_ptr()), int(n)))
+        self._keep = h
+
+    def spectrum(self, flame=0):
+        self._check_flame(flame)
+        out = torch.empty(self.half_shape(flame), dtype=torch.complex64, device=self.device)
+        native.check(self.lib.flame_get_spectrum(self.plan, flame, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def set_phi(self, phi, n=0, flame=0):
+        """Project a physical field (float32, n1 x n2) onto the retained box."""
+        self._check_flame(flame)
+        d = self.descs[flame]
+        x = _dev_tensor(phi, torch.float32, self.device)
+        if tuple(x.shape) != (d.n1, d.n2):
+            raise ValueError(f"field has shape {tuple(x.shape)}, expected {(d.n1, d.n2)}")
+        native.check(self.lib.flame_set_state(self.plan, flame, ctypes.c_void_p(x.data_ptr()), int(n)))
+        self._keep = x
+
+    def phi(self, flame=0):
+        self._check_flame(flame)
+        d = self.descs[flame]
+        out = torch.empty((d.n1, d.n2), dtype=torch.float32, device=self.device)
+        native.check(self.lib.flame_get_state(self.plan, flame, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def state_modified(self, n):
+        native.check(self.lib.flame_state_modified(self.plan, int(n)))
+
+    @property
+    def step_index(self):
+        v = ctypes.c_int64()
+        native.check(self.lib.flame_step_index(self.plan, ctypes.byref(v)))
+        return v.value
+
+    # ------------------------------------------------------------ stepping
+    def step(self, nsteps=1):
+        native.check(self.lib.flame_step(self.plan, int(nsteps)))
+
+    def diagnostics(self, flame=0, out=None):
+        """Mean radius, averaged velocity, area excess and finite flag (doubles)."""
+        self._check_flame(flame)
+        buf = out if out is not None else torch.empty(4, dtype=torch.float64, device=self.device)
+        native.check(self.lib.flame_diagnostics(self.plan, flame, ctypes.c_void_p(buf.data_ptr())))
+        if out is not None:
+            return out
+        v = buf.cpu().tolist()
+        return {"mean_radius": v[0], "velocity": v[1], "area_excess": v[2], "finite": bool(v[3] == 1.0)}
+
+    def timing_begin(self):
+        native.check(self.lib.flame_timing_begin(self.plan))
+
+    def timing_end(self):
+        """Summed kernel milliseconds and launch counts: row, column, diagnostics."""
+        ms = (ctypes.c_double * 3)()
+        cnt = (ctypes.c_int64 * 3)()
+        native.check(self.lib.flame_timing_end(self.plan, ms, cnt))
+        keys = ("row", "col", "diag")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(keys)}
+
+    def close(self):
+        if getattr(self, "plan", None):
+            native.check(self.lib.flame_destroy(self.plan))
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FlameSim(FlameEnsemble):
+    """One flame: FlameSim(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25)."""
+
+    def __init__(self, n1, n2, device="cuda", ws_fill=None, **kw):
+        super().__init__([dict(n1=n1, n2=n2, **kw)], device=device, ws_fill=ws_fill)

@@ -1,0 +1,207 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from flame_testlib import oracle_params, oracle_trajectory, rel_l2, weighted_sq
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def flame():
+    from paper_0911_2889_amd import FlameEnsemble, FlameSim  # noqa: F401
+    import paper_0911_2889_amd
+    return paper_0911_2889_amd
+
+
+def make_sim(mod, w, **kw):
+    return mod.FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt, **kw)
+
+
+def small_workload(n1, n2, seed, amp=1e-2, max_norm=None, dt=0.25, t0=200.0):
+    return synth.Workload(f"t{n1}x{n2}", n1, n2, 1, dt, "disc" if max_norm else "all", amp, -1.0, seed,
+                          max_norm=max_norm, t0=t0)
+
+
+def test_spectrum_roundtrip_is_exact(flame):
+    w = small_workload(64, 128, 1)
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    back = sim.spectrum().cpu().numpy()
+    assert np.array_equal(back, half)
+
+
+@pytest.mark.parametrize("n1,n2", [(16, 16), (32, 64), (128, 64), (256, 512), (2048, 128), (64, 4096)])
+def test_projection_and_synthesis(flame, n1, n2):
+    phi = synth.physical_noise(n1, n2, seed=n1 + n2, kind="uniform", scale=1e-3)
+    w = small_workload(n1, n2, 0)
+    sim = make_sim(flame, w)
+    sim.set_phi(phi)
+    got = sim.spectrum().cpu().numpy()
+    ref = oracle.full_to_half(oracle.symmetrise(oracle.project(phi.astype(np.float64))), n1, n2)
+    assert rel_l2(got, ref) < 1e-6
+    # synthesis of the projected state against the oracle's synthesis of the same coefficients
+    field = sim.phi().cpu().numpy()
+    ref_field = oracle.synthesize(oracle.half_to_full(got.astype(np.complex128), n1, n2)).real
+    assert np.linalg.norm(field - ref_field) / np.linalg.norm(ref_field) < 1e-6
+
+
+@pytest.mark.parametrize("n1,n2,amp", [(16, 32, 1.0), (64, 128, 0.3), (128, 64, 0.3), (256, 512, 0.05),
+                                       (512, 128, 0.1), (32, 4096, 0.02), (4096, 32, 0.02)])
+def test_single_step_matches_oracle(flame, n1, n2, amp):
+    # large amplitude and small t0 so the quadratic term is a sizeable part of the step
+    w = small_workload(n1, n2, seed=n1 * 7 + n2, amp=amp, t0=5.0, dt=0.2)
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    sim.step(1)
+    got = sim.spectrum().cpu().numpy()
+    p = oracle_params(w)
+    ref = oracle_trajectory(half, p, [1])[1]
+    # the update must differ visibly from the initial state, and match the oracle
+    assert rel_l2(ref, half) > 1e-3
+    assert rel_l2(got, ref) < 1e-6
+
+
+def test_axis_scales_and_theta(flame):
+    n1, n2 = 64, 64
+    w = small_workload(n1, n2, seed=5, amp=0.2, t0=5.0, dt=0.1)
+    half = synth.workload_spectrum(w)
+    sim = flame.FlameSim(n1, n2, gamma=0.6, theta_pi=2.0, t0=5.0, dt=0.1, axis_scale=(1.5, 0.5))
+    sim.set_spectrum(half)
+    sim.step(5)
+    got = sim.spectrum().cpu().numpy()
+    p = oracle.Params(n1, n2, gamma=0.6, theta_pi=2.0, t0=5.0, dt=0.1, axis_scale=(1.5, 0.5))
+    ref = oracle_trajectory(half, p, [5])[5]
+    assert rel_l2(got, ref) < 2e-6
+
+
+def test_flame64x128_full_horizon(flame):
+    w = synth.WORKLOADS["flame64x128"]
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    p = oracle_params(w)
+    ref = oracle_trajectory(half, p, [50, 100, 150, 200])
+    for n in (50, 100, 150, 200):
+        sim.step(50)
+        got = sim.spectrum().cpu().numpy()
+        err = rel_l2(got, ref[n])
+        assert err < 1e-5, (n, err)
+
+
+def test_stress256x512_nonlinear(flame):
+    w = synth.WORKLOADS["stress256x512"]
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    p = oracle_params(w)
+    ref = oracle_trajectory(half, p, [100, 500])
+    sim.step(100)
+    assert rel_l2(sim.spectrum().cpu().numpy(), ref[100]) < 1e-5
+    sim.step(400)
+    got = sim.spectrum().cpu().numpy()
+    assert rel_l2(got, ref[500]) < 1e-5
+
+
+def test_repeat_runs_are_bitwise_identical(flame):
+    w = small_workload(256, 512, seed=9, amp=0.05)
+    half = synth.workload_spectrum(w)
+    outs = []
+    for _ in range(2):
+        sim = make_sim(flame, w)
+        sim.set_spectrum(half)
+        sim.step(20)
+        outs.append(sim.spectrum().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_workspace_poison_does_not_change_result(flame):
+    # a workspace filled with NaN bytes before the plan is built must give the same
+    # bits: no kernel may read an intermediate it has not written
+    w = small_workload(128, 256, seed=10, amp=0.05)
+    half = synth.workload_spectrum(w)
+    res = []
+    for fill in (None, 0xFF):
+        sim = make_sim(flame, w, ws_fill=fill)
+        sim.set_spectrum(half)
+        sim.step(10)
+        res.append(sim.spectrum().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
+def test_diagnostics_match_oracle(flame):
+    w = synth.WORKLOADS["stress256x512"]
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    p = oracle_params(w)
+    full0 = oracle.half_to_full(half.astype(np.complex128), w.n1, w.n2)
+    for n in (0, 40):
+        if n:
+            sim.step(n)
+            full0 = oracle.run(full0, p, n)
+        d = sim.diagnostics()
+        r, v, a = oracle.diagnostics(oracle.symmetrise(full0), p, n)
+        assert d["finite"]
+        assert abs(d["mean_radius"] - r) < 1e-9 * r
+        assert abs(d["velocity"] - v) < 2e-5 * abs(v)
+        assert abs(d["area_excess"] - a) < 2e-5 * abs(a)
+
+
+def test_nonfinite_state_is_flagged(flame):
+    w = small_workload(64, 64, seed=3)
+    half = synth.workload_spectrum(w)
+    half[3, 4] = np.nan
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    assert not sim.diagnostics()["finite"]
+
+
+def test_ensemble_members_match_solo_runs(flame):
+    specs = [(64, 128, 1), (64, 128, 2), (128, 64, 3), (256, 512, 4), (64, 128, 5)]
+    descs, halves = [], []
+    for n1, n2, seed in specs:
+        w = small_workload(n1, n2, seed, amp=0.05)
+        descs.append(dict(n1=n1, n2=n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25))
+        halves.append(synth.workload_spectrum(w))
+    ens = flame.FlameEnsemble(descs)
+    for f, h in enumerate(halves):
+        ens.set_spectrum(h, flame=f)
+    ens.step(10)
+    for f, (n1, n2, seed) in enumerate(specs):
+        solo = flame.FlameSim(n1, n2, t0=200.0, dt=0.25)
+        solo.set_spectrum(halves[f])
+        solo.step(10)
+        assert np.array_equal(ens.spectrum(f).cpu().numpy(), solo.spectrum().cpu().numpy())
+
+
+def test_checkpoint_restart_equivalence(flame):
+    w = small_workload(128, 256, seed=12, amp=0.05)
+    half = synth.workload_spectrum(w)
+    a = make_sim(flame, w)
+    a.set_spectrum(half)
+    a.step(30)
+    b = make_sim(flame, w)
+    b.set_spectrum(half)
+    b.step(12)
+    saved = b.states[0].clone()
+    b.step(5)  # wander off, then restore
+    b.states[0].copy_(saved)
+    b.state_modified(12)
+    b.step(18)
+    assert np.array_equal(a.spectrum().cpu().numpy(), b.spectrum().cpu().numpy())
+
+
+def test_zero_state_stays_zero(flame):
+    w = small_workload(64, 128, seed=1)
+    sim = make_sim(flame, w)
+    sim.set_spectrum(np.zeros(sim.half_shape(), dtype=np.complex64))
+    sim.step(5)
+    assert weighted_sq(sim.spectrum().cpu().numpy()) == 0.0

@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports what include/flame.h declares, and rejects
+bad descriptors (host-only calls; no GPU needed)."""
+
+import ctypes
+import os
+import re
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "flame.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(flame_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_0911_2889_amd import native as nat
+    nat.load()
+    return nat
+
+
+def test_library_exports_every_declared_symbol(native):
+    declared = header_functions()
+    assert len(declared) >= 10
+    lib = native.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(native.EXPORTS)
+
+
+def test_state_and_workspace_sizes(native):
+    d = native.make_desc(2048, 4096)
+    assert native.state_bytes(d) == 2048 * 4096
+    ws = native.workspace_bytes([d])
+    # three N1 x N2/4 complex intermediates dominate
+    assert 3 * 2048 * 1024 * 8 <= ws < 3 * 2048 * 1024 * 8 + (1 << 20)
+    assert native.workspace_bytes([d, native.make_desc(64, 128)]) > ws
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n1=100, n2=128), -4),
+    (dict(n1=8, n2=128), -4),
+    (dict(n1=64, n2=8192), -4),
+    (dict(n1=64, n2=128, dt=0.0), -1),
+    (dict(n1=64, n2=128, t0=-1.0), -1),
+    (dict(n1=64, n2=128, gamma=float("nan")), -1),
+    (dict(n1=64, n2=128, theta_pi=0.0), -1),
+    (dict(n1=64, n2=128, axis_scale=(1.0, 0.0)), -1),
+])
+def test_bad_descriptors_are_rejected(native, kw, code):
+    d = native.make_desc(**kw)
+    out = ctypes.c_size_t()
+    rc = native.load().flame_state_bytes(ctypes.byref(d), ctypes.byref(out))
+    assert rc == code
+    assert native.load().flame_last_error().decode()
+
+
+def test_null_and_empty_arguments(native):
+    lib = native.load()
+    out = ctypes.c_size_t()
+    assert lib.flame_workspace_bytes(None, 1, ctypes.byref(out)) == -1
+    d = (native.FlameDesc * 1)(native.make_desc(64, 128))
+    assert lib.flame_workspace_bytes(d, 0, ctypes.byref(out)) == -1
+    assert lib.flame_step(None, 1) == -1
+    assert lib.flame_destroy(None) == -1
+    plan = ctypes.c_void_p()
+    assert lib.flame_init(d, 1, None, None, 0, None, ctypes.byref(plan)) == -1
+
+
+def test_fft_engine_on_host_matches_numpy(tmp_path):
+    """Drive the device FFT engine's passes thread by thread on the CPU."""
+    exe = tmp_path / "fft_engine_check"
+    src = os.path.join(ROOT, "tests", "native", "fft_engine_check.cpp")
+    inc = os.path.join(ROOT, "paper_0911_2889_amd", "csrc")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-I", inc, src, "-o", str(exe)], check=True,
+                   capture_output=True)
+    for logn in range(4, 14):
+        for inv in (0, 1):
+            for stride in (1, 4):
+                n = 1 << logn
+                rng = np.random.default_rng(logn * 10 + inv)
+                x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+                out = subprocess.run([str(exe)], input=struct.pack("3i", logn, inv, stride) + x.tobytes(),
+                                     capture_output=True, check=True).stdout
+                y = np.frombuffer(out, dtype=np.complex64)
+                xd = x.astype(np.complex128)
+                ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
+                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logn, inv, stride)
