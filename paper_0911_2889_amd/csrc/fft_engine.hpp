@@ -15,7 +15,9 @@
 //
 // Twiddles come from a table built on the host in double precision and
 // rounded once to float: pass p >= 1 with Ns = 16^p and radix R stores
-// w(k, r) = exp(-2 pi i r k / (Ns R)) at [k * R + r], k < Ns, r < R.
+// w(k, r) = exp(-2 pi i r k / (Ns R)) at [(r - 1) * Ns + k], 0 < r < R,
+// k < Ns, so that the lanes of a wave (consecutive k) read consecutive
+// addresses for each r.
 //
 // The pass functions are __host__ __device__ so the same code can be
 // driven thread by thread on the CPU to check the index maps.
@@ -51,7 +53,7 @@ constexpr PassPlan make_pass_plan(int logn) {
     p.radix[q] = q < full ? 16 : (1 << rem);
     p.ns[q] = ns;
     p.tw_off[q] = off;
-    if (q > 0) off += ns * p.radix[q];
+    if (q > 0) off += ns * (p.radix[q] - 1);
     ns *= p.radix[q];
   }
   for (int q = p.npass; q < 4; ++q) {
@@ -205,6 +207,60 @@ __host__ __device__ __forceinline__ void dft(float2* x) {
 
 // ------------------------------------------------------------ Stockham passes
 
+// Twiddle source reading the table in global memory on every use.
+template <int LOGN>
+struct GlobalTw {
+  using S = Shape<LOGN>;
+  const float2* __restrict__ tw;
+  int t;
+  template <int P>
+  __host__ __device__ __forceinline__ float2 get(int b, int r) const {
+    constexpr int NS = S::ns(P);
+    const int k = (t + b * S::G) & (NS - 1);
+    return tw[S::tw_off(P) + (r - 1) * NS + k];
+  }
+};
+
+// Twiddle source holding, in registers, every twiddle thread t needs: loaded
+// once and reused by all transforms of one length in a kernel.
+template <int LOGN>
+struct RegTw {
+  using S = Shape<LOGN>;
+  static constexpr int per_pass(int p) { return kPts - kPts / S::radix(p); }
+  static constexpr int offset(int p) {
+    int o = 0;
+    for (int q = 1; q < p; ++q) o += per_pass(q);
+    return o;
+  }
+  static constexpr int COUNT = S::NPASS > 1 ? offset(S::NPASS) : 1;
+  float2 w[COUNT];
+
+  // fetch(i) returns entry i of the twiddle table
+  template <class F>
+  __host__ __device__ __forceinline__ void load(const F& fetch, int t) {
+    load_pass<1>(fetch, t);
+  }
+
+  template <int P, class F>
+  __host__ __device__ __forceinline__ void load_pass(const F& fetch, int t) {
+    if constexpr (P < S::NPASS) {
+      constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int k = (t + b * S::G) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[offset(P) + b * (R - 1) + (r - 1)] = fetch(S::tw_off(P) + (r - 1) * NS + k);
+      }
+      load_pass<P + 1>(fetch, t);
+    }
+  }
+
+  template <int P>
+  __host__ __device__ __forceinline__ float2 get(int b, int r) const {
+    return w[offset(P) + b * (S::radix(P) - 1) + (r - 1)];
+  }
+};
+
 template <int LOGN, bool INV>
 struct Fft {
   using S = Shape<LOGN>;
@@ -214,9 +270,9 @@ struct Fft {
   // applies the twiddles w(j mod Ns, r), the radix-R DFT, and sends output r
   // to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns: into LDS, or, in the
   // last pass (Ns * R = N), back into the same registers.
-  template <int P>
+  template <int P, class TW>
   static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[kPts], int t, float2* lds, int stride,
-                                                              const float2* __restrict__ tw) {
+                                                              const TW& tw) {
     constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
     constexpr bool LAST = (P + 1 == S::NPASS);
 #pragma unroll
@@ -227,10 +283,9 @@ struct Fft {
       const int j = t + b * S::G;
       const int k = j & (NS - 1);
       if constexpr (P > 0) {
-        const float2* w = tw + S::tw_off(P) + k * R;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 wr = w[r];
+          float2 wr = tw.template get<P>(b, r);
           if (INV) wr.y = -wr.y;
           x[r] = cmul(x[r], wr);
         }
@@ -264,12 +319,12 @@ inline void build_twiddles(int logn, float2* out) {
   for (int q = 1; q < p.npass; ++q) {
     const int ns = p.ns[q], r = p.radix[q];
     const double span = double(ns) * double(r);
-    for (int k = 0; k < ns; ++k)
-      for (int m = 0; m < r; ++m) {
-        // reduce r*k modulo span exactly in integers before the angle
+    for (int m = 1; m < r; ++m)
+      for (int k = 0; k < ns; ++k) {
+        // reduce m*k modulo span exactly in integers before the angle
         const long long e = (long long)k * m % (long long)(ns * r);
         const double ang = -2.0 * M_PI * double(e) / span;
-        out[p.tw_off[q] + k * r + m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        out[p.tw_off[q] + (m - 1) * ns + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
       }
   }
 }

@@ -57,6 +57,13 @@ constexpr int row_pairs(int logn2) { return (1 << logn2) / ff::kPts >= 256 ? 1 :
 enum ColMode : int { COL_STEP = 0, COL_FIRST = 1, COL_PROJECT = 2, COL_SYNTH = 3 };
 enum RowMode : int { ROW_STEP = 0, ROW_FORWARD = 1, ROW_SYNTH = 2, ROW_DIAG = 3 };
 
+// Keep each thread's twiddles in registers for a kernel's lifetime (the
+// alternative reads the table in every pass).
+#ifndef FLAME_CACHE_TWIDDLES
+#define FLAME_CACHE_TWIDDLES 1
+#endif
+constexpr bool kCacheTwiddles = FLAME_CACHE_TWIDDLES != 0;
+
 constexpr int kMinLog = 4;
 constexpr int kMaxLog = 12;
 constexpr int kDiagThreads = 256;

@@ -19,6 +19,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fft_engine.hpp"
 #include "flame_dev.hpp"
 #include "flame_kernels.hpp"
@@ -27,9 +29,8 @@ namespace flame {
 
 namespace {
 
-template <int LOGN, bool INV, int P = 0>
-__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride,
-                                           const float2* __restrict__ tw) {
+template <int LOGN, bool INV, int P = 0, class TW>
+__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
   using S = ff::Shape<LOGN>;
   if constexpr (P < S::NPASS) {
     ff::Fft<LOGN, INV>::template butterflies<P>(v, t, lds, stride, tw);
@@ -45,34 +46,80 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2*
 // Transform the 16 registers of every group of the workgroup (all threads
 // must call it: it contains workgroup barriers). On entry v[i] holds the
 // input at position t + G*i, on exit the output at the same position.
-template <int LOGN, bool INV>
-__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride,
-                                    const float2* __restrict__ tw) {
+template <int LOGN, bool INV, class TW>
+__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
   fft_passes<LOGN, INV, 0>(v, t, lds, stride, tw);
 }
+
+// Global-memory views: loads and stores through these pointers compile to
+// global_* instructions (flat ones would also wait on LDS counters).
+using v2f = float __attribute__((ext_vector_type(2)));
+using gf2 = __attribute__((address_space(1))) v2f;
+using gf1 = __attribute__((address_space(1))) float;
+__device__ __forceinline__ gf2* glob(float2* p) { return (gf2*)p; }
+__device__ __forceinline__ const gf1* glob(const float* p) { return (const gf1*)p; }
+__device__ __forceinline__ gf1* glob(float* p) { return (gf1*)p; }
+__device__ __forceinline__ float2 ld(const gf2* p) {
+  const v2f v = *p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st(gf2* p, float2 a) {
+  v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  *p = v;
+}
+
+// Twiddle source of a kernel: cached in registers for the kernel's lifetime
+// (each kernel runs two or three transforms of one length), or read from the
+// table in every pass.
+template <int LOGN>
+struct KernelTw {
+  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN>, ff::GlobalTw<LOGN>>::type;
+  static __device__ __forceinline__ Type make(const float2* __restrict__ tw, int t) {
+    Type out;
+    if constexpr (kCacheTwiddles) {
+      const gf2* g = (const gf2*)tw;
+      out.load([g](int i) { return ld(g + i); }, t);
+    } else {
+      out.tw = tw;
+      out.t = t;
+    }
+    return out;
+  }
+};
 
 struct StepScalars {
   float a;    // dt * c_n / P, multiplies the raw transform of |grad Phi|^2
   float i1;   // int_{t_n}^{t_{n+1}} dt / r0
   float i2;   // int_{t_n}^{t_{n+1}} dt / r0^2
-  float r0;
 };
 
-// r0(t) = t (Section 2). Computed in double, rounded once.
+// r0(t) = t (Section 2): c_n = 1/(2 t_n^2), I1 = ln(t_{n+1}/t_n),
+// I2 = 1/t_n - 1/t_{n+1}. The time is formed in double; the scalars need only
+// float accuracy.
 __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n) {
-  const double t = f.t0 + (double)n * f.dt;
-  const double t1 = t + f.dt;
-  const double c = 0.5 / (t * t);
+  const float t = (float)(f.t0 + (double)n * f.dt);
+  const float dt = (float)f.dt;
+  const float x = dt / t;
   StepScalars s;
-  s.a = (float)(f.dt * c / ((double)f.n1 * (double)f.n2));
-  s.i1 = (float)log1p(f.dt / t);
-  s.i2 = (float)(f.dt / (t * t1));
-  s.r0 = (float)t;
+  s.a = 0.5f * x / (t * (float)f.n1 * (float)f.n2);
+  s.i1 = log1pf(x);
+  s.i2 = x / (t + dt);
   return s;
 }
 
-__device__ __forceinline__ size_t tiled(int j1, int m, int n1, int tshift) {
-  return ((size_t)(m >> tshift) * (size_t)n1 + (size_t)j1) * ((size_t)1 << tshift) + (size_t)(m & ((1 << tshift) - 1));
+// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Wp, Wm, Q.
+__device__ __forceinline__ int tiled(int j1, int m, int n1, int tshift) {
+  return (((m >> tshift) * n1 + j1) << tshift) + (m & ((1 << tshift) - 1));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give every XCD a contiguous range of work items so that neighbouring
+// rows, which share cache lines of the tiled arrays, meet in one L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+  if (nb & 7) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
 // Register slot kk (0..7) of the kept spectral positions: registers 0..3 hold
@@ -90,20 +137,25 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
   const int c = tid % T, t = tid / T;
-  const int m = blockIdx.x * T + c;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int m = tile * T + c;
   const bool live = m < f.m;
   float2* my = lds + c;
-  const size_t tile_base = (size_t)blockIdx.x * N1 * T;
-  const int h1 = f.h1;
+  const size_t tile_base = (size_t)tile * N1 * T + c;
+  gf2* const Qc = glob(f.Q) + tile_base;     // column m of Q: Qc[j1 * T]
+  gf2* const Wpc = glob(f.Wp) + tile_base;
+  gf2* const Wmc = glob(f.Wm) + tile_base;
+  gf2* const Sc = glob(f.S) + (size_t)m * f.h1 + N1 / 4;  // column m of the state: Sc[k1]
+  const auto tw1 = KernelTw<LOGN1>::make(f.tw1, t);
 
   float2 v[ff::kPts];
-  float2 st[8];
+  float2 sv[8];
 
   if constexpr (MODE == COL_STEP || MODE == COL_PROJECT) {
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i)
-      v[i] = live ? f.Q[tile_base + (size_t)(t + G * i) * T + c] : make_float2(0.f, 0.f);
-    fft<LOGN1, false>(v, t, my, T, f.tw1);
+      v[i] = live ? ld(Qc + (t + G * i) * T) : make_float2(0.f, 0.f);
+    fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
     if constexpr (MODE == COL_STEP) sc = step_scalars(f, n);
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
@@ -115,7 +167,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
       const int s = k1 + N1 / 4;
       float2 val;
       if constexpr (MODE == COL_STEP) {
-        const float2 old = live ? f.S[(size_t)m * h1 + s] : make_float2(0.f, 0.f);
+        const float2 old = live ? ld(Sc + k1) : make_float2(0.f, 0.f);
         const float kap1 = f.s1 * (float)k1;
         const float kk2 = kap1 * kap1 + kap2c * kap2c;
         const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
@@ -124,15 +176,15 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
         val = ff::cscale(v[i], inv_p);
       }
       if (s == 0) val = make_float2(0.f, 0.f);
-      st[kk] = val;
+      sv[kk] = val;
     }
-    if (blockIdx.x == 0) {
+    if (tile == 0) {
       // symmetrise column k2 = 0 (group c == 0): copy k1 > 0 conjugated onto -k1
       if (c == 0) {
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int k1 = t + G * kk;
-          lds[k1] = st[kk];
+          lds[k1] = sv[kk];
         }
       }
       __syncthreads();
@@ -140,9 +192,9 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
 #pragma unroll
         for (int kk = 4; kk < 8; ++kk) {
           const int k1 = t + G * kept_reg(kk) - N1;
-          if (k1 > -N1 / 4) st[kk] = ff::cconj(lds[-k1]);
+          if (k1 > -N1 / 4) sv[kk] = ff::cconj(lds[-k1]);
         }
-        if (t == 0) st[0].y = 0.f;
+        if (t == 0) sv[0].y = 0.f;
       }
       __syncthreads();
     }
@@ -151,7 +203,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
       for (int kk = 0; kk < 8; ++kk) {
         const int i = kept_reg(kk);
         const int k1 = t + G * i - (i >= 12 ? N1 : 0);
-        f.S[(size_t)m * h1 + k1 + N1 / 4] = st[kk];
+        st(Sc + k1, sv[kk]);
       }
     }
   } else {
@@ -159,7 +211,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
-      st[kk] = live ? f.S[(size_t)m * h1 + k1 + N1 / 4] : make_float2(0.f, 0.f);
+      sv[kk] = live ? ld(Sc + k1) : make_float2(0.f, 0.f);
     }
   }
 
@@ -167,11 +219,11 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) v[kept_reg(kk)] = st[kk];
-    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    for (int kk = 0; kk < 8; ++kk) v[kept_reg(kk)] = sv[kk];
+    fft<LOGN1, true>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) f.Q[tile_base + (size_t)(t + G * i) * T + c] = v[i];
+      for (int i = 0; i < ff::kPts; ++i) st(Qc + (t + G * i) * T, v[i]);
     }
   } else {
     const float kap2 = f.s2 * (float)m;
@@ -182,12 +234,12 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg(kk);
       const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
-      v[i] = make_float2(-kap1 * st[kk].y - kap2 * st[kk].x, kap1 * st[kk].x - kap2 * st[kk].y);
+      v[i] = make_float2(-kap1 * sv[kk].y - kap2 * sv[kk].x, kap1 * sv[kk].x - kap2 * sv[kk].y);
     }
-    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    fft<LOGN1, true>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) f.Wp[tile_base + (size_t)(t + G * i) * T + c] = v[i];
+      for (int i = 0; i < ff::kPts; ++i) st(Wpc + (t + G * i) * T, v[i]);
     }
     // Z- column for k2 = -m: conj(IFFT_k1((i kappa1 + kappa2) Phi~))
 #pragma unroll
@@ -196,12 +248,12 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg(kk);
       const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
-      v[i] = make_float2(-kap1 * st[kk].y + kap2 * st[kk].x, kap1 * st[kk].x + kap2 * st[kk].y);
+      v[i] = make_float2(-kap1 * sv[kk].y + kap2 * sv[kk].x, kap1 * sv[kk].x + kap2 * sv[kk].y);
     }
-    fft<LOGN1, true>(v, t, my, T, f.tw1);
+    fft<LOGN1, true>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) f.Wm[tile_base + (size_t)(t + G * i) * T + c] = ff::cconj(v[i]);
+      for (int i = 0; i < ff::kPts; ++i) st(Wmc + (t + G * i) * T, ff::cconj(v[i]));
     }
   }
 }
@@ -216,11 +268,15 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
   const int p = tid % B, t = tid / B;
-  const int pair = blockIdx.x * B + p;
+  const int pair = xcd_swizzle(blockIdx.x, gridDim.x) * B + p;
   const bool live = pair < f.n1 / 2;
   const int ja = 2 * pair, jb = 2 * pair + 1;
   const int n1 = f.n1, ts = f.tshift, mcols = f.m;
   float2* my = lds + p;
+  const auto tw2 = KernelTw<LOGN2>::make(f.tw2, t);
+  gf2* const Wp = glob(f.Wp);
+  gf2* const Wm = glob(f.Wm);
+  gf2* const Q = glob(f.Q);
 
   float2 y[ff::kPts];
 
@@ -241,15 +297,15 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
         float2 val = make_float2(0.f, 0.f);
         if (live) {
           if (i < 4) {
-            val = f.Wp[tiled(row, idx, n1, ts)];
+            val = ld(Wp + tiled(row, idx, n1, ts));
           } else if (i >= 12) {
             const int mm = N2 - idx;
-            if (mm < mcols) val = f.Wm[tiled(row, mm, n1, ts)];
+            if (mm < mcols) val = ld(Wm + tiled(row, mm, n1, ts));
           }
         }
         v[i] = val;
       }
-      fft<LOGN2, true>(v, t, my, B, f.tw2);
+      fft<LOGN2, true>(v, t, my, B, tw2);
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) {
         const float q = v[i].x * v[i].x + v[i].y * v[i].y;
@@ -281,7 +337,7 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) {
       const int idx = t + G * i;
-      y[i] = live ? make_float2(phys_in[(size_t)ja * N2 + idx], phys_in[(size_t)jb * N2 + idx])
+      y[i] = live ? make_float2(glob(phys_in)[(size_t)ja * N2 + idx], glob(phys_in)[(size_t)jb * N2 + idx])
                   : make_float2(0.f, 0.f);
     }
   } else {  // ROW_SYNTH: Y = X_a + i X_b with X(k2) = A(m) for k2 = m >= 0, conj(A(m)) for k2 = -m
@@ -291,12 +347,12 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
       float2 val = make_float2(0.f, 0.f);
       if (live) {
         if (i < 4) {
-          const float2 a = f.Q[tiled(ja, idx, n1, ts)], b = f.Q[tiled(jb, idx, n1, ts)];
+          const float2 a = ld(Q + tiled(ja, idx, n1, ts)), b = ld(Q + tiled(jb, idx, n1, ts));
           val = make_float2(a.x - b.y, a.y + b.x);
         } else if (i >= 12) {
           const int mm = N2 - idx;
           if (mm < mcols) {
-            const float2 a = f.Q[tiled(ja, mm, n1, ts)], b = f.Q[tiled(jb, mm, n1, ts)];
+            const float2 a = ld(Q + tiled(ja, mm, n1, ts)), b = ld(Q + tiled(jb, mm, n1, ts));
             // conj(a) + i conj(b)
             val = make_float2(a.x + b.y, -a.y + b.x);
           }
@@ -304,13 +360,13 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
       }
       y[i] = val;
     }
-    fft<LOGN2, true>(y, t, my, B, f.tw2);
+    fft<LOGN2, true>(y, t, my, B, tw2);
     if (live) {
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) {
         const int idx = t + G * i;
-        phys_out[(size_t)ja * N2 + idx] = y[i].x;
-        phys_out[(size_t)jb * N2 + idx] = y[i].y;
+        glob(phys_out)[(size_t)ja * N2 + idx] = y[i].x;
+        glob(phys_out)[(size_t)jb * N2 + idx] = y[i].y;
       }
     }
     return;
@@ -318,7 +374,7 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
 
   // forward transform of the two packed real rows, then split:
   // Q_a(k) = (Y(k) + conj(Y(-k)))/2, Q_b(k) = (Y(k) - conj(Y(-k)))/(2i), k in [0, K2]
-  fft<LOGN2, false>(y, t, my, B, f.tw2);
+  fft<LOGN2, false>(y, t, my, B, tw2);
   __syncthreads();
   ff::Fft<LOGN2, false>::scatter(y, t, my, B);
   __syncthreads();
@@ -330,8 +386,8 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
       const float2 ym = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
       const float2 qa = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
       const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
-      f.Q[tiled(ja, k, n1, ts)] = qa;
-      f.Q[tiled(jb, k, n1, ts)] = qb;
+      st(Q + tiled(ja, k, n1, ts), qa);
+      st(Q + tiled(jb, k, n1, ts), qb);
     }
   }
 }

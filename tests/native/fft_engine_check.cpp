@@ -4,7 +4,8 @@
 // runs the Stockham passes of ff::Fft with every thread of one group emulated
 // in turn (all threads finish a pass before any gathers), and writes the
 // 2^logn transformed values to stdout. The LDS array is shared by `stride`
-// interleaved groups; this group uses slot offset stride - 1.
+// interleaved groups; this group uses slot offset stride - 1. Odd strides
+// take the twiddles from the register cache, even strides from the table.
 
 #include <cstdio>
 #include <vector>
@@ -18,15 +19,23 @@ struct Regs {
 };
 
 template <int LOGN, bool INV, int P>
-void passes(std::vector<Regs>& v, float2* lds, int stride, const float2* tw) {
+void passes(std::vector<Regs>& v, float2* lds, int stride, const float2* tw, bool cached) {
   using S = ff::Shape<LOGN>;
   using F = ff::Fft<LOGN, INV>;
   if constexpr (P < S::NPASS) {
-    for (int t = 0; t < S::G; ++t) F::template butterflies<P>(v[t].a, t, lds, stride, tw);
+    for (int t = 0; t < S::G; ++t) {
+      if (cached) {
+        ff::RegTw<LOGN> rt;
+        rt.load([tw](int i) { return tw[i]; }, t);
+        F::template butterflies<P>(v[t].a, t, lds, stride, rt);
+      } else {
+        F::template butterflies<P>(v[t].a, t, lds, stride, ff::GlobalTw<LOGN>{tw, t});
+      }
+    }
     if constexpr (P + 1 < S::NPASS) {
       for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
     }
-    passes<LOGN, INV, P + 1>(v, lds, stride, tw);
+    passes<LOGN, INV, P + 1>(v, lds, stride, tw, cached);
   }
 }
 
@@ -39,7 +48,8 @@ void run(std::vector<float2>& x, int stride) {
   for (int t = 0; t < S::G; ++t)
     for (int i = 0; i < ff::kPts; ++i) v[t].a[i] = x[t + S::G * i];
   std::vector<float2> lds(size_t(S::LDS) * stride, make_float2(1e30f, 1e30f));
-  passes<LOGN, INV, 0>(v, lds.data() + (stride - 1), stride, tw.data());
+  // odd strides use the twiddles cached in registers, even strides the table
+  passes<LOGN, INV, 0>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
   for (int t = 0; t < S::G; ++t)
     for (int i = 0; i < ff::kPts; ++i) x[t + S::G * i] = v[t].a[i];
 }
