@@ -127,6 +127,29 @@ int flame_step(flame_plan plan, int32_t nsteps);
  * out4 is dev memory (4 doubles), written on the stream. */
 int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
 
+/* Adjoint of one step (integrating-factor Euler; the paper has no adjoint).
+ * Cotangents are the Fourier coefficients of the gradient with respect to the
+ * grid values of Phi, in the state layout (dev, complex64, flame_state_bytes):
+ * for band-limited real fields a, b the pairing is the grid sum
+ * sum_j a(x_j) b(x_j) = P Re sum_k conj(a~_k) b~_k over the whole box.
+ * For the step n -> n+1 taken from state_n (the state at step index n):
+ *   lam_out = mu - 2 dt c_n Pi div(m grad Phi^n),  mu = E^n lam_in,
+ * m the grid field of mu, c_n = 1/(2 r0(t_n)^2). lam_out may equal lam_in;
+ * state_n must not alias lam_out. Uses the plan's workspace, so the next
+ * flame_step rebuilds its intermediates. */
+int flame_adjoint_step(flame_plan plan, int32_t flame, int64_t n, const void* state_n, const void* lam_in,
+                       void* lam_out);
+
+/* Gradient of the area excess J of flame_diagnostics at step index n with
+ * respect to the grid values of Phi, evaluated at `state` (dev, state layout),
+ * written as a cotangent (see flame_adjoint_step):
+ *   lam_out = -Pi div( grad Phi / (P r0^2 sqrt(1 + |grad Phi|^2 / r0^2)) ). */
+int flame_area_gradient(flame_plan plan, int32_t flame, int64_t n, const void* state, void* lam_out);
+
+/* Grid field of any spectrum in the state layout (a state or a cotangent):
+ * phi(x_j) = sum_k spec~_k exp(i k.x_j) (dev, float32, n1 x n2 row-major). */
+int flame_synthesize(flame_plan plan, int32_t flame, const void* spec, float* phi);
+
 /* Start timing every kernel launch that flame_step and flame_diagnostics
  * queue from now on: each launch is bracketed by a pair of HIP events
  * recorded on the plan's stream (benchmarking aid; adds two event records per

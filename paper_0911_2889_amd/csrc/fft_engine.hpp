@@ -191,6 +191,41 @@ __host__ __device__ __forceinline__ void dft16(float2* x) {
   }
 }
 
+// dft16 for inputs x[4..11] == 0 (only the first and last quarter set).
+template <bool INV>
+__host__ __device__ __forceinline__ void dft16_outer(float2* x) {
+  constexpr float c1 = 0.92387953251128675613f;
+  constexpr float s1 = 0.38268343236508977173f;
+  float2 y[16];
+#pragma unroll
+  for (int r2 = 0; r2 < 4; ++r2) {
+    // length-4 transform of (x[r2], 0, 0, x[r2 + 12])
+    const float2 a = x[r2], d = x[r2 + 12], qd = mul_q<INV>(d);
+    y[4 * r2 + 0] = cadd(a, d);
+    y[4 * r2 + 1] = csub(a, qd);
+    y[4 * r2 + 2] = csub(a, d);
+    y[4 * r2 + 3] = cadd(a, qd);
+  }
+  y[5] = mul_root<INV>(y[5], c1, s1);
+  y[6] = mul_e1<INV>(y[6]);
+  y[7] = mul_root<INV>(y[7], s1, c1);
+  y[9] = mul_e1<INV>(y[9]);
+  y[10] = mul_q<INV>(y[10]);
+  y[11] = mul_e3<INV>(y[11]);
+  y[13] = mul_root<INV>(y[13], s1, c1);
+  y[14] = mul_e3<INV>(y[14]);
+  y[15] = mul_root<INV>(y[15], -c1, -s1);
+#pragma unroll
+  for (int m1 = 0; m1 < 4; ++m1) {
+    float2 a = y[m1], b = y[4 + m1], c = y[8 + m1], d = y[12 + m1];
+    dft4<INV>(a, b, c, d);
+    x[m1] = a;
+    x[m1 + 4] = b;
+    x[m1 + 8] = c;
+    x[m1 + 12] = d;
+  }
+}
+
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2* x) {
   if constexpr (R == 2) {
@@ -211,7 +246,7 @@ __host__ __device__ __forceinline__ void dft(float2* x) {
 template <int LOGN>
 struct GlobalTw {
   using S = Shape<LOGN>;
-  const float2* __restrict__ tw;
+  const float2* tw;
   int t;
   template <int P>
   __host__ __device__ __forceinline__ float2 get(int b, int r) const {
@@ -221,43 +256,52 @@ struct GlobalTw {
   }
 };
 
-// Twiddle source holding, in registers, every twiddle thread t needs: loaded
-// once and reused by all transforms of one length in a kernel.
-template <int LOGN>
+// Twiddle source holding in registers the twiddles thread t needs in the
+// passes with Ns >= MIN_NS (others are read from the table at each use; a pass
+// with Ns <= 16 has at most 16 distinct twiddles per radix index, one cache
+// line per wave). Loaded once and reused by every transform of one length in
+// a kernel. `fetch(i)` returns table entry i.
+template <int LOGN, class F, int MIN_NS = 2>
 struct RegTw {
   using S = Shape<LOGN>;
-  static constexpr int per_pass(int p) { return kPts - kPts / S::radix(p); }
+  static constexpr bool cached(int p) { return p > 0 && p < S::NPASS && S::ns(p) >= MIN_NS; }
+  static constexpr int per_pass(int p) { return cached(p) ? kPts - kPts / S::radix(p) : 0; }
   static constexpr int offset(int p) {
     int o = 0;
     for (int q = 1; q < p; ++q) o += per_pass(q);
     return o;
   }
-  static constexpr int COUNT = S::NPASS > 1 ? offset(S::NPASS) : 1;
+  static constexpr int COUNT = offset(S::NPASS) > 0 ? offset(S::NPASS) : 1;
   float2 w[COUNT];
+  F fetch;
+  int t;
 
-  // fetch(i) returns entry i of the twiddle table
-  template <class F>
-  __host__ __device__ __forceinline__ void load(const F& fetch, int t) {
-    load_pass<1>(fetch, t);
-  }
+  __host__ __device__ __forceinline__ RegTw(const F& f, int t_) : fetch(f), t(t_) { load_pass<1>(); }
 
-  template <int P, class F>
-  __host__ __device__ __forceinline__ void load_pass(const F& fetch, int t) {
+  template <int P>
+  __host__ __device__ __forceinline__ void load_pass() {
     if constexpr (P < S::NPASS) {
-      constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
+      if constexpr (cached(P)) {
+        constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int k = (t + b * S::G) & (NS - 1);
+        for (int b = 0; b < NB; ++b) {
+          const int k = (t + b * S::G) & (NS - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[offset(P) + b * (R - 1) + (r - 1)] = fetch(S::tw_off(P) + (r - 1) * NS + k);
+          for (int r = 1; r < R; ++r) w[offset(P) + b * (R - 1) + (r - 1)] = fetch(S::tw_off(P) + (r - 1) * NS + k);
+        }
       }
-      load_pass<P + 1>(fetch, t);
+      load_pass<P + 1>();
     }
   }
 
   template <int P>
   __host__ __device__ __forceinline__ float2 get(int b, int r) const {
-    return w[offset(P) + b * (S::radix(P) - 1) + (r - 1)];
+    if constexpr (cached(P)) {
+      return w[offset(P) + b * (S::radix(P) - 1) + (r - 1)];
+    } else {
+      constexpr int NS = S::ns(P);
+      return fetch(S::tw_off(P) + (r - 1) * NS + ((t + b * S::G) & (NS - 1)));
+    }
   }
 };
 
@@ -270,7 +314,9 @@ struct Fft {
   // applies the twiddles w(j mod Ns, r), the radix-R DFT, and sends output r
   // to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns: into LDS, or, in the
   // last pass (Ns * R = N), back into the same registers.
-  template <int P, class TW>
+  // OUTER: the caller guarantees v[4..11] == 0 on entry to pass 0 (inputs
+  // confined to the first and last quarter), which prunes the first butterfly.
+  template <int P, class TW, bool OUTER = false>
   static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[kPts], int t, float2* lds, int stride,
                                                               const TW& tw) {
     constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
@@ -290,7 +336,11 @@ struct Fft {
           x[r] = cmul(x[r], wr);
         }
       }
-      dft<R, INV>(x);
+      if constexpr (OUTER && P == 0 && R == 16) {
+        dft16_outer<INV>(x);
+      } else {
+        dft<R, INV>(x);
+      }
       if constexpr (LAST) {
 #pragma unroll
         for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -85,7 +86,7 @@ int check_desc(const flame_desc* d, Sizes* s) {
 
 struct Layout {
   std::vector<Sizes> sizes;
-  std::vector<size_t> off_wp, off_wm, off_q, off_part;
+  std::vector<size_t> off_wp, off_wm, off_q, off_a1, off_a2, off_part;
   size_t off_tw[flame::kMaxLog + 1];
   size_t off_dev;
   size_t total;
@@ -108,6 +109,10 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
     L->off_wm.push_back(off);
     off = align_up(off + s.wq_elems * sizeof(float2));
     L->off_q.push_back(off);
+    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_a1.push_back(off);
+    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_a2.push_back(off);
     off = align_up(off + s.wq_elems * sizeof(float2));
     L->off_part.push_back(off);
     off = align_up(off + s.part_elems * sizeof(double));
@@ -161,12 +166,15 @@ struct flame_plan_s {
   long long n = 0;
   // per-kernel timing (flame_timing_begin / flame_timing_end)
   bool timing = false;
+  hipEvent_t chain = nullptr;  // last event of the current chain of timed launches
   std::vector<hipEvent_t> ev_pool;
   std::vector<hipEvent_t> ev_used[3];
   ~flame_plan_s() {
-    for (auto& v : ev_used)
-      for (hipEvent_t e : v) (void)hipEventDestroy(e);
-    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    std::vector<hipEvent_t> all(ev_pool);
+    for (auto& v : ev_used) all.insert(all.end(), v.begin(), v.end());
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    for (hipEvent_t e : all) (void)hipEventDestroy(e);
   }
 };
 
@@ -197,26 +205,27 @@ hipEvent_t take_event(flame_plan p) {
   return e;
 }
 
-// Brackets one launch with events on the plan's stream when timing is on.
+// Times consecutive launches with a chain of events on the plan's stream:
+// the event recorded after one launch also opens the next, so the intervals
+// partition the stream time (each includes its launch gap).
 class Timed {
  public:
   Timed(flame_plan p, int kind) : p_(p), kind_(kind) {
-    if (p_->timing) {
-      start_ = take_event(p_);
-      if (start_) (void)hipEventRecord(start_, p_->stream);
+    if (!p_->timing) return;
+    if (!p_->chain) {
+      p_->chain = take_event(p_);
+      if (p_->chain) (void)hipEventRecord(p_->chain, p_->stream);
     }
+    start_ = p_->chain;
   }
   ~Timed() {
-    if (p_->timing && start_) {
-      hipEvent_t stop = take_event(p_);
-      if (stop) {
-        (void)hipEventRecord(stop, p_->stream);
-        p_->ev_used[kind_].push_back(start_);
-        p_->ev_used[kind_].push_back(stop);
-      } else {
-        p_->ev_pool.push_back(start_);
-      }
-    }
+    if (!p_->timing || !start_) return;
+    hipEvent_t stop = take_event(p_);
+    if (!stop) return;
+    (void)hipEventRecord(stop, p_->stream);
+    p_->ev_used[kind_].push_back(start_);
+    p_->ev_used[kind_].push_back(stop);
+    p_->chain = stop;
   }
 
  private:
@@ -224,6 +233,9 @@ class Timed {
   int kind_;
   hipEvent_t start_ = nullptr;
 };
+
+// Ends a chain of timed launches (another command may follow on the stream).
+void break_chain(flame_plan p) { p->chain = nullptr; }
 
 int rebuild_w(flame_plan p, int flame) {
   const Sizes& s = p->layout.sizes[flame];
@@ -325,6 +337,8 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.Wp = reinterpret_cast<float2*>(base + L.off_wp[f]);
     fd.Wm = reinterpret_cast<float2*>(base + L.off_wm[f]);
     fd.Q = reinterpret_cast<float2*>(base + L.off_q[f]);
+    fd.A1 = reinterpret_cast<float2*>(base + L.off_a1[f]);
+    fd.A2 = reinterpret_cast<float2*>(base + L.off_a2[f]);
     fd.part = reinterpret_cast<double*>(base + L.off_part[f]);
     fd.tw1 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn1]);
     fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
@@ -451,6 +465,7 @@ int flame_step(flame_plan p, int32_t nsteps) {
     }
     p->n += 1;
   }
+  break_chain(p);
   return last_launch("step launch");
 }
 
@@ -471,16 +486,64 @@ int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
     flame::launch_diag_spectral(p->stream, p->ddev, flame, s.n_spec, part + s.rgroups);
     flame::launch_diag_final(p->stream, p->ddev, flame, p->n, s.rgroups, s.n_spec, out4);
   }
+  break_chain(p);
   return last_launch("diagnostics launch");
+}
+
+int flame_adjoint_step(flame_plan p, int32_t flame, int64_t n, const void* state_n, const void* lam_in,
+                       void* lam_out) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!state_n || !lam_in || !lam_out) return fail(FLAME_ERR_INVALID_ARG, "null state or cotangent pointer");
+  if (state_n == lam_out) return fail(FLAME_ERR_INVALID_ARG, "state_n must not alias lam_out");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  flame::FlameDev* fd = p->ddev + flame;
+  flame::launch_adj_col(s.logn1, flame::ADJ_A, s.tiles, p->stream, fd, n, state_n, lam_in, nullptr);
+  flame::launch_adj_row(s.logn2, flame::ROW_ADJ, s.rgroups, p->stream, fd, n);
+  flame::launch_adj_col(s.logn1, flame::ADJ_C, s.tiles, p->stream, fd, n, nullptr, lam_in, lam_out);
+  p->w_valid[flame] = 0;
+  return last_launch("adjoint step launch");
+}
+
+int flame_area_gradient(flame_plan p, int32_t flame, int64_t n, const void* state, void* lam_out) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!state || !lam_out) return fail(FLAME_ERR_INVALID_ARG, "null state or cotangent pointer");
+  if (state == lam_out) return fail(FLAME_ERR_INVALID_ARG, "state must not alias lam_out");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  flame::FlameDev* fd = p->ddev + flame;
+  flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, fd, n, state);
+  flame::launch_adj_row(s.logn2, flame::ROW_SEED, s.rgroups, p->stream, fd, n);
+  flame::launch_adj_col(s.logn1, flame::SEED_C, s.tiles, p->stream, fd, n, nullptr, nullptr, lam_out);
+  p->w_valid[flame] = 0;
+  return last_launch("area gradient launch");
+}
+
+int flame_synthesize(flame_plan p, int32_t flame, const void* spec, float* phi) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!spec || !phi) return fail(FLAME_ERR_INVALID_ARG, "null spectrum or field pointer");
+  DeviceGuard g(p->device);
+  const Sizes& s = p->layout.sizes[flame];
+  flame::launch_col(s.logn1, flame::COL_SYNTH, s.tiles, 1, p->stream, p->ddev + flame, p->n, spec);
+  flame::launch_row(s.logn2, flame::ROW_SYNTH, s.rgroups, 1, p->stream, p->ddev + flame, p->n, nullptr, phi);
+  return last_launch("synthesize launch");
 }
 
 int flame_timing_begin(flame_plan p) {
   int rc = check_plan(p);
   if (rc) return rc;
+  std::vector<hipEvent_t> all;
   for (auto& v : p->ev_used) {
-    p->ev_pool.insert(p->ev_pool.end(), v.begin(), v.end());
+    all.insert(all.end(), v.begin(), v.end());
     v.clear();
   }
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  p->ev_pool.insert(p->ev_pool.end(), all.begin(), all.end());
+  p->chain = nullptr;
   p->timing = true;
   return FLAME_OK;
 }

@@ -18,6 +18,8 @@ struct FlameDev {
   float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~, tiled [m/T][j1][m%T]
   float2* Wm;          // conj of column transforms of (i kappa1 + kappa2) Phi~, same layout
   float2* Q;           // row transforms of |grad Phi|^2 (and scratch), same layout
+  float2* A1;          // adjoint scratch, same layout: row transform of w1 = m g1
+  float2* A2;          // adjoint scratch, same layout: i kappa2 x row transform of w2 = m g2
   const float2* tw1;   // twiddles of the length-N1 transform
   const float2* tw2;   // twiddles of the length-N2 transform
   double* part;        // per-workgroup partial sums of the diagnostics
@@ -56,6 +58,14 @@ constexpr int row_pairs(int logn2) { return (1 << logn2) / ff::kPts >= 256 ? 1 :
 
 enum ColMode : int { COL_STEP = 0, COL_FIRST = 1, COL_PROJECT = 2, COL_SYNTH = 3 };
 enum RowMode : int { ROW_STEP = 0, ROW_FORWARD = 1, ROW_SYNTH = 2, ROW_DIAG = 3 };
+// Adjoint column kernel: ADJ_A forms mu = E lambda and the column transforms
+// of mu and of the state's packed gradient; ADJ_C / SEED_C form the
+// divergence from the row transforms in A1, A2 and write the cotangent.
+enum AdjColMode : int { ADJ_A = 0, ADJ_C = 1, SEED_C = 2 };
+// Adjoint row kernel: ROW_ADJ forms w = m grad Phi, ROW_SEED forms
+// w = grad Phi / (r0^2 sqrt(1 + |grad Phi|^2 / r0^2)); both write the row
+// transforms of w1 and i kappa2 w2 to A1, A2.
+enum AdjRowMode : int { ROW_ADJ = 0, ROW_SEED = 1 };
 
 // Keep each thread's twiddles in registers for a kernel's lifetime (the
 // alternative reads the table in every pass).
@@ -63,6 +73,34 @@ enum RowMode : int { ROW_STEP = 0, ROW_FORWARD = 1, ROW_SYNTH = 2, ROW_DIAG = 3 
 #define FLAME_CACHE_TWIDDLES 1
 #endif
 constexpr bool kCacheTwiddles = FLAME_CACHE_TWIDDLES != 0;
+// Passes with Ns >= this keep their twiddles in registers (2: every pass).
+#ifndef FLAME_TW_CACHE_MIN_NS
+#define FLAME_TW_CACHE_MIN_NS 2
+#endif
+constexpr int kTwCacheMinNs = FLAME_TW_CACHE_MIN_NS;
+// Prune the first butterfly of inverse transforms whose input is zero in the
+// middle half of the padded spectrum.
+#ifndef FLAME_PRUNE
+#define FLAME_PRUNE 1
+#endif
+constexpr bool kPrune = FLAME_PRUNE != 0;
+// Row kernel: load the second row of a pair before transforming the first.
+#ifndef FLAME_ROW_PREFETCH
+#define FLAME_ROW_PREFETCH 1
+#endif
+constexpr bool kRowPrefetch = FLAME_ROW_PREFETCH != 0;
+
+// Minimum waves per SIMD the row and column kernels are compiled for (a
+// register budget of 512 / waves VGPRs).
+#ifndef ROW_WAVES_PER_EU
+#define ROW_WAVES_PER_EU 3
+#endif
+#ifndef COL_WAVES_PER_EU
+#define COL_WAVES_PER_EU 2
+#endif
+#ifndef ADJ_ROW_WAVES_PER_EU
+#define ADJ_ROW_WAVES_PER_EU 2
+#endif
 
 constexpr int kMinLog = 4;
 constexpr int kMaxLog = 12;

@@ -24,113 +24,13 @@
 #include "fft_engine.hpp"
 #include "flame_dev.hpp"
 #include "flame_kernels.hpp"
+#include "kernel_common.hpp"
 
 namespace flame {
 
-namespace {
-
-template <int LOGN, bool INV, int P = 0, class TW>
-__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
-  using S = ff::Shape<LOGN>;
-  if constexpr (P < S::NPASS) {
-    ff::Fft<LOGN, INV>::template butterflies<P>(v, t, lds, stride, tw);
-    if constexpr (P + 1 < S::NPASS) {
-      __syncthreads();
-      ff::Fft<LOGN, INV>::gather(v, t, lds, stride);
-      __syncthreads();
-    }
-    fft_passes<LOGN, INV, P + 1>(v, t, lds, stride, tw);
-  }
-}
-
-// Transform the 16 registers of every group of the workgroup (all threads
-// must call it: it contains workgroup barriers). On entry v[i] holds the
-// input at position t + G*i, on exit the output at the same position.
-template <int LOGN, bool INV, class TW>
-__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
-  fft_passes<LOGN, INV, 0>(v, t, lds, stride, tw);
-}
-
-// Global-memory views: loads and stores through these pointers compile to
-// global_* instructions (flat ones would also wait on LDS counters).
-using v2f = float __attribute__((ext_vector_type(2)));
-using gf2 = __attribute__((address_space(1))) v2f;
-using gf1 = __attribute__((address_space(1))) float;
-__device__ __forceinline__ gf2* glob(float2* p) { return (gf2*)p; }
-__device__ __forceinline__ const gf1* glob(const float* p) { return (const gf1*)p; }
-__device__ __forceinline__ gf1* glob(float* p) { return (gf1*)p; }
-__device__ __forceinline__ float2 ld(const gf2* p) {
-  const v2f v = *p;
-  return make_float2(v.x, v.y);
-}
-__device__ __forceinline__ void st(gf2* p, float2 a) {
-  v2f v;
-  v.x = a.x;
-  v.y = a.y;
-  *p = v;
-}
-
-// Twiddle source of a kernel: cached in registers for the kernel's lifetime
-// (each kernel runs two or three transforms of one length), or read from the
-// table in every pass.
-template <int LOGN>
-struct KernelTw {
-  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN>, ff::GlobalTw<LOGN>>::type;
-  static __device__ __forceinline__ Type make(const float2* __restrict__ tw, int t) {
-    Type out;
-    if constexpr (kCacheTwiddles) {
-      const gf2* g = (const gf2*)tw;
-      out.load([g](int i) { return ld(g + i); }, t);
-    } else {
-      out.tw = tw;
-      out.t = t;
-    }
-    return out;
-  }
-};
-
-struct StepScalars {
-  float a;    // dt * c_n / P, multiplies the raw transform of |grad Phi|^2
-  float i1;   // int_{t_n}^{t_{n+1}} dt / r0
-  float i2;   // int_{t_n}^{t_{n+1}} dt / r0^2
-};
-
-// r0(t) = t (Section 2): c_n = 1/(2 t_n^2), I1 = ln(t_{n+1}/t_n),
-// I2 = 1/t_n - 1/t_{n+1}. The time is formed in double; the scalars need only
-// float accuracy.
-__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n) {
-  const float t = (float)(f.t0 + (double)n * f.dt);
-  const float dt = (float)f.dt;
-  const float x = dt / t;
-  StepScalars s;
-  s.a = 0.5f * x / (t * (float)f.n1 * (float)f.n2);
-  s.i1 = log1pf(x);
-  s.i2 = x / (t + dt);
-  return s;
-}
-
-// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Wp, Wm, Q.
-__device__ __forceinline__ int tiled(int j1, int m, int n1, int tshift) {
-  return (((m >> tshift) * n1 + j1) << tshift) + (m & ((1 << tshift) - 1));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Give every XCD a contiguous range of work items so that neighbouring
-// rows, which share cache lines of the tiled arrays, meet in one L2.
-__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
-  if (nb & 7) return b;
-  return (b & 7) * (nb >> 3) + (b >> 3);
-}
-
-// Register slot kk (0..7) of the kept spectral positions: registers 0..3 hold
-// k1 = t + G*i >= 0, registers 12..15 hold k1 = t + G*i - N1 < 0.
-__device__ __forceinline__ constexpr int kept_reg(int kk) { return kk < 4 ? kk : kk + 8; }
-
-}  // namespace
-
 template <int LOGN1, int MODE>
-__global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
-    col_kernel(const FlameDev* __restrict__ fls, long long n) {
+__global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
+    col_kernel(const FlameDev* __restrict__ fls, long long n, const float2* src) {
   using S = ff::Shape<LOGN1>;
   constexpr int G = S::G, T = ColCfg<LOGN1>::T, N1 = S::N;
   extern __shared__ float2 lds[];
@@ -145,7 +45,10 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
   gf2* const Qc = glob(f.Q) + tile_base;     // column m of Q: Qc[j1 * T]
   gf2* const Wpc = glob(f.Wp) + tile_base;
   gf2* const Wmc = glob(f.Wm) + tile_base;
-  gf2* const Sc = glob(f.S) + (size_t)m * f.h1 + N1 / 4;  // column m of the state: Sc[k1]
+  // column m of the state: Sc[k1]; COL_FIRST and COL_SYNTH may read another
+  // spectrum in the same layout (src), the other modes update the state
+  gf2* const Sc = glob((MODE == COL_FIRST || MODE == COL_SYNTH) && src ? const_cast<float2*>(src) : f.S) +
+                  (size_t)m * f.h1 + N1 / 4;
   const auto tw1 = KernelTw<LOGN1>::make(f.tw1, t);
 
   float2 v[ff::kPts];
@@ -155,6 +58,14 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i)
       v[i] = live ? ld(Qc + (t + G * i) * T) : make_float2(0.f, 0.f);
+    // the old state is loaded before the transform so its latency is hidden
+    float2 old[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+      const int i = kept_reg(kk);
+      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+      old[kk] = (MODE == COL_STEP && live) ? ld(Sc + k1) : make_float2(0.f, 0.f);
+    }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
     if constexpr (MODE == COL_STEP) sc = step_scalars(f, n);
@@ -167,11 +78,10 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
       const int s = k1 + N1 / 4;
       float2 val;
       if constexpr (MODE == COL_STEP) {
-        const float2 old = live ? ld(Sc + k1) : make_float2(0.f, 0.f);
         const float kap1 = f.s1 * (float)k1;
         const float kk2 = kap1 * kap1 + kap2c * kap2c;
         const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
-        val = make_float2(e * (old.x + sc.a * v[i].x), e * (old.y + sc.a * v[i].y));
+        val = make_float2(e * (old[kk].x + sc.a * v[i].x), e * (old[kk].y + sc.a * v[i].y));
       } else {
         val = ff::cscale(v[i], inv_p);
       }
@@ -220,7 +130,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
     for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) v[kept_reg(kk)] = sv[kk];
-    fft<LOGN1, true>(v, t, my, T, tw1);
+    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) st(Qc + (t + G * i) * T, v[i]);
@@ -236,7 +146,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
       const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
       v[i] = make_float2(-kap1 * sv[kk].y - kap2 * sv[kk].x, kap1 * sv[kk].x - kap2 * sv[kk].y);
     }
-    fft<LOGN1, true>(v, t, my, T, tw1);
+    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) st(Wpc + (t + G * i) * T, v[i]);
@@ -250,7 +160,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
       const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
       v[i] = make_float2(-kap1 * sv[kk].y + kap2 * sv[kk].x, kap1 * sv[kk].x + kap2 * sv[kk].y);
     }
-    fft<LOGN1, true>(v, t, my, T, tw1);
+    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) st(Wmc + (t + G * i) * T, ff::cconj(v[i]));
@@ -259,7 +169,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS)
 }
 
 template <int LOGN2, int MODE>
-__global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
+__global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_waves_per_eu(ROW_WAVES_PER_EU)))
     row_kernel(const FlameDev* __restrict__ fls, long long n, const float* __restrict__ phys_in,
                float* __restrict__ phys_out) {
   using S = ff::Shape<LOGN2>;
@@ -287,10 +197,11 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
       const double t0 = f.t0 + (double)n * f.dt;
       return (float)(1.0 / (t0 * t0));
     }();
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
+    // kRowPrefetch: both rows' inputs are loaded up front so the second row's
+    // load latency hides behind the first row's transform
+    float2 vr[2][ff::kPts];
+    auto load_row = [&](int half) {
       const int row = half ? jb : ja;
-      float2 v[ff::kPts];
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) {
         const int idx = t + G * i;
@@ -303,12 +214,20 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
             if (mm < mcols) val = ld(Wm + tiled(row, mm, n1, ts));
           }
         }
-        v[i] = val;
+        vr[half][i] = val;
       }
-      fft<LOGN2, true>(v, t, my, B, tw2);
+    };
+    load_row(0);
+    if constexpr (kRowPrefetch) load_row(1);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if constexpr (!kRowPrefetch) {
+        if (half == 1) load_row(1);
+      }
+      fft<LOGN2, true, kPrune>(vr[half], t, my, B, tw2);
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) {
-        const float q = v[i].x * v[i].x + v[i].y * v[i].y;
+        const float q = vr[half][i].x * vr[half][i].x + vr[half][i].y * vr[half][i].y;
         if constexpr (MODE == ROW_DIAG) {
           const double x = (double)q * (double)inv_r2;
           area += x / (1.0 + sqrt(1.0 + x));
@@ -360,7 +279,7 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS)
       }
       y[i] = val;
     }
-    fft<LOGN2, true>(y, t, my, B, tw2);
+    fft<LOGN2, true, kPrune>(y, t, my, B, tw2);
     if (live) {
 #pragma unroll
       for (int i = 0; i < ff::kPts; ++i) {
@@ -499,13 +418,15 @@ namespace {
 
 template <int LOGN>
 struct ColTable {
-  static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n) {
+  static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n, const float2* src) {
     constexpr int th = ColCfg<LOGN>::THREADS, lds = ColCfg<LOGN>::LDS_BYTES;
     switch (mode) {
-      case COL_STEP: hipLaunchKernelGGL((col_kernel<LOGN, COL_STEP>), grid, dim3(th), lds, st, fl, n); break;
-      case COL_FIRST: hipLaunchKernelGGL((col_kernel<LOGN, COL_FIRST>), grid, dim3(th), lds, st, fl, n); break;
-      case COL_PROJECT: hipLaunchKernelGGL((col_kernel<LOGN, COL_PROJECT>), grid, dim3(th), lds, st, fl, n); break;
-      default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n); break;
+      case COL_STEP: hipLaunchKernelGGL((col_kernel<LOGN, COL_STEP>), grid, dim3(th), lds, st, fl, n, src); break;
+      case COL_FIRST: hipLaunchKernelGGL((col_kernel<LOGN, COL_FIRST>), grid, dim3(th), lds, st, fl, n, src); break;
+      case COL_PROJECT:
+        hipLaunchKernelGGL((col_kernel<LOGN, COL_PROJECT>), grid, dim3(th), lds, st, fl, n, src);
+        break;
+      default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, src); break;
     }
   }
 };
@@ -536,8 +457,9 @@ void dispatch_log(int logn, A... args) {
 
 }  // namespace
 
-void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n) {
-  dispatch_log<ColTable, kMinLog>(logn1, mode, dim3(tiles, nfl), st, fl, n);
+void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
+                const void* src) {
+  dispatch_log<ColTable, kMinLog>(logn1, mode, dim3(tiles, nfl), st, fl, n, static_cast<const float2*>(src));
 }
 
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,

@@ -9,8 +9,15 @@
 namespace flame {
 
 // Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
-// (fl points at their consecutive FlameDev entries in device memory).
-void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n);
+// (fl points at their consecutive FlameDev entries in device memory). src,
+// if not null, replaces the state read by COL_FIRST and COL_SYNTH.
+void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
+                const void* src = nullptr);
+
+// Adjoint kernels (adjoint_kernels.hip); see the modes in flame_dev.hpp.
+void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
+                    const void* state, const void* lam_in, void* lam_out);
+void launch_adj_row(int logn2, int mode, int groups, hipStream_t st, const FlameDev* fl, long long n);
 
 // Row kernel over `groups` groups of B row pairs for `nfl` flames of one size.
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,

@@ -1,0 +1,116 @@
+// Device helpers shared by the forward and adjoint kernels.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "fft_engine.hpp"
+#include "flame_dev.hpp"
+
+namespace flame {
+
+template <int LOGN, bool INV, bool OUTER, int P = 0, class TW>
+__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
+  using S = ff::Shape<LOGN>;
+  if constexpr (P < S::NPASS) {
+    ff::Fft<LOGN, INV>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
+    if constexpr (P + 1 < S::NPASS) {
+      __syncthreads();
+      ff::Fft<LOGN, INV>::gather(v, t, lds, stride);
+      __syncthreads();
+    }
+    fft_passes<LOGN, INV, OUTER, P + 1>(v, t, lds, stride, tw);
+  }
+}
+
+// Transform the 16 registers of every group of the workgroup (all threads
+// must call it: it contains workgroup barriers). On entry v[i] holds the
+// input at position t + G*i, on exit the output at the same position.
+// OUTER: the input is known to vanish in registers 4..11 (the retained box
+// fills only the first and last quarter of a padded spectrum).
+template <int LOGN, bool INV, bool OUTER = false, class TW>
+__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
+  fft_passes<LOGN, INV, OUTER, 0>(v, t, lds, stride, tw);
+}
+
+// Global-memory views: loads and stores through these pointers compile to
+// global_* instructions (flat ones would also wait on LDS counters).
+using v2f = float __attribute__((ext_vector_type(2)));
+using gf2 = __attribute__((address_space(1))) v2f;
+using gf1 = __attribute__((address_space(1))) float;
+__device__ __forceinline__ gf2* glob(float2* p) { return (gf2*)p; }
+__device__ __forceinline__ const gf1* glob(const float* p) { return (const gf1*)p; }
+__device__ __forceinline__ gf1* glob(float* p) { return (gf1*)p; }
+__device__ __forceinline__ float2 ld(const gf2* p) {
+  const v2f v = *p;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st(gf2* p, float2 a) {
+  v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  *p = v;
+}
+
+// Twiddle source of a kernel: cached in registers for the kernel's lifetime
+// (each kernel runs two or three transforms of one length), or read from the
+// table in every pass.
+struct GlobalFetch {
+  const gf2* tw;
+  __device__ __forceinline__ float2 operator()(int i) const { return ld(tw + i); }
+};
+
+template <int LOGN>
+struct KernelTw {
+  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN, GlobalFetch, kTwCacheMinNs>,
+                                         ff::GlobalTw<LOGN>>::type;
+  static __device__ __forceinline__ Type make(const float2* tw, int t) {
+    if constexpr (kCacheTwiddles) {
+      return Type(GlobalFetch{(const gf2*)tw}, t);
+    } else {
+      return Type{tw, t};
+    }
+  }
+};
+
+struct StepScalars {
+  float a;    // dt * c_n / P, multiplies the raw transform of |grad Phi|^2
+  float i1;   // int_{t_n}^{t_{n+1}} dt / r0
+  float i2;   // int_{t_n}^{t_{n+1}} dt / r0^2
+};
+
+// r0(t) = t (Section 2): c_n = 1/(2 t_n^2), I1 = ln(t_{n+1}/t_n),
+// I2 = 1/t_n - 1/t_{n+1}. The time is formed in double; the scalars need only
+// float accuracy.
+__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n) {
+  const float t = (float)(f.t0 + (double)n * f.dt);
+  const float dt = (float)f.dt;
+  const float x = dt / t;
+  StepScalars s;
+  s.a = 0.5f * x / (t * (float)f.n1 * (float)f.n2);
+  s.i1 = log1pf(x);
+  s.i2 = x / (t + dt);
+  return s;
+}
+
+// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Wp, Wm, Q.
+__device__ __forceinline__ int tiled(int j1, int m, int n1, int tshift) {
+  return (((m >> tshift) * n1 + j1) << tshift) + (m & ((1 << tshift) - 1));
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). Give every XCD a contiguous range of work items so that neighbouring
+// rows, which share cache lines of the tiled arrays, meet in one L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+  if (nb & 7) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Register slot kk (0..7) of the kept spectral positions: registers 0..3 hold
+// k1 = t + G*i >= 0, registers 12..15 hold k1 = t + G*i - N1 < 0.
+__device__ __forceinline__ constexpr int kept_reg(int kk) { return kk < 4 ? kk : kk + 8; }
+
+
+}  // namespace flame

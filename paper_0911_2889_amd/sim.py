@@ -116,6 +116,33 @@ class FlameEnsemble:
         v = buf.cpu().tolist()
         return {"mean_radius": v[0], "velocity": v[1], "area_excess": v[2], "finite": bool(v[3] == 1.0)}
 
+    # ------------------------------------------------------------ adjoint
+    def new_cotangent(self, flame=0):
+        """Zeroed buffer in the state layout (for cotangents and saved states)."""
+        return torch.zeros_like(self.states[flame])
+
+    def adjoint_step(self, n, state_n, lam_in, lam_out, flame=0):
+        """lam_out = (d Phi^{n+1} / d Phi^n)^T lam_in for the step taken from state_n."""
+        self._check_flame(flame)
+        native.check(self.lib.flame_adjoint_step(self.plan, flame, int(n), ctypes.c_void_p(state_n.data_ptr()),
+                                                 ctypes.c_void_p(lam_in.data_ptr()),
+                                                 ctypes.c_void_p(lam_out.data_ptr())))
+
+    def area_gradient(self, n, state, lam_out, flame=0):
+        """lam_out = dJ/dPhi of the area excess at `state` (step index n)."""
+        self._check_flame(flame)
+        native.check(self.lib.flame_area_gradient(self.plan, flame, int(n), ctypes.c_void_p(state.data_ptr()),
+                                                  ctypes.c_void_p(lam_out.data_ptr())))
+
+    def synthesize(self, spec, flame=0):
+        """Grid field (float32, n1 x n2) of a spectrum in the state layout."""
+        self._check_flame(flame)
+        d = self.descs[flame]
+        out = torch.empty((d.n1, d.n2), dtype=torch.float32, device=self.device)
+        native.check(self.lib.flame_synthesize(self.plan, flame, ctypes.c_void_p(spec.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def timing_begin(self):
         native.check(self.lib.flame_timing_begin(self.plan))
 
@@ -144,3 +171,50 @@ class FlameSim(FlameEnsemble):
 
     def __init__(self, n1, n2, device="cuda", ws_fill=None, **kw):
         super().__init__([dict(n1=n1, n2=n2, **kw)], device=device, ws_fill=ws_fill)
+
+
+class _FlameArea(torch.autograd.Function):
+    """J(phi0) = area excess after nsteps, with a checkpointed hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, phi0, sim, nsteps, checkpoint_every, flame):
+        sim.set_phi(phi0.detach(), n=0, flame=flame)
+        checkpoints = []
+        n = 0
+        while n < nsteps:
+            checkpoints.append((n, sim.states[flame].clone()))
+            k = min(checkpoint_every, nsteps - n)
+            sim.step(k)
+            n += k
+        final = sim.states[flame].clone()
+        area = sim.diagnostics(flame)["area_excess"]
+        ctx.sim, ctx.nsteps, ctx.every, ctx.flame = sim, nsteps, checkpoint_every, flame
+        ctx.checkpoints, ctx.final = checkpoints, final
+        return torch.tensor(area, dtype=torch.float64, device=phi0.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        sim, f = ctx.sim, ctx.flame
+        lam = sim.new_cotangent(f)
+        sim.area_gradient(ctx.nsteps, ctx.final, lam, flame=f)
+        for n0, saved in reversed(ctx.checkpoints):
+            k = min(ctx.every, ctx.nsteps - n0)
+            # recompute the states n0 .. n0+k-1 of this segment from its checkpoint
+            ring = [saved]
+            sim.states[f].copy_(saved)
+            sim.state_modified(n0)
+            for _ in range(1, k):
+                sim.step(1)
+                ring.append(sim.states[f].clone())
+            for i in reversed(range(k)):
+                sim.adjoint_step(n0 + i, ring[i], lam, lam, flame=f)
+        grad = sim.synthesize(lam, flame=f)
+        return grad * grad_out.to(grad.dtype), None, None, None, None
+
+
+def flame_area(phi0, sim, nsteps, checkpoint_every=50, flame=0):
+    """Area excess J after nsteps from the physical initial field phi0 (float32,
+    n1 x n2, on the sim's device), differentiable with respect to phi0 through
+    the library's adjoint (states are checkpointed every `checkpoint_every`
+    steps and recomputed in the backward pass). The sim's state is overwritten."""
+    return _FlameArea.apply(phi0, sim, int(nsteps), int(checkpoint_every), int(flame))

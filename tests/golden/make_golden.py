@@ -3,7 +3,7 @@
 
 Calls only the oracle (and the seeded input generator for the initial
 conditions). For each workload and checkpoint step it stores: a fixed sample
-of spectral coefficients (all modes with |k1| <= 8, 0 <= k2 <= 16, plus 2048
+of spectral coefficients (all modes with |k1| <= 8, 0 <= k2 <= 16, plus 1024
 modes drawn with numpy.random.default_rng(7) from the canonical half array),
 the full weighted norm sum_k |Phi~_k|^2 over the box, and the oracle's
 diagnostics (mean radius, averaged velocity, area excess).
@@ -36,7 +36,7 @@ def sample_indices(shape):
             rows.append(a + k1max)
             cols.append(b)
     rng = np.random.default_rng(7)
-    flat = rng.choice(shape[0] * shape[1], size=2048, replace=False)
+    flat = rng.choice(shape[0] * shape[1], size=1024, replace=False)
     rows += list((flat // shape[1]).tolist())
     cols += list((flat % shape[1]).tolist())
     return np.array(rows), np.array(cols)
@@ -62,7 +62,8 @@ def main(names):
             wgt[:, 0] = 1.0
             r, v, a = oracle.diagnostics(cur, p, n)
             out["checkpoints"][str(c)] = {
-                "re": h[rows, cols].real.tolist(), "im": h[rows, cols].imag.tolist(),
+                "re": [float(f"{x:.12e}") for x in h[rows, cols].real],
+                "im": [float(f"{x:.12e}") for x in h[rows, cols].imag],
                 "norm_sq": float((wgt * np.abs(h) ** 2).sum()),
                 "mean_radius": r, "velocity": v, "area_excess": a,
             }

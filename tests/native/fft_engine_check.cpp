@@ -1,11 +1,13 @@
 // Host-side drive of the device FFT engine, thread by thread, for CPU tests.
 //
-// Reads "logn inv stride" then 2^logn complex64 values from stdin (binary),
+// Reads "logn inv stride outer" then 2^logn complex64 values from stdin (binary),
 // runs the Stockham passes of ff::Fft with every thread of one group emulated
 // in turn (all threads finish a pass before any gathers), and writes the
 // 2^logn transformed values to stdout. The LDS array is shared by `stride`
 // interleaved groups; this group uses slot offset stride - 1. Odd strides
 // take the twiddles from the register cache, even strides from the table.
+// With outer != 0 the middle half of the input is zeroed and the pruned first
+// pass is used.
 
 #include <cstdio>
 #include <vector>
@@ -18,29 +20,33 @@ struct Regs {
   float2 a[ff::kPts];
 };
 
-template <int LOGN, bool INV, int P>
+struct TableFetch {
+  const float2* tw;
+  float2 operator()(int i) const { return tw[i]; }
+};
+
+template <int LOGN, bool INV, int P, bool OUTER>
 void passes(std::vector<Regs>& v, float2* lds, int stride, const float2* tw, bool cached) {
   using S = ff::Shape<LOGN>;
   using F = ff::Fft<LOGN, INV>;
   if constexpr (P < S::NPASS) {
     for (int t = 0; t < S::G; ++t) {
       if (cached) {
-        ff::RegTw<LOGN> rt;
-        rt.load([tw](int i) { return tw[i]; }, t);
-        F::template butterflies<P>(v[t].a, t, lds, stride, rt);
+        ff::RegTw<LOGN, TableFetch> rt(TableFetch{tw}, t);
+        F::template butterflies<P, decltype(rt), OUTER>(v[t].a, t, lds, stride, rt);
       } else {
-        F::template butterflies<P>(v[t].a, t, lds, stride, ff::GlobalTw<LOGN>{tw, t});
+        F::template butterflies<P, ff::GlobalTw<LOGN>, OUTER>(v[t].a, t, lds, stride, ff::GlobalTw<LOGN>{tw, t});
       }
     }
     if constexpr (P + 1 < S::NPASS) {
       for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
     }
-    passes<LOGN, INV, P + 1>(v, lds, stride, tw, cached);
+    passes<LOGN, INV, P + 1, OUTER>(v, lds, stride, tw, cached);
   }
 }
 
 template <int LOGN, bool INV>
-void run(std::vector<float2>& x, int stride) {
+void run(std::vector<float2>& x, int stride, bool outer) {
   using S = ff::Shape<LOGN>;
   std::vector<float2> tw(S::plan.tw_size + 1);
   ff::build_twiddles(LOGN, tw.data());
@@ -49,21 +55,24 @@ void run(std::vector<float2>& x, int stride) {
     for (int i = 0; i < ff::kPts; ++i) v[t].a[i] = x[t + S::G * i];
   std::vector<float2> lds(size_t(S::LDS) * stride, make_float2(1e30f, 1e30f));
   // odd strides use the twiddles cached in registers, even strides the table
-  passes<LOGN, INV, 0>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  if (outer)
+    passes<LOGN, INV, 0, true>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  else
+    passes<LOGN, INV, 0, false>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
   for (int t = 0; t < S::G; ++t)
     for (int i = 0; i < ff::kPts; ++i) x[t + S::G * i] = v[t].a[i];
 }
 
 template <int LOGN>
-bool dispatch(int logn, int inv, std::vector<float2>& x, int stride) {
+bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer) {
   if constexpr (LOGN > 13) {
     return false;
   } else {
-    if (logn != LOGN) return dispatch<LOGN + 1>(logn, inv, x, stride);
+    if (logn != LOGN) return dispatch<LOGN + 1>(logn, inv, x, stride, outer);
     if (inv)
-      run<LOGN, true>(x, stride);
+      run<LOGN, true>(x, stride, outer);
     else
-      run<LOGN, false>(x, stride);
+      run<LOGN, false>(x, stride, outer);
     return true;
   }
 }
@@ -71,13 +80,15 @@ bool dispatch(int logn, int inv, std::vector<float2>& x, int stride) {
 }  // namespace
 
 int main() {
-  int hdr[3];
-  if (fread(hdr, sizeof(int), 3, stdin) != 3) return 2;
-  const int logn = hdr[0], inv = hdr[1], stride = hdr[2];
+  int hdr[4];
+  if (fread(hdr, sizeof(int), 4, stdin) != 4) return 2;
+  const int logn = hdr[0], inv = hdr[1], stride = hdr[2], outer = hdr[3];
   if (logn < 4 || logn > 13 || stride < 1) return 3;
   std::vector<float2> x(size_t(1) << logn);
   if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
-  if (!dispatch<4>(logn, inv, x, stride)) return 5;
+  if (outer)  // the pruned first pass assumes the middle half of the input is zero
+    for (size_t i = x.size() / 4; i < 3 * x.size() / 4; ++i) x[i] = make_float2(0.f, 0.f);
+  if (!dispatch<4>(logn, inv, x, stride, outer != 0)) return 5;
   fwrite(x.data(), sizeof(float2), x.size(), stdout);
   return 0;
 }
