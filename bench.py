@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
-                  "paper_0911_2889_amd/csrc/flame_dev.hpp")
+                  "paper_0911_2889_amd/csrc/flame_dev.hpp", "paper_0911_2889_amd/csrc/kernel_common.hpp")
 
 
 def algorithmic_bytes(n1, n2):
@@ -85,6 +85,79 @@ def cpu_oracle_baseline(w, half, seconds):
     }, steps, oracle.full_to_half(cur, w.n1, w.n2)
 
 
+def adjoint_leg(steps, every, reps=2):
+    """Checkpointed gradient of the area excess on the adjoint workload: HIP-event
+    time of the forward pass (projection, steps, diagnostics) and of the backward
+    pass (seed, segment recomputation, adjoint steps, synthesis)."""
+    import torch
+
+    import synth
+    from paper_0911_2889_amd import FlameSim, flame_area
+
+    w = synth.WORKLOADS["adjoint1024x2048"]
+    sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
+    sim.set_spectrum(synth.workload_spectrum(w))
+    phi0 = sim.phi().clone()
+    fwd, bwd = [], []
+    for r in range(reps + 1):
+        x = phi0.clone().requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record()
+        J = flame_area(x, sim, steps, checkpoint_every=every)
+        e1.record()
+        J.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        if r:  # the first repetition warms up
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(e1.elapsed_time(e2))
+    f, b = min(fwd), min(bwd)
+    return {
+        "workload": w.name, "grid": [w.n1, w.n2], "steps": steps, "checkpoint_every": every,
+        "forward_ms": f, "backward_ms": b, "backward_over_forward": b / f,
+        "adjoint_point_steps_per_s": w.points * steps / (b * 1e-3),
+        "forward_point_steps_per_s": w.points * steps / (f * 1e-3),
+        "J": J.item(),
+    }
+
+
+def ensemble_leg(steps, graph_steps):
+    """The batched ensemble (256 flames of three grids) stepped in graphs of
+    graph_steps steps, and with direct launches, timed with HIP events."""
+    import torch
+
+    import synth
+    from paper_0911_2889_amd import FlameEnsemble
+
+    members = synth.ensemble_members()
+    descs = [dict(n1=w.n1, n2=w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt) for w in members]
+    ens = FlameEnsemble(descs)
+    halves = [synth.workload_spectrum(w) for w in members]
+    points = sum(w.points for w in members)
+    nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2).values()) for w in members)
+    out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
+           "points": points, "step_bytes": nbytes}
+    for mode, gs in (("graph", graph_steps), ("direct", 0)):
+        ens.set_graph_steps(gs)
+        for f, h in enumerate(halves):
+            ens.set_spectrum(h, flame=f)
+        ens.step(gs if gs else 10)  # warm-up (builds the graph)
+        for f, h in enumerate(halves):
+            ens.set_spectrum(h, flame=f)
+        ens.step(0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ens.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[mode] = {"ms_per_step": ms / steps, "point_steps_per_s": points * steps / (ms * 1e-3),
+                     "step_hbm_frac": nbytes / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +167,10 @@ def main():
     ap.add_argument("--diag-every", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--ensemble-steps", type=int, default=200,
+                    help="steps of the 256-flame ensemble leg (0 skips it)")
+    ap.add_argument("--adjoint-steps", type=int, default=100,
+                    help="steps of the checkpointed adjoint leg on 1024x2048 (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -171,7 +248,7 @@ def main():
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, w.name)
     result = {
-        "metric": "flame point-steps/s (forward step, FP32 vs FP64 oracle at 1e-5; % HBM roofline)",
+        "metric": "flame point-steps/s fwd & adjoint, FP32 vs FP64 oracle at 1e-5; % HBM roofline",
         "value": w.points * args.steps / (ms * 1e-3),
         "unit": "point-steps/s",
         "n_gpus": 1,
@@ -201,6 +278,11 @@ def main():
         "step_hbm_frac": (nbytes["row"] + nbytes["col"]) / (ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "diagnostics_at_first_checkpoint": final_diag,
     }
+
+    if args.adjoint_steps > 0:
+        result["adjoint"] = adjoint_leg(args.adjoint_steps, 50)
+    if args.ensemble_steps > 0:
+        result["ensemble"] = ensemble_leg(args.ensemble_steps, 50)
 
     if not args.no_cpu:
         base, nref, ref = cpu_oracle_baseline(w, half, args.cpu_seconds)

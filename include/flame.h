@@ -156,11 +156,22 @@ int flame_synthesize(flame_plan plan, int32_t flame, const void* spec, float* ph
  * launch). */
 int flame_timing_begin(flame_plan plan);
 
-/* Stop timing, synchronise the plan's stream and report the summed kernel
- * durations in milliseconds and the launch counts, per kind:
- * [0] row kernels, [1] column kernels, [2] diagnostics kernels.
- * ms3 and counts3 are host arrays of 3 entries. */
-int flame_timing_end(flame_plan plan, double* ms3, int64_t* counts3);
+/* Stop timing, synchronise the plan's stream and report the summed
+ * durations in milliseconds and the counts, per kind: [0] row kernels,
+ * [1] column kernels, [2] diagnostics kernels, [3] graph launches (each
+ * covering steps_per_graph steps). Consecutive launches share their boundary
+ * event, so each interval includes the launch gap before the next one.
+ * ms4 and counts4 are host arrays of 4 entries. */
+int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
+
+/* Run flame_step in graphs of `steps` steps (0: direct launches, the default).
+ * The graph holds, for every group of flames with equal grids, the chain
+ * row kernel -> column kernel for each step; chains of different groups have
+ * no edges between them, so a mixed ensemble runs its groups concurrently.
+ * flame_step(n) launches floor(n / steps) graphs and the remainder directly.
+ * The graph is built on first use and replayed; the step index is read from
+ * the workspace, set by a one-thread kernel before each replay. */
+int flame_set_graph_steps(flame_plan plan, int32_t steps);
 
 /* Release the plan's host metadata (device buffers stay the caller's). */
 int flame_destroy(flame_plan plan);

@@ -64,19 +64,33 @@ def step_adjoint(state_n, lam_next, p, n):
     return (mu - 2.0 * p.dt * c * _div(m * g1, m * g2, p)) * box_mask(p.n1, p.n2)
 
 
-def trajectory_gradient(full0, p, nsteps, n_start=0):
+def trajectory_gradient(full0, p, nsteps, n_start=0, checkpoint_every=None):
     """(J(Phi^T), coefficients of dJ/dPhi^0) for nsteps steps from full0.
 
-    Stores the whole trajectory (the oracle runs small grids); the grid-value
-    gradient with respect to a physical initial field that is first projected
-    onto the box is the synthesis of the returned coefficients.
+    Without checkpoint_every the whole trajectory is stored; with it only every
+    checkpoint_every-th state is kept and each segment is recomputed from its
+    checkpoint before its adjoint steps (the same states, so the same result).
+    The grid-value gradient with respect to a physical initial field that is
+    first projected onto the box is the synthesis of the returned coefficients.
     """
-    states = [run(full0, p, 0, n_start)]
-    for i in range(nsteps):
-        states.append(step(states[-1], p, n_start + i))
+    every = nsteps if not checkpoint_every else int(checkpoint_every)
+    checkpoints = []
+    cur = run(full0, p, 0, n_start)
+    n = 0
+    while n < nsteps:
+        checkpoints.append((n, cur))
+        k = min(every, nsteps - n)
+        for i in range(k):
+            cur = step(cur, p, n_start + n + i)
+        n += k
     n_end = n_start + nsteps
-    value = area_excess(states[-1], p, n_end)
-    lam = area_gradient(states[-1], p, n_end)
-    for i in reversed(range(nsteps)):
-        lam = step_adjoint(states[i], lam, p, n_start + i)
+    value = area_excess(cur, p, n_end)
+    lam = area_gradient(cur, p, n_end)
+    for n0, saved in reversed(checkpoints):
+        k = min(every, nsteps - n0)
+        states = [saved]
+        for i in range(1, k):
+            states.append(step(states[-1], p, n_start + n0 + i - 1))
+        for i in reversed(range(k)):
+            lam = step_adjoint(states[i], lam, p, n_start + n0 + i)
     return value, lam

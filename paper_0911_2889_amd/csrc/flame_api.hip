@@ -89,6 +89,7 @@ struct Layout {
   std::vector<size_t> off_wp, off_wm, off_q, off_a1, off_a2, off_part;
   size_t off_tw[flame::kMaxLog + 1];
   size_t off_dev;
+  size_t off_counter;  // step index read by graph replays
   size_t total;
 };
 
@@ -126,6 +127,8 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   }
   L->off_dev = off;
   off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
+  L->off_counter = off;
+  off = align_up(off + sizeof(long long));
   L->total = off;
   return FLAME_OK;
 }
@@ -168,8 +171,15 @@ struct flame_plan_s {
   bool timing = false;
   hipEvent_t chain = nullptr;  // last event of the current chain of timed launches
   std::vector<hipEvent_t> ev_pool;
-  std::vector<hipEvent_t> ev_used[3];
+  std::vector<hipEvent_t> ev_used[4];
+  // graph of graph_steps steps (one kernel chain per grid-size group)
+  int graph_steps = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  long long* counter = nullptr;
   ~flame_plan_s() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
     std::vector<hipEvent_t> all(ev_pool);
     for (auto& v : ev_used) all.insert(all.end(), v.begin(), v.end());
     std::sort(all.begin(), all.end());
@@ -192,7 +202,7 @@ int last_launch(const char* what) {
   return FLAME_OK;
 }
 
-enum TimedKind { KIND_ROW = 0, KIND_COL = 1, KIND_OTHER = 2 };
+enum TimedKind { KIND_ROW = 0, KIND_COL = 1, KIND_OTHER = 2, KIND_GRAPH = 3 };
 
 hipEvent_t take_event(flame_plan p) {
   if (!p->ev_pool.empty()) {
@@ -245,6 +255,61 @@ int rebuild_w(flame_plan p, int flame) {
   }
   p->w_valid[flame] = 1;
   return last_launch("column transform launch");
+}
+
+void drop_graph(flame_plan p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+}
+
+// graph_steps steps of every flame: for each grid-size group a chain
+// row(0) -> col(0) -> row(1) -> ... ; chains of different groups carry no
+// edges between them, so the groups run concurrently. Kernels read the step
+// index as counter + s.
+int build_graph(flame_plan p) {
+  drop_graph(p);
+  hipError_t e = hipGraphCreate(&p->graph, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+  std::vector<hipGraphNode_t> last(p->groups.size(), nullptr);
+  for (int s = 0; s < p->graph_steps; ++s) {
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+      const Group& gr = p->groups[gi];
+      const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2), ck = flame::col_step_kernel(gr.logn1);
+      if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
+      const flame::FlameDev* fl = p->ddev + gr.first;
+      long long n = s;
+      const long long* nb = p->counter;
+      const float* in = nullptr;
+      float* outp = nullptr;
+      const float2* src = nullptr;
+      void* rargs[] = {&fl, &n, &nb, &in, &outp};
+      void* cargs[] = {&fl, &n, &nb, &src};
+      hipKernelNodeParams rp{};
+      rp.func = const_cast<void*>(rk.func);
+      rp.gridDim = dim3(gr.rgroups, gr.count);
+      rp.blockDim = dim3(rk.threads);
+      rp.sharedMemBytes = rk.lds;
+      rp.kernelParams = rargs;
+      hipGraphNode_t rn;
+      e = hipGraphAddKernelNode(&rn, p->graph, last[gi] ? &last[gi] : nullptr, last[gi] ? 1 : 0, &rp);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (row)");
+      hipKernelNodeParams cp{};
+      cp.func = const_cast<void*>(ck.func);
+      cp.gridDim = dim3(gr.tiles, gr.count);
+      cp.blockDim = dim3(ck.threads);
+      cp.sharedMemBytes = ck.lds;
+      cp.kernelParams = cargs;
+      hipGraphNode_t cn;
+      e = hipGraphAddKernelNode(&cn, p->graph, &rn, 1, &cp);
+      if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (col)");
+      last[gi] = cn;
+    }
+  }
+  e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return FLAME_OK;
 }
 
 }  // namespace
@@ -364,6 +429,7 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     }
   }
   p->ddev = reinterpret_cast<flame::FlameDev*>(base + L.off_dev);
+  p->counter = reinterpret_cast<long long*>(base + L.off_counter);
   e = hipMemcpyAsync(p->ddev, p->hdev.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) {
     delete p;
@@ -453,6 +519,23 @@ int flame_step(flame_plan p, int32_t nsteps) {
       rc = rebuild_w(p, f);
       if (rc) return rc;
     }
+  if (p->graph_steps > 0 && nsteps >= p->graph_steps) {
+    if (!p->graph_exec) {
+      rc = build_graph(p);
+      if (rc) return rc;
+    }
+    while (nsteps >= p->graph_steps) {
+      flame::launch_set_step(p->stream, p->counter, p->n);
+      {
+        Timed tm(p, KIND_GRAPH);
+        const hipError_t e = hipGraphLaunch(p->graph_exec, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      }
+      p->n += p->graph_steps;
+      nsteps -= p->graph_steps;
+      break_chain(p);
+    }
+  }
   for (int s = 0; s < nsteps; ++s) {
     for (const Group& gr : p->groups) {
       Timed tm(p, KIND_ROW);
@@ -548,15 +631,27 @@ int flame_timing_begin(flame_plan p) {
   return FLAME_OK;
 }
 
-int flame_timing_end(flame_plan p, double* ms3, int64_t* counts3) {
+int flame_set_graph_steps(flame_plan p, int32_t steps) {
   int rc = check_plan(p);
   if (rc) return rc;
-  if (!ms3 || !counts3) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  if (steps < 0) return fail(FLAME_ERR_INVALID_ARG, "steps per graph must be >= 0");
+  if (steps != p->graph_steps) {
+    DeviceGuard g(p->device);
+    drop_graph(p);
+    p->graph_steps = steps;
+  }
+  return FLAME_OK;
+}
+
+int flame_timing_end(flame_plan p, double* ms4, int64_t* counts4) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!ms4 || !counts4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
   DeviceGuard g(p->device);
   p->timing = false;
   hipError_t e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return hip_fail(e, "timing synchronise");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < 4; ++k) {
     double total = 0.0;
     const auto& v = p->ev_used[k];
     for (size_t i = 0; i + 1 < v.size(); i += 2) {
@@ -565,8 +660,8 @@ int flame_timing_end(flame_plan p, double* ms3, int64_t* counts3) {
       if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
       total += ms;
     }
-    ms3[k] = total;
-    counts3[k] = (int64_t)(v.size() / 2);
+    ms4[k] = total;
+    counts4[k] = (int64_t)(v.size() / 2);
   }
   return FLAME_OK;
 }

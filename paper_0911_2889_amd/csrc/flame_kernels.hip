@@ -30,7 +30,8 @@ namespace flame {
 
 template <int LOGN1, int MODE>
 __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
-    col_kernel(const FlameDev* __restrict__ fls, long long n, const float2* src) {
+    col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  if (nbase) n += *nbase;  // graph replays read the step index from device memory
   using S = ff::Shape<LOGN1>;
   constexpr int G = S::G, T = ColCfg<LOGN1>::T, N1 = S::N;
   extern __shared__ float2 lds[];
@@ -170,8 +171,9 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
 
 template <int LOGN2, int MODE>
 __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_waves_per_eu(ROW_WAVES_PER_EU)))
-    row_kernel(const FlameDev* __restrict__ fls, long long n, const float* __restrict__ phys_in,
-               float* __restrict__ phys_out) {
+    row_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase,
+               const float* __restrict__ phys_in, float* __restrict__ phys_out) {
+  if (nbase) n += *nbase;
   using S = ff::Shape<LOGN2>;
   constexpr int G = S::G, B = RowCfg<LOGN2>::B, N2 = S::N;
   extern __shared__ float2 lds[];
@@ -420,14 +422,21 @@ template <int LOGN>
 struct ColTable {
   static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n, const float2* src) {
     constexpr int th = ColCfg<LOGN>::THREADS, lds = ColCfg<LOGN>::LDS_BYTES;
+    const long long* nb = nullptr;
     switch (mode) {
-      case COL_STEP: hipLaunchKernelGGL((col_kernel<LOGN, COL_STEP>), grid, dim3(th), lds, st, fl, n, src); break;
-      case COL_FIRST: hipLaunchKernelGGL((col_kernel<LOGN, COL_FIRST>), grid, dim3(th), lds, st, fl, n, src); break;
-      case COL_PROJECT:
-        hipLaunchKernelGGL((col_kernel<LOGN, COL_PROJECT>), grid, dim3(th), lds, st, fl, n, src);
+      case COL_STEP: hipLaunchKernelGGL((col_kernel<LOGN, COL_STEP>), grid, dim3(th), lds, st, fl, n, nb, src); break;
+      case COL_FIRST:
+        hipLaunchKernelGGL((col_kernel<LOGN, COL_FIRST>), grid, dim3(th), lds, st, fl, n, nb, src);
         break;
-      default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, src); break;
+      case COL_PROJECT:
+        hipLaunchKernelGGL((col_kernel<LOGN, COL_PROJECT>), grid, dim3(th), lds, st, fl, n, nb, src);
+        break;
+      default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, nb, src); break;
     }
+  }
+  static KernelLaunch step_kernel() {
+    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP>), ColCfg<LOGN>::THREADS,
+                        ColCfg<LOGN>::LDS_BYTES};
   }
 };
 
@@ -436,12 +445,23 @@ struct RowTable {
   static void launch(int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n, const float* in,
                      float* out) {
     constexpr int th = RowCfg<LOGN>::THREADS, lds = RowCfg<LOGN>::LDS_BYTES;
+    const long long* nb = nullptr;
     switch (mode) {
-      case ROW_STEP: hipLaunchKernelGGL((row_kernel<LOGN, ROW_STEP>), grid, dim3(th), lds, st, fl, n, in, out); break;
-      case ROW_FORWARD: hipLaunchKernelGGL((row_kernel<LOGN, ROW_FORWARD>), grid, dim3(th), lds, st, fl, n, in, out); break;
-      case ROW_SYNTH: hipLaunchKernelGGL((row_kernel<LOGN, ROW_SYNTH>), grid, dim3(th), lds, st, fl, n, in, out); break;
-      default: hipLaunchKernelGGL((row_kernel<LOGN, ROW_DIAG>), grid, dim3(th), lds, st, fl, n, in, out); break;
+      case ROW_STEP:
+        hipLaunchKernelGGL((row_kernel<LOGN, ROW_STEP>), grid, dim3(th), lds, st, fl, n, nb, in, out);
+        break;
+      case ROW_FORWARD:
+        hipLaunchKernelGGL((row_kernel<LOGN, ROW_FORWARD>), grid, dim3(th), lds, st, fl, n, nb, in, out);
+        break;
+      case ROW_SYNTH:
+        hipLaunchKernelGGL((row_kernel<LOGN, ROW_SYNTH>), grid, dim3(th), lds, st, fl, n, nb, in, out);
+        break;
+      default: hipLaunchKernelGGL((row_kernel<LOGN, ROW_DIAG>), grid, dim3(th), lds, st, fl, n, nb, in, out); break;
     }
+  }
+  static KernelLaunch step_kernel() {
+    return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP>), RowCfg<LOGN>::THREADS,
+                        RowCfg<LOGN>::LDS_BYTES};
   }
 };
 
@@ -455,6 +475,16 @@ void dispatch_log(int logn, A... args) {
   }
 }
 
+template <template <int> class Tab, int L>
+void dispatch_info(int logn, KernelLaunch* out) {
+  if constexpr (L <= kMaxLog) {
+    if (logn == L)
+      *out = Tab<L>::step_kernel();
+    else
+      dispatch_info<Tab, L + 1>(logn, out);
+  }
+}
+
 }  // namespace
 
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
@@ -465,6 +495,30 @@ void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const F
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                 const float* in, float* out) {
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
+}
+
+KernelLaunch col_step_kernel(int logn1) {
+  KernelLaunch out{nullptr, 0, 0};
+  dispatch_info<ColTable, kMinLog>(logn1, &out);
+  return out;
+}
+
+KernelLaunch row_step_kernel(int logn2) {
+  KernelLaunch out{nullptr, 0, 0};
+  dispatch_info<RowTable, kMinLog>(logn2, &out);
+  return out;
+}
+
+// One thread stores the step index that graph replays read (a vector store).
+__global__ void set_step_kernel(long long* __restrict__ counter, long long value) {
+  if (threadIdx.x == 0) {
+    volatile long long* p = counter;
+    *p = value;
+  }
+}
+
+void launch_set_step(hipStream_t st, long long* counter, long long value) {
+  hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, counter, value);
 }
 
 void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half) {

@@ -8,6 +8,18 @@
 
 namespace flame {
 
+// A kernel function and its launch shape, for graph nodes.
+struct KernelLaunch {
+  const void* func;
+  int threads;
+  int lds;
+};
+
+// The step kernels for a transform length (arguments: fls, n, nbase, src / in, out).
+KernelLaunch col_step_kernel(int logn1);
+KernelLaunch row_step_kernel(int logn2);
+void launch_set_step(hipStream_t st, long long* counter, long long value);
+
 // Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
 // (fl points at their consecutive FlameDev entries in device memory). src,
 // if not null, replaces the state read by COL_FIRST and COL_SYNTH.

@@ -143,15 +143,19 @@ class FlameEnsemble:
                                                ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_graph_steps(self, steps):
+        """Step in hipGraphs of `steps` steps (0: direct launches)."""
+        native.check(self.lib.flame_set_graph_steps(self.plan, int(steps)))
+
     def timing_begin(self):
         native.check(self.lib.flame_timing_begin(self.plan))
 
     def timing_end(self):
-        """Summed kernel milliseconds and launch counts: row, column, diagnostics."""
-        ms = (ctypes.c_double * 3)()
-        cnt = (ctypes.c_int64 * 3)()
+        """Summed milliseconds and counts: row, column, diagnostics kernels, graph launches."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
         native.check(self.lib.flame_timing_end(self.plan, ms, cnt))
-        keys = ("row", "col", "diag")
+        keys = ("row", "col", "diag", "graph")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(keys)}
 
     def close(self):
