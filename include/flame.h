@@ -164,6 +164,23 @@ int flame_timing_begin(flame_plan plan);
  * ms4 and counts4 are host arrays of 4 entries. */
 int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
 
+/* Points per thread of the step kernels for the flames of grid n1 x n2: each
+ * length-N transform is owned by N/pts threads holding pts points, with
+ * radix-pts passes (col_pts for the column kernel, row_pts for the row
+ * kernel; 8 or 16, default 16). Results agree to rounding, not bit for bit;
+ * the choice trades registers per thread for waves per transform. */
+int flame_set_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t col_pts, int32_t row_pts);
+int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t* col_pts, int32_t* row_pts);
+
+/* Choose the points per thread of each grid group's step kernels by timing:
+ * for every group of equal grids, each (col_pts, row_pts) in {16, 8}^2 runs
+ * one untimed and `steps` timed steps of that group (HIP events on the plan's
+ * stream) and the fastest is kept. The states and the step index are saved
+ * in the workspace and restored afterwards, so the call does not change the
+ * simulation; it synchronises the stream. *n_configs_tried (nullable)
+ * receives the number of timed configurations. */
+int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
+
 /* Run flame_step in graphs of `steps` steps (0: direct launches, the default).
  * The graph holds, for every group of flames with equal grids, the chain
  * row kernel -> column kernel for each step; chains of different groups have

@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   if constexpr (MODE != SEED_C) {
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
+      const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       lam[kk] = live ? ld(glob(const_cast<float2*>(lam_in)) + col + k1) : make_float2(0.f, 0.f);
     }
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     float2 sv[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
+      const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       sv[kk] = live ? ld(glob(const_cast<float2*>(state)) + col + k1) : make_float2(0.f, 0.f);
     }
@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
+      const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       v[i] = ff::cscale(lam[kk], efactor(f, sc, k1, kap2));
     }
@@ -105,15 +105,16 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
-        const int i = kept_reg(kk);
+        const int i = kept_reg<ff::kPts>(kk);
         const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
         v[i] = make_float2(-kap1 * sv[kk].y + sgn * kap2 * sv[kk].x, kap1 * sv[kk].x + sgn * kap2 * sv[kk].y);
       }
       fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
       if (live) {
-        gf2* dst = glob(pass == 0 ? f.Wp : f.Wm) + tile_base;
+        gf2* dst = glob(pass == 0 ? f.Wp : f.Wm);
 #pragma unroll
-        for (int i = 0; i < ff::kPts; ++i) st(dst + (t + G * i) * T, pass == 0 ? v[i] : ff::cconj(v[i]));
+        for (int i = 0; i < ff::kPts; ++i)
+          st(dst + pair_major(t + G * i, m, f.m), pass == 0 ? v[i] : ff::cconj(v[i]));
       }
     }
   } else {
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       for (int i = 0; i < ff::kPts; ++i) v[i] = live ? ld(srcp + (t + G * i) * T) : make_float2(0.f, 0.f);
       fft<LOGN1, false>(v, t, my, T, tw1);
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg(kk)];
+      for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg<ff::kPts>(kk)];
     }
     float2 out[8];
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
@@ -134,7 +135,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     if constexpr (MODE == ADJ_C) sc = step_scalars(f, n);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
+      const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       const float kap1 = f.s1 * (float)k1;
       // raw divergence i kappa1 U1 + V2 (sums without the 1/P factors)
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       if (c == 0) {
 #pragma unroll
         for (int kk = 4; kk < 8; ++kk) {
-          const int k1 = t + G * kept_reg(kk) - N1;
+          const int k1 = t + G * kept_reg<ff::kPts>(kk) - N1;
           if (k1 > -N1 / 4) out[kk] = ff::cconj(lds[-k1]);
         }
         if (t == 0) out[0].y = 0.f;
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     if (live) {
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
-        const int i = kept_reg(kk);
+        const int i = kept_reg<ff::kPts>(kk);
         const int k1 = t + G * i - (i >= 12 ? N1 : 0);
         st(glob(lam_out) + col + k1, out[kk]);
       }
@@ -241,10 +242,10 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
       float2 val = make_float2(0.f, 0.f);
       if (live) {
         if (i < 4) {
-          val = ld(Wp + tiled(row, idx, n1, ts));
+          val = ld(Wp + pair_major(row, idx, mcols));
         } else if (i >= 12) {
           const int mm = N2 - idx;
-          if (mm < mcols) val = ld(Wm + tiled(row, mm, n1, ts));
+          if (mm < mcols) val = ld(Wm + pair_major(row, mm, mcols));
         }
       }
       v[i] = val;

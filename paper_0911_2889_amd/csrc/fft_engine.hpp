@@ -1,9 +1,10 @@
 // Register/LDS Stockham FFT engine for gfx950 (wave64).
 //
 // One length-N transform (N = 2^LOGN, 16 <= N <= 8192) is owned by a group
-// of G = N/16 threads. Thread t holds the 16 points x[t + G*i], i = 0..15,
-// in registers. A pass of radix R (16, or the 2/4/8 remainder in the last
-// pass) lets each thread run 16/R butterflies on its own registers; between
+// of G = N/PTS threads (PTS = 16 or 8 points per thread). Thread t holds the
+// points x[t + G*i], i = 0..PTS-1, in registers. A pass of radix R (PTS, or
+// the smaller power-of-two remainder in the last pass) lets each thread run
+// PTS/R butterflies on its own registers; between
 // passes the group exchanges data through LDS (Stockham autosort ordering,
 // so input and output both come out in natural order with the same
 // "t + G*i" register map). Global loads and stores therefore stay coalesced:
@@ -31,32 +32,36 @@
 
 namespace ff {
 
-constexpr int kPts = 16;  // points per thread
+constexpr int kPts = 16;  // default points per thread
 
 struct PassPlan {
   int logn, n, g, npass;
-  int radix[4];
-  int ns[4];
-  int tw_off[4];
+  int radix[5];
+  int ns[5];
+  int tw_off[5];
   int tw_size;
 };
 
-constexpr PassPlan make_pass_plan(int logn) {
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// Radix-PTS passes, the remainder radix last.
+constexpr PassPlan make_pass_plan(int logn, int pts = kPts) {
   PassPlan p{};
+  const int lp = ilog2c(pts);
   p.logn = logn;
   p.n = 1 << logn;
-  p.g = p.n / kPts;
-  const int full = logn / 4, rem = logn % 4;
+  p.g = p.n / pts;
+  const int full = logn / lp, rem = logn % lp;
   p.npass = full + (rem ? 1 : 0);
   int ns = 1, off = 0;
   for (int q = 0; q < p.npass; ++q) {
-    p.radix[q] = q < full ? 16 : (1 << rem);
+    p.radix[q] = q < full ? pts : (1 << rem);
     p.ns[q] = ns;
     p.tw_off[q] = off;
     if (q > 0) off += ns * (p.radix[q] - 1);
     ns *= p.radix[q];
   }
-  for (int q = p.npass; q < 4; ++q) {
+  for (int q = p.npass; q < 5; ++q) {
     p.radix[q] = 1;
     p.ns[q] = ns;
     p.tw_off[q] = off;
@@ -67,17 +72,18 @@ constexpr PassPlan make_pass_plan(int logn) {
 
 __host__ __device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
 
-template <int LOGN>
+template <int LOGN, int PTS = kPts>
 struct Shape {
-  static constexpr PassPlan plan = make_pass_plan(LOGN);
+  static constexpr PassPlan plan = make_pass_plan(LOGN, PTS);
   static constexpr int N = 1 << LOGN;
-  static constexpr int G = N / kPts;
+  static constexpr int G = N / PTS;
   static constexpr int NPASS = plan.npass;
   static constexpr int LDS = N + N / 16;  // padded slots per transform
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
   static_assert(LOGN >= 4 && LOGN <= 13, "transform length must be 16..8192");
+  static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
 
 // ---------------------------------------------------------------- complex
@@ -226,6 +232,26 @@ __host__ __device__ __forceinline__ void dft16_outer(float2* x) {
   }
 }
 
+// dft8 for inputs x[2..5] == 0.
+template <bool INV>
+__host__ __device__ __forceinline__ void dft8_outer(float2* x) {
+  // even part: length-4 transform of (x0, 0, 0, x6); odd part of (x1, 0, 0, x7)
+  const float2 qe = mul_q<INV>(x[6]), qo = mul_q<INV>(x[7]);
+  const float2 e0 = cadd(x[0], x[6]), e1 = csub(x[0], qe), e2 = csub(x[0], x[6]), e3 = cadd(x[0], qe);
+  float2 o0 = cadd(x[1], x[7]), o1 = csub(x[1], qo), o2 = csub(x[1], x[7]), o3 = cadd(x[1], qo);
+  o1 = mul_e1<INV>(o1);
+  o2 = mul_q<INV>(o2);
+  o3 = mul_e3<INV>(o3);
+  x[0] = cadd(e0, o0);
+  x[4] = csub(e0, o0);
+  x[1] = cadd(e1, o1);
+  x[5] = csub(e1, o1);
+  x[2] = cadd(e2, o2);
+  x[6] = csub(e2, o2);
+  x[3] = cadd(e3, o3);
+  x[7] = csub(e3, o3);
+}
+
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2* x) {
   if constexpr (R == 2) {
@@ -243,9 +269,9 @@ __host__ __device__ __forceinline__ void dft(float2* x) {
 // ------------------------------------------------------------ Stockham passes
 
 // Twiddle source reading the table in global memory on every use.
-template <int LOGN>
+template <int LOGN, int PTS = kPts>
 struct GlobalTw {
-  using S = Shape<LOGN>;
+  using S = Shape<LOGN, PTS>;
   const float2* tw;
   int t;
   template <int P>
@@ -261,11 +287,11 @@ struct GlobalTw {
 // with Ns <= 16 has at most 16 distinct twiddles per radix index, one cache
 // line per wave). Loaded once and reused by every transform of one length in
 // a kernel. `fetch(i)` returns table entry i.
-template <int LOGN, class F, int MIN_NS = 2>
+template <int LOGN, class F, int MIN_NS = 2, int PTS = kPts>
 struct RegTw {
-  using S = Shape<LOGN>;
+  using S = Shape<LOGN, PTS>;
   static constexpr bool cached(int p) { return p > 0 && p < S::NPASS && S::ns(p) >= MIN_NS; }
-  static constexpr int per_pass(int p) { return cached(p) ? kPts - kPts / S::radix(p) : 0; }
+  static constexpr int per_pass(int p) { return cached(p) ? PTS - PTS / S::radix(p) : 0; }
   static constexpr int offset(int p) {
     int o = 0;
     for (int q = 1; q < p; ++q) o += per_pass(q);
@@ -282,7 +308,7 @@ struct RegTw {
   __host__ __device__ __forceinline__ void load_pass() {
     if constexpr (P < S::NPASS) {
       if constexpr (cached(P)) {
-        constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
+        constexpr int R = S::radix(P), NS = S::ns(P), NB = PTS / R;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int k = (t + b * S::G) & (NS - 1);
@@ -305,21 +331,22 @@ struct RegTw {
   }
 };
 
-template <int LOGN, bool INV>
+template <int LOGN, bool INV, int PTS = kPts>
 struct Fft {
-  using S = Shape<LOGN>;
+  using S = Shape<LOGN, PTS>;
 
-  // Pass P: thread t runs 16/R butterflies on its registers. Butterfly b has
-  // global index j = t + b*G and inputs x[j + r*N/R] = v[b + r*16/R]; it
+  // Pass P: thread t runs PTS/R butterflies on its registers. Butterfly b has
+  // global index j = t + b*G and inputs x[j + r*N/R] = v[b + r*PTS/R]; it
   // applies the twiddles w(j mod Ns, r), the radix-R DFT, and sends output r
   // to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns: into LDS, or, in the
   // last pass (Ns * R = N), back into the same registers.
-  // OUTER: the caller guarantees v[4..11] == 0 on entry to pass 0 (inputs
-  // confined to the first and last quarter), which prunes the first butterfly.
+  // OUTER: the caller guarantees v[PTS/4 .. 3PTS/4 - 1] == 0 on entry to
+  // pass 0 (inputs confined to the first and last quarter), which prunes the
+  // first butterfly.
   template <int P, class TW, bool OUTER = false>
-  static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[kPts], int t, float2* lds, int stride,
+  static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[PTS], int t, float2* lds, int stride,
                                                               const TW& tw) {
-    constexpr int R = S::radix(P), NS = S::ns(P), NB = kPts / R;
+    constexpr int R = S::radix(P), NS = S::ns(P), NB = PTS / R;
     constexpr bool LAST = (P + 1 == S::NPASS);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -336,8 +363,10 @@ struct Fft {
           x[r] = cmul(x[r], wr);
         }
       }
-      if constexpr (OUTER && P == 0 && R == 16) {
+      if constexpr (OUTER && P == 0 && R == 16 && PTS == 16) {
         dft16_outer<INV>(x);
+      } else if constexpr (OUTER && P == 0 && R == 8 && PTS == 8) {
+        dft8_outer<INV>(x);
       } else {
         dft<R, INV>(x);
       }
@@ -352,20 +381,21 @@ struct Fft {
     }
   }
 
-  static __host__ __device__ __forceinline__ void gather(float2 (&v)[kPts], int t, const float2* lds, int stride) {
+  static __host__ __device__ __forceinline__ void gather(float2 (&v)[PTS], int t, const float2* lds, int stride) {
 #pragma unroll
-    for (int i = 0; i < kPts; ++i) v[i] = lds[lds_pad(t + S::G * i) * stride];
+    for (int i = 0; i < PTS; ++i) v[i] = lds[lds_pad(t + S::G * i) * stride];
   }
 
-  static __host__ __device__ __forceinline__ void scatter(const float2 (&v)[kPts], int t, float2* lds, int stride) {
+  static __host__ __device__ __forceinline__ void scatter(const float2 (&v)[PTS], int t, float2* lds, int stride) {
 #pragma unroll
-    for (int i = 0; i < kPts; ++i) lds[lds_pad(t + S::G * i) * stride] = v[i];
+    for (int i = 0; i < PTS; ++i) lds[lds_pad(t + S::G * i) * stride] = v[i];
   }
 };
 
-// Host: fill the twiddle table of a length 2^logn transform (tw_size entries).
-inline void build_twiddles(int logn, float2* out) {
-  const PassPlan p = make_pass_plan(logn);
+// Host: fill the twiddle table of a length 2^logn transform with pts points
+// per thread (tw_size entries of that pass plan).
+inline void build_twiddles(int logn, float2* out, int pts = kPts) {
+  const PassPlan p = make_pass_plan(logn, pts);
   for (int q = 1; q < p.npass; ++q) {
     const int ns = p.ns[q], r = p.radix[q];
     const double span = double(ns) * double(r);

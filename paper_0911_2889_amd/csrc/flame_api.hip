@@ -87,7 +87,8 @@ int check_desc(const flame_desc* d, Sizes* s) {
 struct Layout {
   std::vector<Sizes> sizes;
   std::vector<size_t> off_wp, off_wm, off_q, off_a1, off_a2, off_part;
-  size_t off_tw[flame::kMaxLog + 1];
+  size_t off_tw[flame::kMaxLog + 1];   // twiddles, 16 points per thread
+  size_t off_tw8[flame::kMaxLog + 1];  // twiddles, 8 points per thread
   size_t off_dev;
   size_t off_counter;  // step index read by graph replays
   size_t total;
@@ -121,7 +122,12 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   for (int l = 0; l <= flame::kMaxLog; ++l) {
     L->off_tw[l] = off;
     if (need_tw[l]) {
-      const ff::PassPlan pp = ff::make_pass_plan(l);
+      const ff::PassPlan pp = ff::make_pass_plan(l, 16);
+      off = align_up(off + (size_t)(pp.tw_size > 0 ? pp.tw_size : 1) * sizeof(float2));
+    }
+    L->off_tw8[l] = off;
+    if (need_tw[l]) {
+      const ff::PassPlan pp = ff::make_pass_plan(l, 8);
       off = align_up(off + (size_t)(pp.tw_size > 0 ? pp.tw_size : 1) * sizeof(float2));
     }
   }
@@ -135,6 +141,7 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
 
 struct Group {
   int logn1, logn2, first, count, tiles, rgroups;
+  int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
 };
 
 class DeviceGuard {
@@ -162,7 +169,8 @@ struct flame_plan_s {
   std::vector<flame_desc> descs;
   Layout layout;
   std::vector<flame::FlameDev> hdev;
-  std::vector<std::vector<float2>> tw_host;
+  std::vector<std::vector<float2>> tw_host;   // host copies of the tables (16 points per thread)
+  std::vector<std::vector<float2>> tw_host8;  // 8 points per thread
   flame::FlameDev* ddev = nullptr;
   std::vector<Group> groups;
   std::vector<char> w_valid;
@@ -276,7 +284,8 @@ int build_graph(flame_plan p) {
   for (int s = 0; s < p->graph_steps; ++s) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
       const Group& gr = p->groups[gi];
-      const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2), ck = flame::col_step_kernel(gr.logn1);
+      const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
+      const flame::KernelLaunch ck = flame::col_step_kernel(gr.logn1, gr.col_pts);
       if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
       const flame::FlameDev* fl = p->ddev + gr.first;
       long long n = s;
@@ -377,18 +386,22 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
   const Layout& L = p->layout;
   // twiddle tables, built in double precision and rounded once
   p->tw_host.resize(flame::kMaxLog + 1);
+  p->tw_host8.resize(flame::kMaxLog + 1);
   for (int l = flame::kMinLog; l <= flame::kMaxLog; ++l) {
     bool used = false;
     for (const Sizes& s : L.sizes) used |= (s.logn1 == l || s.logn2 == l);
     if (!used) continue;
-    const ff::PassPlan pp = ff::make_pass_plan(l);
-    p->tw_host[l].assign(pp.tw_size > 0 ? pp.tw_size : 1, make_float2(1.f, 0.f));
-    ff::build_twiddles(l, p->tw_host[l].data());
-    e = hipMemcpyAsync(base + L.off_tw[l], p->tw_host[l].data(), p->tw_host[l].size() * sizeof(float2),
-                       hipMemcpyHostToDevice, p->stream);
-    if (e != hipSuccess) {
-      delete p;
-      return hip_fail(e, "twiddle upload");
+    for (int pts : {16, 8}) {
+      auto& host = pts == 16 ? p->tw_host[l] : p->tw_host8[l];
+      const ff::PassPlan pp = ff::make_pass_plan(l, pts);
+      host.assign(pp.tw_size > 0 ? pp.tw_size : 1, make_float2(1.f, 0.f));
+      ff::build_twiddles(l, host.data(), pts);
+      e = hipMemcpyAsync(base + (pts == 16 ? L.off_tw[l] : L.off_tw8[l]), host.data(), host.size() * sizeof(float2),
+                         hipMemcpyHostToDevice, p->stream);
+      if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "twiddle upload");
+      }
     }
   }
   // device flame table, ordered so that flames of one grid size are contiguous
@@ -407,6 +420,8 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.part = reinterpret_cast<double*>(base + L.off_part[f]);
     fd.tw1 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn1]);
     fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
+    fd.tw1_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn1]);
+    fd.tw2_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn2]);
     fd.n1 = d.n1;
     fd.n2 = d.n2;
     fd.m = d.n2 / 4;
@@ -540,11 +555,12 @@ int flame_step(flame_plan p, int32_t nsteps) {
     for (const Group& gr : p->groups) {
       Timed tm(p, KIND_ROW);
       flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
-                        nullptr);
+                        nullptr, gr.row_pts);
     }
     for (const Group& gr : p->groups) {
       Timed tm(p, KIND_COL);
-      flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, p->n);
+      flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
+                        gr.col_pts);
     }
     p->n += 1;
   }
@@ -629,6 +645,115 @@ int flame_timing_begin(flame_plan p) {
   p->chain = nullptr;
   p->timing = true;
   return FLAME_OK;
+}
+
+int flame_set_points_per_thread(flame_plan p, int32_t n1, int32_t n2, int32_t col_pts, int32_t row_pts) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if ((col_pts != 8 && col_pts != 16) || (row_pts != 8 && row_pts != 16))
+    return fail(FLAME_ERR_INVALID_ARG, "points per thread must be 8 or 16");
+  bool found = false;
+  for (Group& gr : p->groups) {
+    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
+      gr.col_pts = col_pts;
+      gr.row_pts = row_pts;
+      found = true;
+    }
+  }
+  if (!found) return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+  DeviceGuard g(p->device);
+  drop_graph(p);
+  return FLAME_OK;
+}
+
+int flame_get_points_per_thread(flame_plan p, int32_t n1, int32_t n2, int32_t* col_pts, int32_t* row_pts) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!col_pts || !row_pts) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  for (const Group& gr : p->groups) {
+    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
+      *col_pts = gr.col_pts;
+      *row_pts = gr.row_pts;
+      return FLAME_OK;
+    }
+  }
+  return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+}
+
+int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (steps <= 0) return fail(FLAME_ERR_INVALID_ARG, "steps must be > 0");
+  DeviceGuard g(p->device);
+  // save every state in its flame's adjoint scratch (each at least 2x the state)
+  hipError_t e;
+  for (int f = 0; f < p->nfl; ++f) {
+    const size_t bytes = (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2);
+    e = hipMemcpyAsync(p->hdev[f].A1, p->hdev[f].S, bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune save");
+  }
+  for (int f = 0; f < p->nfl; ++f)
+    if (!p->w_valid[f]) {
+      rc = rebuild_w(p, f);
+      if (rc) return rc;
+    }
+  const long long n0 = p->n;
+  const int saved_graph = p->graph_steps;
+  drop_graph(p);
+  p->graph_steps = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+    return fail(FLAME_ERR_HIP, "autotune: hipEventCreate failed");
+  int tried = 0;
+  const int opts[2] = {16, 8};
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    Group& gr = p->groups[gi];
+    float best = 1e30f;
+    int best_c = gr.col_pts, best_r = gr.row_pts;
+    for (int c : opts) {
+      for (int r : opts) {
+        gr.col_pts = c;
+        gr.row_pts = r;
+        // one untimed step, then `steps` timed steps of this group alone
+        for (int s = 0; s <= steps; ++s) {
+          if (s == 1) (void)hipEventRecord(ev0, p->stream);
+          flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, n0,
+                            nullptr, nullptr, r);
+          flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n0,
+                            nullptr, c);
+        }
+        (void)hipEventRecord(ev1, p->stream);
+        e = hipEventSynchronize(ev1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e != hipSuccess) {
+          (void)hipEventDestroy(ev0);
+          (void)hipEventDestroy(ev1);
+          return hip_fail(e, "autotune timing");
+        }
+        ++tried;
+        if (ms < best) {
+          best = ms;
+          best_c = c;
+          best_r = r;
+        }
+      }
+    }
+    gr.col_pts = best_c;
+    gr.row_pts = best_r;
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  for (int f = 0; f < p->nfl; ++f) {
+    const size_t bytes = (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2);
+    e = hipMemcpyAsync(p->hdev[f].S, p->hdev[f].A1, bytes, hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "autotune restore");
+    p->w_valid[f] = 0;
+  }
+  p->n = n0;
+  p->graph_steps = saved_graph;
+  if (n_configs_tried) *n_configs_tried = tried;
+  return last_launch("autotune launch");
 }
 
 int flame_set_graph_steps(flame_plan p, int32_t steps) {

@@ -15,13 +15,15 @@ namespace flame {
 // in a device array; blockIdx.y selects the flame inside a launch).
 struct FlameDev {
   float2* S;           // state, [M][H1]
-  float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~, tiled [m/T][j1][m%T]
+  float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~, pair-major [j1/2][m][j1%2]
   float2* Wm;          // conj of column transforms of (i kappa1 + kappa2) Phi~, same layout
-  float2* Q;           // row transforms of |grad Phi|^2 (and scratch), same layout
+  float2* Q;           // row transforms of |grad Phi|^2 (and scratch), tiled [m/T][j1][m%T]
   float2* A1;          // adjoint scratch, same layout: row transform of w1 = m g1
   float2* A2;          // adjoint scratch, same layout: i kappa2 x row transform of w2 = m g2
-  const float2* tw1;   // twiddles of the length-N1 transform
-  const float2* tw2;   // twiddles of the length-N2 transform
+  const float2* tw1;   // twiddles of the length-N1 transform, 16 points per thread
+  const float2* tw2;   // twiddles of the length-N2 transform, 16 points per thread
+  const float2* tw1_8; // the same for 8 points per thread
+  const float2* tw2_8;
   double* part;        // per-workgroup partial sums of the diagnostics
   int n1, n2;
   int m;               // stored k2 columns, N2/4
@@ -34,21 +36,25 @@ struct FlameDev {
   double t0, dt;
 };
 
-// Column kernel: T = max(1, 256/G) columns per workgroup, interleaved
-// (thread tid works on column tid % T, FFT lane tid / T).
-template <int LOGN1>
+// Column kernel: T = max(1, 16*256/N1) columns per workgroup, interleaved
+// (thread tid works on column tid % T, FFT lane tid / T); the transform of
+// each column uses G = N1/PTS threads. T fixes the tiling of Wp/Wm/Q, so it
+// does not depend on PTS.
+template <int LOGN1, int PTS = ff::kPts>
 struct ColCfg {
-  static constexpr int G = ff::Shape<LOGN1>::G;
-  static constexpr int T = G >= 256 ? 1 : 256 / G;
+  static constexpr int G16 = ff::Shape<LOGN1>::G;
+  static constexpr int G = ff::Shape<LOGN1, PTS>::G;
+  static constexpr int T = G16 >= 256 ? 1 : 256 / G16;
   static constexpr int THREADS = T * G;
   static constexpr int LDS_BYTES = ff::Shape<LOGN1>::LDS * T * 8;
 };
 
-// Row kernel: B = max(1, 256/G) row pairs per workgroup, interleaved.
-template <int LOGN2>
+// Row kernel: B = max(1, 16*256/N2) row pairs per workgroup, interleaved.
+template <int LOGN2, int PTS = ff::kPts>
 struct RowCfg {
-  static constexpr int G = ff::Shape<LOGN2>::G;
-  static constexpr int B = G >= 256 ? 1 : 256 / G;
+  static constexpr int G16 = ff::Shape<LOGN2>::G;
+  static constexpr int G = ff::Shape<LOGN2, PTS>::G;
+  static constexpr int B = G16 >= 256 ? 1 : 256 / G16;
   static constexpr int THREADS = B * G;
   static constexpr int LDS_BYTES = ff::Shape<LOGN2>::LDS * B * 8;
 };
@@ -84,11 +90,7 @@ constexpr int kTwCacheMinNs = FLAME_TW_CACHE_MIN_NS;
 #define FLAME_PRUNE 1
 #endif
 constexpr bool kPrune = FLAME_PRUNE != 0;
-// Row kernel: load the second row of a pair before transforming the first.
-#ifndef FLAME_ROW_PREFETCH
-#define FLAME_ROW_PREFETCH 1
-#endif
-constexpr bool kRowPrefetch = FLAME_ROW_PREFETCH != 0;
+
 
 // Minimum waves per SIMD the row and column kernels are compiled for (a
 // register budget of 512 / waves VGPRs).

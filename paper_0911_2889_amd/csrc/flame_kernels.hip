@@ -28,12 +28,13 @@
 
 namespace flame {
 
-template <int LOGN1, int MODE>
-__global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
+template <int LOGN1, int MODE, int PTS = ff::kPts>
+__global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   if (nbase) n += *nbase;  // graph replays read the step index from device memory
-  using S = ff::Shape<LOGN1>;
-  constexpr int G = S::G, T = ColCfg<LOGN1>::T, N1 = S::N;
+  using S = ff::Shape<LOGN1, PTS>;
+  constexpr int G = S::G, T = ColCfg<LOGN1, PTS>::T, N1 = S::N;
+  constexpr int KEEP = PTS / 2, LOW = PTS / 4, HIGH = 3 * PTS / 4;
   extern __shared__ float2 lds[];
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
@@ -44,27 +45,27 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   float2* my = lds + c;
   const size_t tile_base = (size_t)tile * N1 * T + c;
   gf2* const Qc = glob(f.Q) + tile_base;     // column m of Q: Qc[j1 * T]
-  gf2* const Wpc = glob(f.Wp) + tile_base;
-  gf2* const Wmc = glob(f.Wm) + tile_base;
+  gf2* const Wpc = glob(f.Wp);  // pair-major: element (j1, m) at pair_major(j1, m, M)
+  gf2* const Wmc = glob(f.Wm);
   // column m of the state: Sc[k1]; COL_FIRST and COL_SYNTH may read another
   // spectrum in the same layout (src), the other modes update the state
   gf2* const Sc = glob((MODE == COL_FIRST || MODE == COL_SYNTH) && src ? const_cast<float2*>(src) : f.S) +
                   (size_t)m * f.h1 + N1 / 4;
-  const auto tw1 = KernelTw<LOGN1>::make(f.tw1, t);
+  const auto tw1 = KernelTw<LOGN1, PTS>::make(PTS == 8 ? f.tw1_8 : f.tw1, t);
 
-  float2 v[ff::kPts];
-  float2 sv[8];
+  float2 v[PTS];
+  float2 sv[KEEP];
 
   if constexpr (MODE == COL_STEP || MODE == COL_PROJECT) {
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i)
+    for (int i = 0; i < PTS; ++i)
       v[i] = live ? ld(Qc + (t + G * i) * T) : make_float2(0.f, 0.f);
     // the old state is loaded before the transform so its latency is hidden
-    float2 old[8];
+    float2 old[KEEP];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
-      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+    for (int kk = 0; kk < KEEP; ++kk) {
+      const int i = kept_reg<PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
       old[kk] = (MODE == COL_STEP && live) ? ld(Sc + k1) : make_float2(0.f, 0.f);
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
@@ -73,9 +74,9 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     const float kap2c = f.s2 * (float)m;
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
-      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+    for (int kk = 0; kk < KEEP; ++kk) {
+      const int i = kept_reg<PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
       const int s = k1 + N1 / 4;
       float2 val;
       if constexpr (MODE == COL_STEP) {
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       // symmetrise column k2 = 0 (group c == 0): copy k1 > 0 conjugated onto -k1
       if (c == 0) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int kk = 0; kk < LOW; ++kk) {
           const int k1 = t + G * kk;
           lds[k1] = sv[kk];
         }
@@ -101,8 +102,8 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       __syncthreads();
       if (c == 0) {
 #pragma unroll
-        for (int kk = 4; kk < 8; ++kk) {
-          const int k1 = t + G * kept_reg(kk) - N1;
+        for (int kk = LOW; kk < KEEP; ++kk) {
+          const int k1 = t + G * kept_reg<PTS>(kk) - N1;
           if (k1 > -N1 / 4) sv[kk] = ff::cconj(lds[-k1]);
         }
         if (t == 0) sv[0].y = 0.f;
@@ -111,71 +112,72 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     }
     if (live) {
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int i = kept_reg(kk);
-        const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+      for (int kk = 0; kk < KEEP; ++kk) {
+        const int i = kept_reg<PTS>(kk);
+        const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
         st(Sc + k1, sv[kk]);
       }
     }
   } else {
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
-      const int k1 = t + G * i - (i >= 12 ? N1 : 0);
+    for (int kk = 0; kk < KEEP; ++kk) {
+      const int i = kept_reg<PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
       sv[kk] = live ? ld(Sc + k1) : make_float2(0.f, 0.f);
     }
   }
 
   if constexpr (MODE == COL_SYNTH) {
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) v[kept_reg(kk)] = sv[kk];
+    for (int kk = 0; kk < KEEP; ++kk) v[kept_reg<PTS>(kk)] = sv[kk];
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) st(Qc + (t + G * i) * T, v[i]);
+      for (int i = 0; i < PTS; ++i) st(Qc + (t + G * i) * T, v[i]);
     }
   } else {
     const float kap2 = f.s2 * (float)m;
     // Z+ = IFFT_k1((i kappa1 - kappa2) Phi~), stored as is
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
-      const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
+    for (int kk = 0; kk < KEEP; ++kk) {
+      const int i = kept_reg<PTS>(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? N1 : 0));
       v[i] = make_float2(-kap1 * sv[kk].y - kap2 * sv[kk].x, kap1 * sv[kk].x - kap2 * sv[kk].y);
     }
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) st(Wpc + (t + G * i) * T, v[i]);
+      for (int i = 0; i < PTS; ++i) st(Wpc + pair_major(t + G * i, m, f.m), v[i]);
     }
     // Z- column for k2 = -m: conj(IFFT_k1((i kappa1 + kappa2) Phi~))
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg(kk);
-      const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
+    for (int kk = 0; kk < KEEP; ++kk) {
+      const int i = kept_reg<PTS>(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? N1 : 0));
       v[i] = make_float2(-kap1 * sv[kk].y + kap2 * sv[kk].x, kap1 * sv[kk].x + kap2 * sv[kk].y);
     }
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) st(Wmc + (t + G * i) * T, ff::cconj(v[i]));
+      for (int i = 0; i < PTS; ++i) st(Wmc + pair_major(t + G * i, m, f.m), ff::cconj(v[i]));
     }
   }
 }
 
-template <int LOGN2, int MODE>
-__global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_waves_per_eu(ROW_WAVES_PER_EU)))
+template <int LOGN2, int MODE, int PTS = ff::kPts>
+__global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(ROW_WAVES_PER_EU)))
     row_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase,
                const float* __restrict__ phys_in, float* __restrict__ phys_out) {
   if (nbase) n += *nbase;
-  using S = ff::Shape<LOGN2>;
-  constexpr int G = S::G, B = RowCfg<LOGN2>::B, N2 = S::N;
+  using S = ff::Shape<LOGN2, PTS>;
+  constexpr int G = S::G, B = RowCfg<LOGN2, PTS>::B, N2 = S::N;
+  constexpr int LOW = PTS / 4, HIGH = 3 * PTS / 4;
   extern __shared__ float2 lds[];
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
@@ -185,50 +187,43 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
   const int ja = 2 * pair, jb = 2 * pair + 1;
   const int n1 = f.n1, ts = f.tshift, mcols = f.m;
   float2* my = lds + p;
-  const auto tw2 = KernelTw<LOGN2>::make(f.tw2, t);
+  const auto tw2 = KernelTw<LOGN2, PTS>::make(PTS == 8 ? f.tw2_8 : f.tw2, t);
   gf2* const Wp = glob(f.Wp);
   gf2* const Wm = glob(f.Wm);
   gf2* const Q = glob(f.Q);
 
-  float2 y[ff::kPts];
+  float2 y[PTS];
 
   if constexpr (MODE == ROW_STEP || MODE == ROW_DIAG) {
-    float qa[ff::kPts];
+    float qa[PTS];
     double area = 0.0;
     const float inv_r2 = [&] {
       const double t0 = f.t0 + (double)n * f.dt;
       return (float)(1.0 / (t0 * t0));
     }();
-    // kRowPrefetch: both rows' inputs are loaded up front so the second row's
-    // load latency hides behind the first row's transform
-    float2 vr[2][ff::kPts];
-    auto load_row = [&](int half) {
-      const int row = half ? jb : ja;
+    // both rows' inputs come in one 16-byte load per register (pair-major Wp, Wm)
+    float2 vr[2][PTS];
+    const int pbase = pair * mcols;
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) {
-        const int idx = t + G * i;
-        float2 val = make_float2(0.f, 0.f);
-        if (live) {
-          if (i < 4) {
-            val = ld(Wp + tiled(row, idx, n1, ts));
-          } else if (i >= 12) {
-            const int mm = N2 - idx;
-            if (mm < mcols) val = ld(Wm + tiled(row, mm, n1, ts));
-          }
+    for (int i = 0; i < PTS; ++i) {
+      const int idx = t + G * i;
+      float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+      if (live) {
+        if (i < LOW) {
+          ld_pair(Wp + ((pbase + idx) << 1), a, b);
+        } else if (i >= HIGH) {
+          const int mm = N2 - idx;
+          if (mm < mcols) ld_pair(Wm + ((pbase + mm) << 1), a, b);
         }
-        vr[half][i] = val;
       }
-    };
-    load_row(0);
-    if constexpr (kRowPrefetch) load_row(1);
+      vr[0][i] = a;
+      vr[1][i] = b;
+    }
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      if constexpr (!kRowPrefetch) {
-        if (half == 1) load_row(1);
-      }
       fft<LOGN2, true, kPrune>(vr[half], t, my, B, tw2);
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) {
+      for (int i = 0; i < PTS; ++i) {
         const float q = vr[half][i].x * vr[half][i].x + vr[half][i].y * vr[half][i].y;
         if constexpr (MODE == ROW_DIAG) {
           const double x = (double)q * (double)inv_r2;
@@ -247,7 +242,7 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
       double* red = reinterpret_cast<double*>(lds);
       red[tid] = live ? area : 0.0;
       __syncthreads();
-      for (int w = RowCfg<LOGN2>::THREADS / 2; w > 0; w >>= 1) {
+      for (int w = RowCfg<LOGN2, PTS>::THREADS / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
       }
@@ -256,21 +251,21 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
     }
   } else if constexpr (MODE == ROW_FORWARD) {
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) {
+    for (int i = 0; i < PTS; ++i) {
       const int idx = t + G * i;
       y[i] = live ? make_float2(glob(phys_in)[(size_t)ja * N2 + idx], glob(phys_in)[(size_t)jb * N2 + idx])
                   : make_float2(0.f, 0.f);
     }
   } else {  // ROW_SYNTH: Y = X_a + i X_b with X(k2) = A(m) for k2 = m >= 0, conj(A(m)) for k2 = -m
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) {
+    for (int i = 0; i < PTS; ++i) {
       const int idx = t + G * i;
       float2 val = make_float2(0.f, 0.f);
       if (live) {
-        if (i < 4) {
+        if (i < LOW) {
           const float2 a = ld(Q + tiled(ja, idx, n1, ts)), b = ld(Q + tiled(jb, idx, n1, ts));
           val = make_float2(a.x - b.y, a.y + b.x);
-        } else if (i >= 12) {
+        } else if (i >= HIGH) {
           const int mm = N2 - idx;
           if (mm < mcols) {
             const float2 a = ld(Q + tiled(ja, mm, n1, ts)), b = ld(Q + tiled(jb, mm, n1, ts));
@@ -284,7 +279,7 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
     fft<LOGN2, true, kPrune>(y, t, my, B, tw2);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) {
+      for (int i = 0; i < PTS; ++i) {
         const int idx = t + G * i;
         glob(phys_out)[(size_t)ja * N2 + idx] = y[i].x;
         glob(phys_out)[(size_t)jb * N2 + idx] = y[i].y;
@@ -297,11 +292,11 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
   // Q_a(k) = (Y(k) + conj(Y(-k)))/2, Q_b(k) = (Y(k) - conj(Y(-k)))/(2i), k in [0, K2]
   fft<LOGN2, false>(y, t, my, B, tw2);
   __syncthreads();
-  ff::Fft<LOGN2, false>::scatter(y, t, my, B);
+  ff::Fft<LOGN2, false, PTS>::scatter(y, t, my, B);
   __syncthreads();
   if (live) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < LOW; ++i) {
       const int k = t + G * i;
       const float2 yk = my[ff::lds_pad(k) * B];
       const float2 ym = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
@@ -434,7 +429,10 @@ struct ColTable {
       default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, nb, src); break;
     }
   }
-  static KernelLaunch step_kernel() {
+  static KernelLaunch step_kernel(int pts) {
+    if (pts == 8)
+      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8>), ColCfg<LOGN, 8>::THREADS,
+                          ColCfg<LOGN, 8>::LDS_BYTES};
     return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP>), ColCfg<LOGN>::THREADS,
                         ColCfg<LOGN>::LDS_BYTES};
   }
@@ -459,7 +457,10 @@ struct RowTable {
       default: hipLaunchKernelGGL((row_kernel<LOGN, ROW_DIAG>), grid, dim3(th), lds, st, fl, n, nb, in, out); break;
     }
   }
-  static KernelLaunch step_kernel() {
+  static KernelLaunch step_kernel(int pts) {
+    if (pts == 8)
+      return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8>), RowCfg<LOGN, 8>::THREADS,
+                          RowCfg<LOGN, 8>::LDS_BYTES};
     return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP>), RowCfg<LOGN>::THREADS,
                         RowCfg<LOGN>::LDS_BYTES};
   }
@@ -476,36 +477,51 @@ void dispatch_log(int logn, A... args) {
 }
 
 template <template <int> class Tab, int L>
-void dispatch_info(int logn, KernelLaunch* out) {
+void dispatch_info(int logn, int pts, KernelLaunch* out) {
   if constexpr (L <= kMaxLog) {
     if (logn == L)
-      *out = Tab<L>::step_kernel();
+      *out = Tab<L>::step_kernel(pts);
     else
-      dispatch_info<Tab, L + 1>(logn, out);
+      dispatch_info<Tab, L + 1>(logn, pts, out);
   }
 }
 
 }  // namespace
 
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const void* src) {
+                const void* src, int pts) {
+  if (mode == COL_STEP && pts != ff::kPts) {
+    const KernelLaunch kl = col_step_kernel(logn1, pts);
+    const long long* nb = nullptr;
+    const float2* s = static_cast<const float2*>(src);
+    void* args[] = {&fl, &n, &nb, &s};
+    (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
+    return;
+  }
   dispatch_log<ColTable, kMinLog>(logn1, mode, dim3(tiles, nfl), st, fl, n, static_cast<const float2*>(src));
 }
 
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const float* in, float* out) {
+                const float* in, float* out, int pts) {
+  if (mode == ROW_STEP && pts != ff::kPts) {
+    const KernelLaunch kl = row_step_kernel(logn2, pts);
+    const long long* nb = nullptr;
+    void* args[] = {&fl, &n, &nb, &in, &out};
+    (void)hipLaunchKernel(kl.func, dim3(groups, nfl), dim3(kl.threads), args, kl.lds, st);
+    return;
+  }
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
 }
 
-KernelLaunch col_step_kernel(int logn1) {
+KernelLaunch col_step_kernel(int logn1, int pts) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<ColTable, kMinLog>(logn1, &out);
+  dispatch_info<ColTable, kMinLog>(logn1, pts, &out);
   return out;
 }
 
-KernelLaunch row_step_kernel(int logn2) {
+KernelLaunch row_step_kernel(int logn2, int pts) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<RowTable, kMinLog>(logn2, &out);
+  dispatch_info<RowTable, kMinLog>(logn2, pts, &out);
   return out;
 }
 

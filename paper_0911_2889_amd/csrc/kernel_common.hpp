@@ -11,28 +11,29 @@
 
 namespace flame {
 
-template <int LOGN, bool INV, bool OUTER, int P = 0, class TW>
-__device__ __forceinline__ void fft_passes(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
-  using S = ff::Shape<LOGN>;
+template <int LOGN, bool INV, bool OUTER, int PTS, int P = 0, class TW>
+__device__ __forceinline__ void fft_passes(float2 (&v)[PTS], int t, float2* lds, int stride, const TW& tw) {
+  using S = ff::Shape<LOGN, PTS>;
   if constexpr (P < S::NPASS) {
-    ff::Fft<LOGN, INV>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
+    ff::Fft<LOGN, INV, PTS>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
     if constexpr (P + 1 < S::NPASS) {
       __syncthreads();
-      ff::Fft<LOGN, INV>::gather(v, t, lds, stride);
+      ff::Fft<LOGN, INV, PTS>::gather(v, t, lds, stride);
       __syncthreads();
     }
-    fft_passes<LOGN, INV, OUTER, P + 1>(v, t, lds, stride, tw);
+    fft_passes<LOGN, INV, OUTER, PTS, P + 1>(v, t, lds, stride, tw);
   }
 }
 
-// Transform the 16 registers of every group of the workgroup (all threads
+// Transform the PTS registers of every group of the workgroup (all threads
 // must call it: it contains workgroup barriers). On entry v[i] holds the
 // input at position t + G*i, on exit the output at the same position.
-// OUTER: the input is known to vanish in registers 4..11 (the retained box
-// fills only the first and last quarter of a padded spectrum).
-template <int LOGN, bool INV, bool OUTER = false, class TW>
-__device__ __forceinline__ void fft(float2 (&v)[ff::kPts], int t, float2* lds, int stride, const TW& tw) {
-  fft_passes<LOGN, INV, OUTER, 0>(v, t, lds, stride, tw);
+// OUTER: the input is known to vanish in the middle half of the registers
+// (the retained box fills only the first and last quarter of a padded
+// spectrum).
+template <int LOGN, bool INV, bool OUTER = false, class TW, int PTS>
+__device__ __forceinline__ void fft(float2 (&v)[PTS], int t, float2* lds, int stride, const TW& tw) {
+  fft_passes<LOGN, INV, OUTER, PTS, 0>(v, t, lds, stride, tw);
 }
 
 // Global-memory views: loads and stores through these pointers compile to
@@ -62,10 +63,10 @@ struct GlobalFetch {
   __device__ __forceinline__ float2 operator()(int i) const { return ld(tw + i); }
 };
 
-template <int LOGN>
+template <int LOGN, int PTS = ff::kPts>
 struct KernelTw {
-  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN, GlobalFetch, kTwCacheMinNs>,
-                                         ff::GlobalTw<LOGN>>::type;
+  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN, GlobalFetch, kTwCacheMinNs, PTS>,
+                                         ff::GlobalTw<LOGN, PTS>>::type;
   static __device__ __forceinline__ Type make(const float2* tw, int t) {
     if constexpr (kCacheTwiddles) {
       return Type(GlobalFetch{(const gf2*)tw}, t);
@@ -95,7 +96,25 @@ __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long
   return s;
 }
 
-// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Wp, Wm, Q.
+// Offset of element (j1, m) of Wp and Wm: pair-major [j1/2][m][j1%2], so that
+// the spectra of a row pair are one contiguous run (the row kernel reads both
+// rows with one 16-byte load per lane; the column kernel's writes are the
+// scattered side of the transpose and merge in L2).
+__device__ __forceinline__ int pair_major(int j1, int m, int mcols) {
+  return (((j1 >> 1) * mcols + m) << 1) + (j1 & 1);
+}
+
+using v4f = float __attribute__((ext_vector_type(4)));
+using gf4 = __attribute__((address_space(1))) v4f;
+// Elements (2 q, m) and (2 q + 1, m) of a pair-major array at p = base + pair_major(2 q, m).
+__device__ __forceinline__ void ld_pair(const gf2* p, float2& a, float2& b) {
+  const v4f v = *(const gf4*)p;
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+
+// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Q (and of
+// the adjoint scratch A1, A2).
 __device__ __forceinline__ int tiled(int j1, int m, int n1, int tshift) {
   return (((m >> tshift) * n1 + j1) << tshift) + (m & ((1 << tshift) - 1));
 }
@@ -108,9 +127,13 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Register slot kk (0..7) of the kept spectral positions: registers 0..3 hold
-// k1 = t + G*i >= 0, registers 12..15 hold k1 = t + G*i - N1 < 0.
-__device__ __forceinline__ constexpr int kept_reg(int kk) { return kk < 4 ? kk : kk + 8; }
+// Register slot kk (0..PTS/2-1) of the kept spectral positions: registers
+// 0..PTS/4-1 hold k1 = t + G*i >= 0, registers 3PTS/4..PTS-1 hold
+// k1 = t + G*i - N1 < 0 (the first and last quarter of the padded length).
+template <int PTS>
+__device__ __forceinline__ constexpr int kept_reg(int kk) {
+  return kk < PTS / 4 ? kk : kk + PTS / 2;
+}
 
 
 }  // namespace flame

@@ -143,6 +143,23 @@ class FlameEnsemble:
                                                ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_points_per_thread(self, n1, n2, col_pts, row_pts):
+        """Points per thread (8 or 16) of the step kernels for the grid n1 x n2."""
+        native.check(self.lib.flame_set_points_per_thread(self.plan, int(n1), int(n2), int(col_pts), int(row_pts)))
+
+    def points_per_thread(self, n1, n2):
+        c, r = ctypes.c_int32(), ctypes.c_int32()
+        native.check(self.lib.flame_get_points_per_thread(self.plan, int(n1), int(n2), ctypes.byref(c),
+                                                          ctypes.byref(r)))
+        return c.value, r.value
+
+    def autotune(self, steps=20):
+        """Time every points-per-thread choice per grid group and keep the fastest;
+        the simulation state is unchanged. Returns the number of timed configurations."""
+        tried = ctypes.c_int32()
+        native.check(self.lib.flame_autotune(self.plan, int(steps), ctypes.byref(tried)))
+        return tried.value
+
     def set_graph_steps(self, steps):
         """Step in hipGraphs of `steps` steps (0: direct launches)."""
         native.check(self.lib.flame_set_graph_steps(self.plan, int(steps)))

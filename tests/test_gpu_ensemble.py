@@ -101,3 +101,24 @@ def test_full_ensemble_256_flames():
         err = rel_l2(ens.spectrum(f).cpu().numpy(), ref)
         assert err < 1e-5, (f, err)
     assert all(ens.diagnostics(f)["finite"] for f in range(0, 256, 17))
+
+
+def test_autotune_keeps_the_state_and_agrees_with_the_oracle():
+    from paper_0911_2889_amd import FlameEnsemble
+    members = [synth.Workload(f"a{i}", n1, n2, 20, 0.25, "disc", 1e-3, -1.0, 3000 + i, max_norm=12)
+               for i, (n1, n2) in enumerate([(64, 128), (64, 128), (256, 512), (128, 64)])]
+    ens = FlameEnsemble(member_descs(members))
+    halves = [synth.workload_spectrum(w) for w in members]
+    for f, h in enumerate(halves):
+        ens.set_spectrum(h, flame=f, n=0)
+    ens.step(5)
+    before = [ens.spectrum(f).cpu().numpy() for f in range(len(members))]
+    assert ens.autotune(steps=4) == 3 * 4  # three grid groups, four choices each
+    assert ens.step_index == 5
+    for f in range(len(members)):
+        assert np.array_equal(ens.spectrum(f).cpu().numpy(), before[f])
+        assert ens.points_per_thread(members[f].n1, members[f].n2)[0] in (8, 16)
+    ens.step(15)
+    for f in range(len(members)):
+        ref = oracle_trajectory(halves[f], oracle_params(members[f]), [20])[20]
+        assert rel_l2(ens.spectrum(f).cpu().numpy(), ref) < 1e-5

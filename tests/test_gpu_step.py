@@ -205,3 +205,18 @@ def test_zero_state_stays_zero(flame):
     sim.set_spectrum(np.zeros(sim.half_shape(), dtype=np.complex64))
     sim.step(5)
     assert weighted_sq(sim.spectrum().cpu().numpy()) == 0.0
+
+
+@pytest.mark.parametrize("n1,n2", [(64, 128), (256, 512), (2048, 64), (32, 4096), (4096, 32)])
+@pytest.mark.parametrize("cp,rp", [(8, 8), (8, 16), (16, 8)])
+def test_points_per_thread_variants_match_oracle(flame, n1, n2, cp, rp):
+    w = small_workload(n1, n2, seed=n1 + 3 * n2 + cp + rp, amp=0.05, t0=5.0, dt=0.2)
+    half = synth.workload_spectrum(w)
+    sim = make_sim(flame, w)
+    sim.set_points_per_thread(n1, n2, cp, rp)
+    assert sim.points_per_thread(n1, n2) == (cp, rp)
+    sim.set_spectrum(half)
+    sim.step(3)
+    got = sim.spectrum().cpu().numpy()
+    ref = oracle_trajectory(half, oracle_params(w), [3])[3]
+    assert rel_l2(got, ref) < 2e-6

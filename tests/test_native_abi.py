@@ -81,18 +81,20 @@ def test_fft_engine_on_host_matches_numpy(tmp_path):
     subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-I", inc, src, "-o", str(exe)], check=True,
                    capture_output=True)
     # odd strides use register-cached twiddles, even strides the table; outer = 1
-    # zeroes the middle half of the input and uses the pruned first pass
+    # zeroes the middle half of the input and uses the pruned first pass; pts is
+    # the number of points per thread (radix of the full passes)
     for logn in range(4, 14):
         for inv in (0, 1):
-            for stride, outer in ((1, 0), (4, 0), (3, 1), (2, 1)):
+            for stride, outer, pts in ((1, 0, 16), (4, 0, 16), (3, 1, 16), (2, 1, 16), (1, 0, 8), (2, 1, 8),
+                                       (3, 1, 8)):
                 n = 1 << logn
                 rng = np.random.default_rng(logn * 10 + inv)
                 x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
                 if outer:
                     x[n // 4: 3 * n // 4] = 0
-                out = subprocess.run([str(exe)], input=struct.pack("4i", logn, inv, stride, outer) + x.tobytes(),
+                out = subprocess.run([str(exe)], input=struct.pack("5i", logn, inv, stride, outer, pts) + x.tobytes(),
                                      capture_output=True, check=True).stdout
                 y = np.frombuffer(out, dtype=np.complex64)
                 xd = x.astype(np.complex128)
                 ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
-                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logn, inv, stride, outer)
+                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logn, inv, stride, outer, pts)
