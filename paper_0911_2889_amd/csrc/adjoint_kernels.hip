@@ -58,7 +58,8 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   const int m = tile * T + c;
   const bool live = m < f.m;
   float2* my = lds + c;
-  const size_t tile_base = (size_t)tile * N1 * T + c;
+  constexpr int TQ = ColCfg<LOGN1>::TQ, QS = ColCfg<LOGN1>::QS;
+  const size_t tile_base = ((((size_t)m >> QS) * N1) << QS) + (m & (TQ - 1));  // column m of Q, A1, A2
   const size_t col = (size_t)m * f.h1 + N1 / 4;  // element k1 of column m at col + k1
   const auto tw1 = KernelTw<LOGN1>::make(f.tw1, t);
   const float kap2 = f.s2 * (float)m;
@@ -95,7 +96,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) st(glob(f.Q) + tile_base + (t + G * i) * T, v[i]);
+      for (int i = 0; i < ff::kPts; ++i) st(glob(f.Q) + tile_base + (t + G * i) * TQ, v[i]);
     }
     // Z+ and Z- of the state, exactly as the forward column kernel
 #pragma unroll
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
         gf2* dst = glob(pass == 0 ? f.Wp : f.Wm);
 #pragma unroll
         for (int i = 0; i < ff::kPts; ++i)
-          st(dst + pair_major(t + G * i, m, f.m), pass == 0 ? v[i] : ff::cconj(v[i]));
+          st(dst + w_index(t + G * i, m, f.m), pass == 0 ? v[i] : ff::cconj(v[i]));
       }
     }
   } else {
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int pass = 0; pass < 2; ++pass) {
       gf2* srcp = glob(pass == 0 ? f.A1 : f.A2) + tile_base;
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) v[i] = live ? ld(srcp + (t + G * i) * T) : make_float2(0.f, 0.f);
+      for (int i = 0; i < ff::kPts; ++i) v[i] = live ? ld(srcp + (t + G * i) * TQ) : make_float2(0.f, 0.f);
       fft<LOGN1, false>(v, t, my, T, tw1);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg<ff::kPts>(kk)];
@@ -242,10 +243,10 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
       float2 val = make_float2(0.f, 0.f);
       if (live) {
         if (i < 4) {
-          val = ld(Wp + pair_major(row, idx, mcols));
+          val = ld(Wp + w_index(row, idx, mcols));
         } else if (i >= 12) {
           const int mm = N2 - idx;
-          if (mm < mcols) val = ld(Wm + pair_major(row, mm, mcols));
+          if (mm < mcols) val = ld(Wm + w_index(row, mm, mcols));
         }
       }
       v[i] = val;

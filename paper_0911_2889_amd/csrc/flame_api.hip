@@ -47,8 +47,9 @@ int ilog2_exact(int n) {
 struct Sizes {
   int logn1, logn2;
   int tcol, tiles;       // column tile width and tile count
+  int tq;                // tile width of the Q layout
   int rpairs, rgroups;   // row pairs per workgroup and row workgroups
-  size_t wq_elems;       // elements of each of Wp, Wm, Q
+  size_t wq_elems;       // elements of each of Q, A1, A2 (Wp and Wm share 2 wq_elems)
   int n_spec;            // diag spectral workgroups
   size_t part_elems;     // doubles of the partial-sum buffer
 };
@@ -76,7 +77,9 @@ int check_desc(const flame_desc* d, Sizes* s) {
     s->tiles = (m + s->tcol - 1) / s->tcol;
     s->rpairs = flame::row_pairs(l2);
     s->rgroups = (d->n1 / 2 + s->rpairs - 1) / s->rpairs;
-    s->wq_elems = (size_t)s->tiles * s->tcol * d->n1;
+    s->tq = flame::q_tile(l1);
+    const int qcols = (m + s->tq - 1) / s->tq * s->tq;
+    s->wq_elems = (size_t)std::max(s->tiles * s->tcol, qcols) * d->n1;
     const long long spec = (long long)m * (d->n1 / 2);
     s->n_spec = (int)std::min<long long>(1024, (spec + flame::kDiagThreads - 1) / flame::kDiagThreads);
     s->part_elems = (size_t)s->rgroups + 2 * (size_t)s->n_spec;
@@ -86,7 +89,7 @@ int check_desc(const flame_desc* d, Sizes* s) {
 
 struct Layout {
   std::vector<Sizes> sizes;
-  std::vector<size_t> off_wp, off_wm, off_q, off_a1, off_a2, off_part;
+  std::vector<size_t> off_w, off_q, off_a1, off_a2, off_part;
   size_t off_tw[flame::kMaxLog + 1];   // twiddles, 16 points per thread
   size_t off_tw8[flame::kMaxLog + 1];  // twiddles, 8 points per thread
   size_t off_dev;
@@ -106,10 +109,8 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   }
   for (int f = 0; f < nfl; ++f) {
     const Sizes& s = L->sizes[f];
-    L->off_wp.push_back(off);
-    off = align_up(off + s.wq_elems * sizeof(float2));
-    L->off_wm.push_back(off);
-    off = align_up(off + s.wq_elems * sizeof(float2));
+    L->off_w.push_back(off);  // Wp and Wm interleaved
+    off = align_up(off + 2 * s.wq_elems * sizeof(float2));
     L->off_q.push_back(off);
     off = align_up(off + s.wq_elems * sizeof(float2));
     L->off_a1.push_back(off);
@@ -412,8 +413,8 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     flame::FlameDev& fd = p->hdev[f];
     std::memset(&fd, 0, sizeof fd);
     fd.S = static_cast<float2*>(states[f]);
-    fd.Wp = reinterpret_cast<float2*>(base + L.off_wp[f]);
-    fd.Wm = reinterpret_cast<float2*>(base + L.off_wm[f]);
+    fd.Wp = reinterpret_cast<float2*>(base + L.off_w[f]);
+    fd.Wm = fd.Wp + 2;
     fd.Q = reinterpret_cast<float2*>(base + L.off_q[f]);
     fd.A1 = reinterpret_cast<float2*>(base + L.off_a1[f]);
     fd.A2 = reinterpret_cast<float2*>(base + L.off_a2[f]);
@@ -426,7 +427,7 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.n2 = d.n2;
     fd.m = d.n2 / 4;
     fd.h1 = d.n1 / 2;
-    fd.tshift = ilog2_exact(s.tcol);
+    fd.tshift = ilog2_exact(s.tq);
     const bool lit = d.axis_scale[0] == 0.0;
     fd.s1 = (float)(lit ? d.theta_pi : d.axis_scale[0]);
     fd.s2 = (float)(lit ? d.theta_pi : d.axis_scale[1]);

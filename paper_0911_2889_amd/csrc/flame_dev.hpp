@@ -15,9 +15,10 @@ namespace flame {
 // in a device array; blockIdx.y selects the flame inside a launch).
 struct FlameDev {
   float2* S;           // state, [M][H1]
-  float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~, pair-major [j1/2][m][j1%2]
-  float2* Wm;          // conj of column transforms of (i kappa1 + kappa2) Phi~, same layout
-  float2* Q;           // row transforms of |grad Phi|^2 (and scratch), tiled [m/T][j1][m%T]
+  float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~ and ...
+  float2* Wm;          // ... the conj of those of (i kappa1 + kappa2) Phi~, interleaved
+                       // [j1/2][m][Wp, Wm][j1%2] (Wm = Wp + 2; index with w_index)
+  float2* Q;           // row transforms of |grad Phi|^2 (and scratch), tiled [m/TQ][j1][m%TQ]
   float2* A1;          // adjoint scratch, same layout: row transform of w1 = m g1
   float2* A2;          // adjoint scratch, same layout: i kappa2 x row transform of w2 = m g2
   const float2* tw1;   // twiddles of the length-N1 transform, 16 points per thread
@@ -28,7 +29,7 @@ struct FlameDev {
   int n1, n2;
   int m;               // stored k2 columns, N2/4
   int h1;              // stored k1 slots, N1/2
-  int tshift;          // log2 of the tile width T of Wp/Wm/Q
+  int tshift;          // log2 of the tile width TQ of Q, A1, A2
   int pad_;
   float s1, s2;        // axis scales of kappa
   float gamma;
@@ -38,13 +39,24 @@ struct FlameDev {
 
 // Column kernel: T = max(1, 16*256/N1) columns per workgroup, interleaved
 // (thread tid works on column tid % T, FFT lane tid / T); the transform of
-// each column uses G = N1/PTS threads. T fixes the tiling of Wp/Wm/Q, so it
-// does not depend on PTS.
+// each column uses G = N1/PTS threads. T does not depend on PTS.
+//
+// Q is tiled [m/TQ][j1][m%TQ] with TQ = 2T for N1 >= 2048 (else TQ = T): a
+// row-kernel workgroup at N2 = 4096 holds one row pair, so with TQ = T its
+// pieces of Q (2 rows x TQ columns of 8 bytes) would be 32 or 16 bytes, and
+// HBM writes in pieces under 64 bytes run at about half the bandwidth of
+// longer ones. The column kernel then reads half of each 2-row piece and the
+// neighbouring workgroup (same XCD) the other half.
+constexpr int col_tile_for(int g16) { return g16 >= 256 ? 1 : 256 / g16; }
+constexpr int q_tile_for(int g16) { return g16 >= 128 ? 2 * col_tile_for(g16) : col_tile_for(g16); }
+
 template <int LOGN1, int PTS = ff::kPts>
 struct ColCfg {
   static constexpr int G16 = ff::Shape<LOGN1>::G;
   static constexpr int G = ff::Shape<LOGN1, PTS>::G;
-  static constexpr int T = G16 >= 256 ? 1 : 256 / G16;
+  static constexpr int T = col_tile_for(G16);
+  static constexpr int TQ = q_tile_for(G16);
+  static constexpr int QS = ff::ilog2c(TQ);
   static constexpr int THREADS = T * G;
   static constexpr int LDS_BYTES = ff::Shape<LOGN1>::LDS * T * 8;
 };
@@ -59,7 +71,8 @@ struct RowCfg {
   static constexpr int LDS_BYTES = ff::Shape<LOGN2>::LDS * B * 8;
 };
 
-constexpr int col_tile(int logn1) { return (1 << logn1) / ff::kPts >= 256 ? 1 : 256 / ((1 << logn1) / ff::kPts); }
+constexpr int col_tile(int logn1) { return col_tile_for((1 << logn1) / ff::kPts); }
+constexpr int q_tile(int logn1) { return q_tile_for((1 << logn1) / ff::kPts); }
 constexpr int row_pairs(int logn2) { return (1 << logn2) / ff::kPts >= 256 ? 1 : 256 / ((1 << logn2) / ff::kPts); }
 
 enum ColMode : int { COL_STEP = 0, COL_FIRST = 1, COL_PROJECT = 2, COL_SYNTH = 3 };

@@ -14,8 +14,9 @@
 //    store the state, then immediately form the next step's column transforms
 //    of (i kappa1 -+ kappa2) Phi~ -> Wp, Wm. (Section 3: column transforms of
 //    k1 Psi and k2 Psi; the inverse column transform of the product.)
-// The global transposes of Section 3 are the tiled layout of Wp/Wm/Q in HBM:
-// the column kernel writes whole tiles, the row kernel reads row segments.
+// The global transposes of Section 3 are the layouts of Wp/Wm and Q in HBM:
+// each kernel reads long contiguous runs and writes pieces of at least 64
+// bytes (2 rows x 4 columns of Q; 2 rows x 2 columns of Wp and Wm).
 
 #include <hip/hip_runtime.h>
 
@@ -43,9 +44,9 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   const int m = tile * T + c;
   const bool live = m < f.m;
   float2* my = lds + c;
-  const size_t tile_base = (size_t)tile * N1 * T + c;
-  gf2* const Qc = glob(f.Q) + tile_base;     // column m of Q: Qc[j1 * T]
-  gf2* const Wpc = glob(f.Wp);  // pair-major: element (j1, m) at pair_major(j1, m, M)
+  constexpr int TQ = ColCfg<LOGN1, PTS>::TQ, QS = ColCfg<LOGN1, PTS>::QS;
+  gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * N1) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
+  gf2* const Wpc = glob(f.Wp);  // element (j1, m) at w_index(j1, m, M)
   gf2* const Wmc = glob(f.Wm);
   // column m of the state: Sc[k1]; COL_FIRST and COL_SYNTH may read another
   // spectrum in the same layout (src), the other modes update the state
@@ -59,7 +60,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   if constexpr (MODE == COL_STEP || MODE == COL_PROJECT) {
 #pragma unroll
     for (int i = 0; i < PTS; ++i)
-      v[i] = live ? ld(Qc + (t + G * i) * T) : make_float2(0.f, 0.f);
+      v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state is loaded before the transform so its latency is hidden
     float2 old[KEEP];
 #pragma unroll
@@ -135,7 +136,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < PTS; ++i) st(Qc + (t + G * i) * T, v[i]);
+      for (int i = 0; i < PTS; ++i) st(Qc + (t + G * i) * TQ, v[i]);
     }
   } else {
     const float kap2 = f.s2 * (float)m;
@@ -151,7 +152,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < PTS; ++i) st(Wpc + pair_major(t + G * i, m, f.m), v[i]);
+      for (int i = 0; i < PTS; ++i) st(Wpc + w_index(t + G * i, m, f.m), v[i]);
     }
     // Z- column for k2 = -m: conj(IFFT_k1((i kappa1 + kappa2) Phi~))
 #pragma unroll
@@ -165,7 +166,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < PTS; ++i) st(Wmc + pair_major(t + G * i, m, f.m), ff::cconj(v[i]));
+      for (int i = 0; i < PTS; ++i) st(Wmc + w_index(t + G * i, m, f.m), ff::cconj(v[i]));
     }
   }
 }
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       const double t0 = f.t0 + (double)n * f.dt;
       return (float)(1.0 / (t0 * t0));
     }();
-    // both rows' inputs come in one 16-byte load per register (pair-major Wp, Wm)
+    // both rows' inputs come in one 16-byte load per register (w_index layout)
     float2 vr[2][PTS];
     const int pbase = pair * mcols;
 #pragma unroll
@@ -210,10 +211,10 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
       if (live) {
         if (i < LOW) {
-          ld_pair(Wp + ((pbase + idx) << 1), a, b);
+          ld_pair(Wp + ((pbase + idx) << 2), a, b);
         } else if (i >= HIGH) {
           const int mm = N2 - idx;
-          if (mm < mcols) ld_pair(Wm + ((pbase + mm) << 1), a, b);
+          if (mm < mcols) ld_pair(Wm + ((pbase + mm) << 2), a, b);
         }
       }
       vr[0][i] = a;

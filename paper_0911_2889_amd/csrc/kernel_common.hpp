@@ -96,17 +96,18 @@ __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long
   return s;
 }
 
-// Offset of element (j1, m) of Wp and Wm: pair-major [j1/2][m][j1%2], so that
-// the spectra of a row pair are one contiguous run (the row kernel reads both
-// rows with one 16-byte load per lane; the column kernel's writes are the
-// scattered side of the transpose and merge in L2).
-__device__ __forceinline__ int pair_major(int j1, int m, int mcols) {
-  return (((j1 >> 1) * mcols + m) << 1) + (j1 & 1);
+// Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm = f.Wp + 2:
+// [j1/2][m][Wp, Wm][j1%2], so that the spectra of a row pair are one
+// contiguous run (the row kernel reads both rows of Wp or Wm with one 16-byte
+// load per lane) and the column kernel writes its two columns of a row pair,
+// Wp and Wm, as one 64-byte piece.
+__device__ __forceinline__ int w_index(int j1, int m, int mcols) {
+  return (((j1 >> 1) * mcols + m) << 2) + (j1 & 1);
 }
 
 using v4f = float __attribute__((ext_vector_type(4)));
 using gf4 = __attribute__((address_space(1))) v4f;
-// Elements (2 q, m) and (2 q + 1, m) of a pair-major array at p = base + pair_major(2 q, m).
+// Elements (2 q, m) and (2 q + 1, m) of Wp (or Wm) at p = f.Wp + w_index(2 q, m, M) (or f.Wm + ...).
 __device__ __forceinline__ void ld_pair(const gf2* p, float2& a, float2& b) {
   const v4f v = *(const gf4*)p;
   a = make_float2(v.x, v.y);
