@@ -46,15 +46,16 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, pts):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources; else None."""
+    was taken on the current kernel sources and the same points-per-thread
+    variant of the kernel; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_digest") != source_digest():
+    if rec.get("source_digest") != source_digest() or rec.get("points_per_thread") != pts:
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -136,8 +137,12 @@ def ensemble_leg(steps, graph_steps):
     halves = [synth.workload_spectrum(w) for w in members]
     points = sum(w.points for w in members)
     nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2).values()) for w in members)
+    for f, h in enumerate(halves):
+        ens.set_spectrum(h, flame=f)
+    ens.autotune(steps=10)  # points per thread per grid group
+    tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) for n1, n2 in ((128, 256), (256, 512), (512, 1024))}
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
-           "points": points, "step_bytes": nbytes}
+           "points": points, "step_bytes": nbytes, "points_per_thread": tuned}
     for mode, gs in (("graph", graph_steps), ("direct", 0)):
         ens.set_graph_steps(gs)
         for f, h in enumerate(halves):
@@ -217,6 +222,11 @@ def main():
                 d += 1
         return sim.timing_end() if time_kernels else None
 
+    # points per thread of the step kernels chosen by the library's autotuner
+    sim.set_spectrum(half)
+    sim.autotune(steps=20)
+    pts = sim.points_per_thread(w.n1, w.n2)
+
     # warm-up from the initial condition
     sim.set_spectrum(half)
     run_steps(args.warmup, False)
@@ -246,7 +256,7 @@ def main():
     per_launch = {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")}
     dom = max(per_launch, key=per_launch.get)
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, w.name)
+    traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1])
     result = {
         "metric": "flame point-steps/s fwd & adjoint, FP32 vs FP64 oracle at 1e-5; % HBM roofline",
         "value": w.points * args.steps / (ms * 1e-3),
@@ -261,7 +271,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
-                   "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}"},
+                   "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}",
+                   "points_per_thread": {"col": pts[0], "row": pts[1]}},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom}_kernel",

@@ -151,17 +151,19 @@ int flame_area_gradient(flame_plan plan, int32_t flame, int64_t n, const void* s
 int flame_synthesize(flame_plan plan, int32_t flame, const void* spec, float* phi);
 
 /* Start timing every kernel launch that flame_step and flame_diagnostics
- * queue from now on: each launch is bracketed by a pair of HIP events
- * recorded on the plan's stream (benchmarking aid; adds two event records per
- * launch). */
+ * queue from now on (benchmarking aid). The row and column step kernels that
+ * flame_step launches directly carry a start and a stop HIP event in their
+ * own dispatch (hipExtLaunchKernel), so their intervals are the kernels'
+ * execution times; the other kinds are bracketed by event records on the
+ * plan's stream. */
 int flame_timing_begin(flame_plan plan);
 
 /* Stop timing, synchronise the plan's stream and report the summed
- * durations in milliseconds and the counts, per kind: [0] row kernels,
- * [1] column kernels, [2] diagnostics kernels, [3] graph launches (each
- * covering steps_per_graph steps). Consecutive launches share their boundary
- * event, so each interval includes the launch gap before the next one.
- * ms4 and counts4 are host arrays of 4 entries. */
+ * durations in milliseconds and the counts, per kind: [0] row step kernels,
+ * [1] column step kernels, [2] diagnostics and other kernels, [3] graph
+ * launches (each covering steps_per_graph steps). Bracketed launches that
+ * follow each other share their boundary event, so their intervals include
+ * the launch gap. ms4 and counts4 are host arrays of 4 entries. */
 int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
 
 /* Points per thread of the step kernels for the flames of grid n1 x n2: each

@@ -253,13 +253,31 @@ class Timed {
   hipEvent_t start_ = nullptr;
 };
 
+// Start and stop events of one step-kernel launch while timing is on (null
+// otherwise); the launch records them in its own dispatch, so the interval is
+// the kernel's execution alone.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  KernelEvents(flame_plan p, int kind) {
+    if (!p->timing) return;
+    start = take_event(p);
+    stop = take_event(p);
+    if (!start || !stop) {
+      start = stop = nullptr;
+      return;
+    }
+    p->ev_used[kind].push_back(start);
+    p->ev_used[kind].push_back(stop);
+  }
+};
+
 // Ends a chain of timed launches (another command may follow on the stream).
 void break_chain(flame_plan p) { p->chain = nullptr; }
 
 int rebuild_w(flame_plan p, int flame) {
   const Sizes& s = p->layout.sizes[flame];
   {
-    Timed tm(p, KIND_COL);
+    Timed tm(p, KIND_OTHER);
     flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
   }
   p->w_valid[flame] = 1;
@@ -552,20 +570,20 @@ int flame_step(flame_plan p, int32_t nsteps) {
       break_chain(p);
     }
   }
+  break_chain(p);
   for (int s = 0; s < nsteps; ++s) {
     for (const Group& gr : p->groups) {
-      Timed tm(p, KIND_ROW);
+      KernelEvents ev(p, KIND_ROW);
       flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
-                        nullptr, gr.row_pts);
+                        nullptr, gr.row_pts, ev.start, ev.stop);
     }
     for (const Group& gr : p->groups) {
-      Timed tm(p, KIND_COL);
+      KernelEvents ev(p, KIND_COL);
       flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
-                        gr.col_pts);
+                        gr.col_pts, ev.start, ev.stop);
     }
     p->n += 1;
   }
-  break_chain(p);
   return last_launch("step launch");
 }
 

@@ -18,6 +18,7 @@
 // each kernel reads long contiguous runs and writes pieces of at least 64
 // bytes (2 rows x 4 columns of Q; 2 rows x 2 columns of Wp and Wm).
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -489,26 +490,35 @@ void dispatch_info(int logn, int pts, KernelLaunch* out) {
 
 }  // namespace
 
+// Step-mode launches go through the kernel tables; with timing events they
+// use hipExtLaunchKernel, which records the events in the kernel's own
+// dispatch (kernel start and end, no extra queue packets).
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const void* src, int pts) {
-  if (mode == COL_STEP && pts != ff::kPts) {
+                const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (mode == COL_STEP && (pts != ff::kPts || ev_start || ev_stop)) {
     const KernelLaunch kl = col_step_kernel(logn1, pts);
     const long long* nb = nullptr;
     const float2* s = static_cast<const float2*>(src);
     void* args[] = {&fl, &n, &nb, &s};
-    (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
+    if (ev_start || ev_stop)
+      (void)hipExtLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st, ev_start, ev_stop, 0);
+    else
+      (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
     return;
   }
   dispatch_log<ColTable, kMinLog>(logn1, mode, dim3(tiles, nfl), st, fl, n, static_cast<const float2*>(src));
 }
 
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const float* in, float* out, int pts) {
-  if (mode == ROW_STEP && pts != ff::kPts) {
+                const float* in, float* out, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  if (mode == ROW_STEP && (pts != ff::kPts || ev_start || ev_stop)) {
     const KernelLaunch kl = row_step_kernel(logn2, pts);
     const long long* nb = nullptr;
     void* args[] = {&fl, &n, &nb, &in, &out};
-    (void)hipLaunchKernel(kl.func, dim3(groups, nfl), dim3(kl.threads), args, kl.lds, st);
+    if (ev_start || ev_stop)
+      (void)hipExtLaunchKernel(kl.func, dim3(groups, nfl), dim3(kl.threads), args, kl.lds, st, ev_start, ev_stop, 0);
+    else
+      (void)hipLaunchKernel(kl.func, dim3(groups, nfl), dim3(kl.threads), args, kl.lds, st);
     return;
   }
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);

@@ -23,8 +23,10 @@ void launch_set_step(hipStream_t st, long long* counter, long long value);
 // Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
 // (fl points at their consecutive FlameDev entries in device memory). src,
 // if not null, replaces the state read by COL_FIRST and COL_SYNTH.
+// With ev_start/ev_stop (step mode only) the events mark the kernel's start and end.
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const void* src = nullptr, int pts = ff::kPts);
+                const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
+                hipEvent_t ev_stop = nullptr);
 
 // Adjoint kernels (adjoint_kernels.hip); see the modes in flame_dev.hpp.
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
@@ -33,7 +35,8 @@ void launch_adj_row(int logn2, int mode, int groups, hipStream_t st, const Flame
 
 // Row kernel over `groups` groups of B row pairs for `nfl` flames of one size.
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const float* in, float* out, int pts = ff::kPts);
+                const float* in, float* out, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
+                hipEvent_t ev_stop = nullptr);
 
 void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half);
 void launch_get_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, void* half);
