@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--diag-every", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--pts", type=int, nargs=2, metavar=("COL", "ROW"),
+                    help="points per thread of the column and row step kernels (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-flame ensemble leg (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=100,
@@ -224,7 +226,10 @@ def main():
 
     # points per thread of the step kernels chosen by the library's autotuner
     sim.set_spectrum(half)
-    sim.autotune(steps=20)
+    if args.pts:
+        sim.set_points_per_thread(w.n1, w.n2, *args.pts)
+    else:
+        sim.autotune(steps=20)
     pts = sim.points_per_thread(w.n1, w.n2)
 
     # warm-up from the initial condition
