@@ -174,13 +174,29 @@ int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
 int flame_set_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t col_pts, int32_t row_pts);
 int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t* col_pts, int32_t* row_pts);
 
-/* Choose the points per thread of each grid group's step kernels by timing:
- * for every group of equal grids, each (col_pts, row_pts) in {16, 8}^2 runs
- * one untimed and `steps` timed steps of that group (HIP events on the plan's
- * stream) and the fastest is kept. The states and the step index are saved
- * in the workspace and restored afterwards, so the call does not change the
- * simulation; it synchronises the stream. *n_configs_tried (nullable)
- * receives the number of timed configurations. */
+/* Grid on which flame_step (and its graphs) forms the quadratic term of
+ * Eq. (1) for the flames of grid n1 x n2: enable = 0, the N1 x N2 grid of the
+ * paper's augmented array (Section 3); enable = 1, a product grid of
+ * M1 = 3 N1/4 theta rows (n1 >= 128). The product of two fields truncated to
+ * |k1| <= K1 = N1/4 - 1 reaches |k1| <= 2 K1; on M1 >= 3 K1 + 1 rows none of
+ * its aliases falls inside |k1| <= K1, so the truncated term, and the step,
+ * are the same as on N1 rows up to rounding. It moves 3/4 of the
+ * intermediate data and does 3/4 of the row transforms. The column
+ * transforms then have length 3 N1/4 (radix-16 passes and a radix-6 pass, 16
+ * points per thread; col_pts applies to the N1-row grid only). Diagnostics,
+ * state I/O, synthesis and the adjoint always use the N1 x N2 grid. Default:
+ * enabled for n1 >= 128. Changing it synchronises the stream. */
+int flame_set_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);
+int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* enabled);
+
+/* Choose the step kernels of each grid group by timing. For every group of
+ * equal grids, each configuration runs one untimed and `steps` timed steps of
+ * that group (HIP events on the plan's stream), and the fastest is kept. The
+ * configurations are the N1-row grid with (col_pts, row_pts) in {16, 8}^2,
+ * and, for n1 >= 128, the product grid with row_pts in {16, 8}. The states
+ * and the step index are saved in the workspace and restored afterwards, so
+ * the call does not change the simulation; it synchronises the stream.
+ * *n_configs_tried (nullable) receives the number of timed configurations. */
 int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
 
 /* Run flame_step in graphs of `steps` steps (0: direct launches, the default).

@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   }
 
   if constexpr (MODE == ADJ_A) {
-    const StepScalars sc = step_scalars(f, n);
+    const StepScalars sc = step_scalars(f, n, f.n1);
     float2 sv[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     float2 out[8];
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     StepScalars sc{};
-    if constexpr (MODE == ADJ_C) sc = step_scalars(f, n);
+    if constexpr (MODE == ADJ_C) sc = step_scalars(f, n, f.n1);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg<ff::kPts>(kk);

@@ -72,18 +72,49 @@ constexpr PassPlan make_pass_plan(int logn, int pts = kPts) {
 
 __host__ __device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
 
-template <int LOGN, int PTS = kPts>
+template <int LOGN, int PTS_ = kPts>
 struct Shape {
+  static constexpr int PTS = PTS_;
   static constexpr PassPlan plan = make_pass_plan(LOGN, PTS);
   static constexpr int N = 1 << LOGN;
   static constexpr int G = N / PTS;
   static constexpr int NPASS = plan.npass;
+  static constexpr int NBF = NPASS;  // passes run by Fft::butterflies (all of them)
   static constexpr int LDS = N + N / 16;  // padded slots per transform
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
   static_assert(LOGN >= 4 && LOGN <= 13, "transform length must be 16..8192");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
+};
+
+// Transform of N = 6 * 2^LOGP points: the radix-PTS passes of the length-2^LOGP
+// plan run over the whole array (G = N/PTS threads, PTS points each), then a
+// last radix-6 pass with Ns = N6 = 2^LOGP. Its N6 butterflies are spread over
+// the G threads as j = t + G*it, it < IT6 (the last round partly idle); it
+// reads its inputs x[j + r*N6] from LDS and leaves output r of butterfly j,
+// the transform at position j + r*N6, in register it*6 + r. The twiddles of
+// the power-of-two passes are those of the length-2^LOGP table (they depend
+// on Ns*R only); the radix-6 pass adds exp(-2 pi i r k / N) at
+// [TW6 + (r - 1)*N6 + k], 0 < r < 6, k < N6.
+template <int LOGP, int PTS_ = kPts>
+struct Shape6 {
+  static constexpr int PTS = PTS_;
+  static constexpr PassPlan plan = make_pass_plan(LOGP, PTS);
+  static constexpr int N6 = 1 << LOGP;
+  static constexpr int N = 6 * N6;
+  static constexpr int G = N / PTS;
+  static constexpr int NBF = plan.npass;  // power-of-two passes (Fft::butterflies)
+  static constexpr int NPASS = NBF + 1;
+  static constexpr int IT6 = (N6 + G - 1) / G;
+  static constexpr int TW6 = plan.tw_size;
+  static constexpr int TW_SIZE = TW6 + 5 * N6;
+  static constexpr int LDS = N + N / 16;
+  static constexpr int radix(int p) { return p < NBF ? plan.radix[p] : 6; }
+  static constexpr int ns(int p) { return p < NBF ? plan.ns[p] : N6; }
+  static constexpr int tw_off(int p) { return p < NBF ? plan.tw_off[p] : TW6; }
+  static_assert(LOGP >= 4 && LOGP <= 10, "power-of-two part must be 16..1024");
+  static_assert(PTS == 16, "16 points per thread");
 };
 
 // ---------------------------------------------------------------- complex
@@ -252,6 +283,42 @@ __host__ __device__ __forceinline__ void dft8_outer(float2* x) {
   x[7] = csub(e3, o3);
 }
 
+// length-3 DFT: w3 = exp(-+ 2 pi i / 3) = -1/2 -+ i sqrt(3)/2
+template <bool INV>
+__host__ __device__ __forceinline__ void dft3(float2& a, float2& b, float2& c) {
+  constexpr float h = 0.86602540378443864676f;  // sqrt(3)/2
+  const float2 s = cadd(b, c), d = csub(b, c);
+  const float2 m = make_float2(a.x - 0.5f * s.x, a.y - 0.5f * s.y);
+  // forward: X1 = m - i h d, X2 = m + i h d (inverse swaps them)
+  const float2 ihd = make_float2(-h * d.y, h * d.x);
+  a = cadd(a, s);
+  b = INV ? cadd(m, ihd) : csub(m, ihd);
+  c = INV ? csub(m, ihd) : cadd(m, ihd);
+}
+
+// length-6 DFT as 3 x 2: r = 3 r1 + r2, m = m1 + 2 m2; radix-2 over r1, the
+// inner roots w6^(r2 m1), radix-3 over r2
+template <bool INV>
+__host__ __device__ __forceinline__ void dft6(float2* x) {
+  constexpr float h = 0.86602540378443864676f;
+  float2 a0 = cadd(x[0], x[3]), b0 = csub(x[0], x[3]);
+  float2 a1 = cadd(x[1], x[4]), b1 = csub(x[1], x[4]);
+  float2 a2 = cadd(x[2], x[5]), b2 = csub(x[2], x[5]);
+  // b1 *= w6 = 1/2 -+ i h, b2 *= w6^2 = -1/2 -+ i h
+  b1 = INV ? make_float2(0.5f * b1.x - h * b1.y, 0.5f * b1.y + h * b1.x)
+           : make_float2(0.5f * b1.x + h * b1.y, 0.5f * b1.y - h * b1.x);
+  b2 = INV ? make_float2(-0.5f * b2.x - h * b2.y, -0.5f * b2.y + h * b2.x)
+           : make_float2(-0.5f * b2.x + h * b2.y, -0.5f * b2.y - h * b2.x);
+  dft3<INV>(a0, a1, a2);
+  dft3<INV>(b0, b1, b2);
+  x[0] = a0;
+  x[2] = a1;
+  x[4] = a2;
+  x[1] = b0;
+  x[3] = b1;
+  x[5] = b2;
+}
+
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2* x) {
   if constexpr (R == 2) {
@@ -269,9 +336,8 @@ __host__ __device__ __forceinline__ void dft(float2* x) {
 // ------------------------------------------------------------ Stockham passes
 
 // Twiddle source reading the table in global memory on every use.
-template <int LOGN, int PTS = kPts>
-struct GlobalTw {
-  using S = Shape<LOGN, PTS>;
+template <class S>
+struct GlobalTwS {
   const float2* tw;
   int t;
   template <int P>
@@ -280,33 +346,61 @@ struct GlobalTw {
     const int k = (t + b * S::G) & (NS - 1);
     return tw[S::tw_off(P) + (r - 1) * NS + k];
   }
+  // radix-6 pass of a Shape6 transform: round `it`, butterfly j = t + G*it
+  __host__ __device__ __forceinline__ float2 get6(int it, int r) const {
+    const int j = t + it * S::G;
+    return tw[S::TW6 + (r - 1) * S::N6 + (j < S::N6 ? j : 0)];
+  }
 };
+template <int LOGN, int PTS = kPts>
+using GlobalTw = GlobalTwS<Shape<LOGN, PTS>>;
+
+template <class S>
+constexpr int six_twiddles() {
+  if constexpr (S::NPASS > S::NBF) {
+    return S::IT6 * 5;
+  } else {
+    return 0;
+  }
+}
 
 // Twiddle source holding in registers the twiddles thread t needs in the
 // passes with Ns >= MIN_NS (others are read from the table at each use; a pass
 // with Ns <= 16 has at most 16 distinct twiddles per radix index, one cache
-// line per wave). Loaded once and reused by every transform of one length in
-// a kernel. `fetch(i)` returns table entry i.
-template <int LOGN, class F, int MIN_NS = 2, int PTS = kPts>
-struct RegTw {
-  using S = Shape<LOGN, PTS>;
-  static constexpr bool cached(int p) { return p > 0 && p < S::NPASS && S::ns(p) >= MIN_NS; }
+// line per wave), and those of a radix-6 last pass. Loaded once and reused by
+// every transform of one length in a kernel. `fetch(i)` returns table entry i.
+template <class S, class F, int MIN_NS = 2>
+struct RegTwS {
+  static constexpr int PTS = S::PTS;
+  static constexpr bool cached(int p) { return p > 0 && p < S::NBF && S::ns(p) >= MIN_NS; }
   static constexpr int per_pass(int p) { return cached(p) ? PTS - PTS / S::radix(p) : 0; }
   static constexpr int offset(int p) {
     int o = 0;
     for (int q = 1; q < p; ++q) o += per_pass(q);
     return o;
   }
-  static constexpr int COUNT = offset(S::NPASS) > 0 ? offset(S::NPASS) : 1;
+  static constexpr int C6 = six_twiddles<S>();
+  static constexpr int COUNT = offset(S::NBF) + C6 > 0 ? offset(S::NBF) + C6 : 1;
   float2 w[COUNT];
   F fetch;
   int t;
 
-  __host__ __device__ __forceinline__ RegTw(const F& f, int t_) : fetch(f), t(t_) { load_pass<1>(); }
+  __host__ __device__ __forceinline__ RegTwS(const F& f, int t_) : fetch(f), t(t_) {
+    load_pass<1>();
+    if constexpr (C6 > 0) {
+#pragma unroll
+      for (int it = 0; it < S::IT6; ++it) {
+        const int j = t + it * S::G;
+#pragma unroll
+        for (int r = 1; r < 6; ++r)
+          w[offset(S::NBF) + it * 5 + (r - 1)] = fetch(S::TW6 + (r - 1) * S::N6 + (j < S::N6 ? j : 0));
+      }
+    }
+  }
 
   template <int P>
   __host__ __device__ __forceinline__ void load_pass() {
-    if constexpr (P < S::NPASS) {
+    if constexpr (P < S::NBF) {
       if constexpr (cached(P)) {
         constexpr int R = S::radix(P), NS = S::ns(P), NB = PTS / R;
 #pragma unroll
@@ -329,17 +423,21 @@ struct RegTw {
       return fetch(S::tw_off(P) + (r - 1) * NS + ((t + b * S::G) & (NS - 1)));
     }
   }
+
+  __host__ __device__ __forceinline__ float2 get6(int it, int r) const { return w[offset(S::NBF) + it * 5 + (r - 1)]; }
 };
+template <int LOGN, class F, int MIN_NS = 2, int PTS = kPts>
+using RegTw = RegTwS<Shape<LOGN, PTS>, F, MIN_NS>;
 
-template <int LOGN, bool INV, int PTS = kPts>
-struct Fft {
-  using S = Shape<LOGN, PTS>;
+template <class S, bool INV>
+struct FftS {
+  static constexpr int PTS = S::PTS;
 
-  // Pass P: thread t runs PTS/R butterflies on its registers. Butterfly b has
-  // global index j = t + b*G and inputs x[j + r*N/R] = v[b + r*PTS/R]; it
-  // applies the twiddles w(j mod Ns, r), the radix-R DFT, and sends output r
-  // to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns: into LDS, or, in the
-  // last pass (Ns * R = N), back into the same registers.
+  // Pass P < S::NBF: thread t runs PTS/R butterflies on its registers.
+  // Butterfly b has global index j = t + b*G and inputs x[j + r*N/R] =
+  // v[b + r*PTS/R]; it applies the twiddles w(j mod Ns, r), the radix-R DFT,
+  // and sends output r to position (j / Ns) * Ns * R + (j mod Ns) + r * Ns:
+  // into LDS, or, in the last pass (Ns * R = N), back into the same registers.
   // OUTER: the caller guarantees v[PTS/4 .. 3PTS/4 - 1] == 0 on entry to
   // pass 0 (inputs confined to the first and last quarter), which prunes the
   // first butterfly.
@@ -381,6 +479,37 @@ struct Fft {
     }
   }
 
+  // Radix-6 last pass of a Shape6 transform (after the power-of-two passes
+  // have written LDS and the group has synchronised): round it, butterfly
+  // j = t + G*it < N6 reads x[j + r*N6], applies exp(-+2 pi i r j / N) and the
+  // length-6 DFT, and leaves output r (position j + r*N6) in o[it*6 + r].
+  // Rounds past N6 leave zeros.
+  template <class TW, class SS = S>
+  static __host__ __device__ __forceinline__ void last6(float2 (&o)[SS::IT6 * 6], int t, const float2* lds, int stride,
+                                                       const TW& tw) {
+#pragma unroll
+    for (int it = 0; it < S::IT6; ++it) {
+      const int j = t + it * S::G;
+      float2 x[6];
+      if (it + 1 < S::IT6 || j < S::N6) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) x[r] = lds[lds_pad(j + r * S::N6) * stride];
+#pragma unroll
+        for (int r = 1; r < 6; ++r) {
+          float2 wr = tw.get6(it, r);
+          if (INV) wr.y = -wr.y;
+          x[r] = cmul(x[r], wr);
+        }
+        dft6<INV>(x);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) x[r] = make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int r = 0; r < 6; ++r) o[it * 6 + r] = x[r];
+    }
+  }
+
   static __host__ __device__ __forceinline__ void gather(float2 (&v)[PTS], int t, const float2* lds, int stride) {
 #pragma unroll
     for (int i = 0; i < PTS; ++i) v[i] = lds[lds_pad(t + S::G * i) * stride];
@@ -391,6 +520,8 @@ struct Fft {
     for (int i = 0; i < PTS; ++i) lds[lds_pad(t + S::G * i) * stride] = v[i];
   }
 };
+template <int LOGN, bool INV, int PTS = kPts>
+using Fft = FftS<Shape<LOGN, PTS>, INV>;
 
 // Host: fill the twiddle table of a length 2^logn transform with pts points
 // per thread (tw_size entries of that pass plan).
@@ -408,5 +539,22 @@ inline void build_twiddles(int logn, float2* out, int pts = kPts) {
       }
   }
 }
+
+// Host: the twiddle table of a length 6*2^logp transform (Shape6 layout): the
+// power-of-two passes' table, then exp(-2 pi i r k / N) at TW6 + (r-1)*N6 + k.
+inline void build_twiddles6(int logp, float2* out, int pts = kPts) {
+  build_twiddles(logp, out, pts);
+  const PassPlan p = make_pass_plan(logp, pts);
+  const int n6 = 1 << logp;
+  const long long n = 6LL * n6;
+  for (int r = 1; r < 6; ++r)
+    for (int k = 0; k < n6; ++k) {
+      const long long e = (long long)k * r % n;
+      const double ang = -2.0 * M_PI * double(e) / double(n);
+      out[p.tw_size + (r - 1) * n6 + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+}
+
+inline int twiddles6_size(int logp, int pts = kPts) { return make_pass_plan(logp, pts).tw_size + 5 * (1 << logp); }
 
 }  // namespace ff

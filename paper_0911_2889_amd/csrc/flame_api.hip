@@ -92,7 +92,9 @@ struct Layout {
   std::vector<size_t> off_w, off_q, off_a1, off_a2, off_part;
   size_t off_tw[flame::kMaxLog + 1];   // twiddles, 16 points per thread
   size_t off_tw8[flame::kMaxLog + 1];  // twiddles, 8 points per thread
+  size_t off_tw6[flame::kMaxLog + 1];  // twiddles of the length-3N1/4 transform (product grid)
   size_t off_dev;
+  size_t off_dev_full;  // device flame table whose W is the adjoint scratch (physical-grid W for diagnostics)
   size_t off_counter;  // step index read by graph replays
   size_t total;
 };
@@ -101,11 +103,12 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   if (!descs || nfl <= 0) return fail(FLAME_ERR_INVALID_ARG, "need at least one flame descriptor");
   L->sizes.resize(nfl);
   size_t off = 0;
-  bool need_tw[flame::kMaxLog + 1] = {};
+  bool need_tw[flame::kMaxLog + 1] = {}, need_tw6[flame::kMaxLog + 1] = {};
   for (int f = 0; f < nfl; ++f) {
     int rc = check_desc(&descs[f], &L->sizes[f]);
     if (rc) return rc;
     need_tw[L->sizes[f].logn1] = need_tw[L->sizes[f].logn2] = true;
+    need_tw6[L->sizes[f].logn1] = L->sizes[f].logn1 >= flame::kMinLogProduct;
   }
   for (int f = 0; f < nfl; ++f) {
     const Sizes& s = L->sizes[f];
@@ -131,8 +134,12 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
       const ff::PassPlan pp = ff::make_pass_plan(l, 8);
       off = align_up(off + (size_t)(pp.tw_size > 0 ? pp.tw_size : 1) * sizeof(float2));
     }
+    L->off_tw6[l] = off;
+    if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3) * sizeof(float2));
   }
   L->off_dev = off;
+  off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
+  L->off_dev_full = off;
   off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
   L->off_counter = off;
   off = align_up(off + sizeof(long long));
@@ -141,8 +148,11 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
 }
 
 struct Group {
-  int logn1, logn2, first, count, tiles, rgroups;
+  int logn1, logn2, first, count, tiles, rpairs;
   int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
+  bool product = false;                        // step on the 3N1/4-row product grid
+  int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
+  int rgroups() const { return (rows() / 2 + rpairs - 1) / rpairs; }
 };
 
 class DeviceGuard {
@@ -172,8 +182,12 @@ struct flame_plan_s {
   std::vector<flame::FlameDev> hdev;
   std::vector<std::vector<float2>> tw_host;   // host copies of the tables (16 points per thread)
   std::vector<std::vector<float2>> tw_host8;  // 8 points per thread
+  std::vector<std::vector<float2>> tw_host6;  // length-3N1/4 transforms
   flame::FlameDev* ddev = nullptr;
+  flame::FlameDev* ddev_full = nullptr;       // same flames, W in the adjoint scratch
+  std::vector<flame::FlameDev> hdev_full;
   std::vector<Group> groups;
+  std::vector<int> group_of;
   std::vector<char> w_valid;
   long long n = 0;
   // per-kernel timing (flame_timing_begin / flame_timing_end)
@@ -278,10 +292,43 @@ int rebuild_w(flame_plan p, int flame) {
   const Sizes& s = p->layout.sizes[flame];
   {
     Timed tm(p, KIND_OTHER);
-    flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+    if (p->groups[p->group_of[flame]].product)
+      flame::launch_colp(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+    else
+      flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
   }
   p->w_valid[flame] = 1;
   return last_launch("column transform launch");
+}
+
+// The step's row count lives in the device flame table (the row kernel
+// reads it); rewrite the group's entries after a change of grid. The
+// intermediates of the old grid are stale.
+int apply_rows(flame_plan p, int gi) {
+  const Group& gr = p->groups[gi];
+  for (int f = gr.first; f < gr.first + gr.count; ++f) {
+    p->hdev[f].rows = gr.rows();
+    p->w_valid[f] = 0;
+  }
+  hipError_t e = hipMemcpyAsync(p->ddev + gr.first, p->hdev.data() + gr.first, sizeof(flame::FlameDev) * gr.count,
+                                hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host table may change again
+  if (e != hipSuccess) return hip_fail(e, "flame table update");
+  return FLAME_OK;
+}
+
+void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups(), gr.count, p->stream, p->ddev + gr.first, n, nullptr,
+                    nullptr, gr.row_pts, e0, e1);
+}
+
+void launch_step_col(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (gr.product)
+    flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr, e0,
+                       e1);
+  else
+    flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
+                      gr.col_pts, e0, e1);
 }
 
 void drop_graph(flame_plan p) {
@@ -304,7 +351,8 @@ int build_graph(flame_plan p) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
       const Group& gr = p->groups[gi];
       const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
-      const flame::KernelLaunch ck = flame::col_step_kernel(gr.logn1, gr.col_pts);
+      const flame::KernelLaunch ck = gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP)
+                                                : flame::col_step_kernel(gr.logn1, gr.col_pts);
       if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
       const flame::FlameDev* fl = p->ddev + gr.first;
       long long n = s;
@@ -316,7 +364,7 @@ int build_graph(flame_plan p) {
       void* cargs[] = {&fl, &n, &nb, &src};
       hipKernelNodeParams rp{};
       rp.func = const_cast<void*>(rk.func);
-      rp.gridDim = dim3(gr.rgroups, gr.count);
+      rp.gridDim = dim3(gr.rgroups(), gr.count);
       rp.blockDim = dim3(rk.threads);
       rp.sharedMemBytes = rk.lds;
       rp.kernelParams = rargs;
@@ -423,6 +471,21 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
       }
     }
   }
+  p->tw_host6.resize(flame::kMaxLog + 1);
+  for (int l = flame::kMinLogProduct; l <= flame::kMaxLog; ++l) {
+    bool used = false;
+    for (const Sizes& s : L.sizes) used |= s.logn1 == l;
+    if (!used) continue;
+    auto& host = p->tw_host6[l];
+    host.assign(ff::twiddles6_size(l - 3), make_float2(1.f, 0.f));
+    ff::build_twiddles6(l - 3, host.data());
+    e = hipMemcpyAsync(base + L.off_tw6[l], host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice,
+                       p->stream);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "twiddle upload");
+    }
+  }
   // device flame table, ordered so that flames of one grid size are contiguous
   p->hdev.resize(n_flames);
   for (int f = 0; f < n_flames; ++f) {
@@ -441,6 +504,7 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
     fd.tw1_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn1]);
     fd.tw2_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn2]);
+    fd.tw6 = s.logn1 >= flame::kMinLogProduct ? reinterpret_cast<const float2*>(base + L.off_tw6[s.logn1]) : nullptr;
     fd.n1 = d.n1;
     fd.n2 = d.n2;
     fd.m = d.n2 / 4;
@@ -453,18 +517,36 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.t0 = d.t0;
     fd.dt = d.dt;
   }
-  // groups of consecutive flames with equal grids (one launch per group)
+  // groups of consecutive flames with equal grids (one launch per group); the
+  // step uses the product grid wherever the column kernel for it exists
+  p->group_of.resize(n_flames);
   for (int f = 0; f < n_flames; ++f) {
     const Sizes& s = L.sizes[f];
     if (!p->groups.empty() && p->groups.back().logn1 == s.logn1 && p->groups.back().logn2 == s.logn2) {
       p->groups.back().count++;
     } else {
-      p->groups.push_back(Group{s.logn1, s.logn2, f, 1, s.tiles, s.rgroups});
+      Group gr{s.logn1, s.logn2, f, 1, s.tiles, s.rpairs};
+      gr.product = s.logn1 >= flame::kMinLogProduct;
+      p->groups.push_back(gr);
     }
+    p->group_of[f] = (int)p->groups.size() - 1;
+  }
+  for (int f = 0; f < n_flames; ++f) p->hdev[f].rows = p->groups[p->group_of[f]].rows();
+  // the physical-grid W of the diagnostics goes to the adjoint scratch A1..A2
+  // (2 wq_elems, contiguous), so the step's W stays valid
+  p->hdev_full = p->hdev;
+  for (int f = 0; f < n_flames; ++f) {
+    p->hdev_full[f].Wp = p->hdev[f].A1;
+    p->hdev_full[f].Wm = p->hdev[f].A1 + 2;
+    p->hdev_full[f].rows = p->descs[f].n1;
   }
   p->ddev = reinterpret_cast<flame::FlameDev*>(base + L.off_dev);
+  p->ddev_full = reinterpret_cast<flame::FlameDev*>(base + L.off_dev_full);
   p->counter = reinterpret_cast<long long*>(base + L.off_counter);
   e = hipMemcpyAsync(p->ddev, p->hdev.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ddev_full, p->hdev_full.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice,
+                       p->stream);
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e, "flame table upload");
@@ -512,7 +594,7 @@ int flame_set_state(flame_plan p, int32_t flame, const float* phi, int64_t n) {
   p->n = n;
   flame::launch_row(s.logn2, flame::ROW_FORWARD, s.rgroups, 1, p->stream, p->ddev + flame, p->n, phi, nullptr);
   flame::launch_col(s.logn1, flame::COL_PROJECT, s.tiles, 1, p->stream, p->ddev + flame, p->n);
-  p->w_valid[flame] = 1;
+  p->w_valid[flame] = !p->groups[p->group_of[flame]].product;  // the W just written is the physical grid's
   return last_launch("set_state launch");
 }
 
@@ -574,13 +656,11 @@ int flame_step(flame_plan p, int32_t nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     for (const Group& gr : p->groups) {
       KernelEvents ev(p, KIND_ROW);
-      flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
-                        nullptr, gr.row_pts, ev.start, ev.stop);
+      launch_step_row(p, gr, p->n, ev.start, ev.stop);
     }
     for (const Group& gr : p->groups) {
       KernelEvents ev(p, KIND_COL);
-      flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, p->n, nullptr,
-                        gr.col_pts, ev.start, ev.stop);
+      launch_step_col(p, gr, p->n, ev.start, ev.stop);
     }
     p->n += 1;
   }
@@ -593,13 +673,18 @@ int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
   if (!out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
   DeviceGuard g(p->device);
   const Sizes& s = p->layout.sizes[flame];
-  if (!p->w_valid[flame]) {
+  // the area is a grid mean on the physical N1 x N2 grid: with the product
+  // grid, its W is built into the adjoint scratch and the step's W is kept
+  const bool product = p->groups[p->group_of[flame]].product;
+  if (!product && !p->w_valid[flame]) {
     rc = rebuild_w(p, flame);
     if (rc) return rc;
   }
   {
     Timed tm(p, KIND_OTHER);
-    flame::launch_row(s.logn2, flame::ROW_DIAG, s.rgroups, 1, p->stream, p->ddev + flame, p->n, nullptr, nullptr);
+    flame::FlameDev* fd = product ? p->ddev_full + flame : p->ddev + flame;
+    if (product) flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, fd, p->n);
+    flame::launch_row(s.logn2, flame::ROW_DIAG, s.rgroups, 1, p->stream, fd, p->n, nullptr, nullptr);
     double* part = p->hdev[flame].part;
     flame::launch_diag_spectral(p->stream, p->ddev, flame, s.n_spec, part + s.rgroups);
     flame::launch_diag_final(p->stream, p->ddev, flame, p->n, s.rgroups, s.n_spec, out4);
@@ -699,6 +784,41 @@ int flame_get_points_per_thread(flame_plan p, int32_t n1, int32_t n2, int32_t* c
   return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
 }
 
+int flame_set_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t enable) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  bool found = false;
+  DeviceGuard g(p->device);
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    Group& gr = p->groups[gi];
+    if ((1 << gr.logn1) != n1 || (1 << gr.logn2) != n2) continue;
+    found = true;
+    if (enable && gr.logn1 < flame::kMinLogProduct)
+      return fail(FLAME_ERR_UNSUPPORTED_SIZE, "the product grid needs n1 >= %d", 1 << flame::kMinLogProduct);
+    if (gr.product != (enable != 0)) {
+      gr.product = enable != 0;
+      rc = apply_rows(p, (int)gi);
+      if (rc) return rc;
+    }
+  }
+  if (!found) return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+  drop_graph(p);
+  return FLAME_OK;
+}
+
+int flame_get_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t* enabled) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!enabled) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  for (const Group& gr : p->groups) {
+    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
+      *enabled = gr.product ? 1 : 0;
+      return FLAME_OK;
+    }
+  }
+  return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+}
+
 int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
@@ -724,42 +844,64 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
     return fail(FLAME_ERR_HIP, "autotune: hipEventCreate failed");
   int tried = 0;
-  const int opts[2] = {16, 8};
+  struct Cfg {
+    bool product;
+    int c, r;
+  };
   for (size_t gi = 0; gi < p->groups.size(); ++gi) {
     Group& gr = p->groups[gi];
+    std::vector<Cfg> cfgs;
+    for (int c : {16, 8})
+      for (int r : {16, 8}) cfgs.push_back(Cfg{false, c, r});
+    if (gr.logn1 >= flame::kMinLogProduct)  // the product-grid column kernel has 16 points per thread
+      for (int r : {16, 8}) cfgs.push_back(Cfg{true, gr.col_pts, r});
     float best = 1e30f;
-    int best_c = gr.col_pts, best_r = gr.row_pts;
-    for (int c : opts) {
-      for (int r : opts) {
-        gr.col_pts = c;
-        gr.row_pts = r;
-        // one untimed step, then `steps` timed steps of this group alone
-        for (int s = 0; s <= steps; ++s) {
-          if (s == 1) (void)hipEventRecord(ev0, p->stream);
-          flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups, gr.count, p->stream, p->ddev + gr.first, n0,
-                            nullptr, nullptr, r);
-          flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n0,
-                            nullptr, c);
-        }
-        (void)hipEventRecord(ev1, p->stream);
-        e = hipEventSynchronize(ev1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-        if (e != hipSuccess) {
-          (void)hipEventDestroy(ev0);
-          (void)hipEventDestroy(ev1);
-          return hip_fail(e, "autotune timing");
-        }
-        ++tried;
-        if (ms < best) {
-          best = ms;
-          best_c = c;
-          best_r = r;
-        }
+    Cfg best_cfg{gr.product, gr.col_pts, gr.row_pts};
+    auto select = [&](const Cfg& cf) -> int {
+      gr.col_pts = cf.c;
+      gr.row_pts = cf.r;
+      if (gr.product != cf.product) {
+        gr.product = cf.product;
+        return apply_rows(p, (int)gi);
+      }
+      return FLAME_OK;
+    };
+    for (const Cfg& cf : cfgs) {
+      rc = select(cf);
+      for (int f = gr.first; rc == FLAME_OK && f < gr.first + gr.count; ++f)
+        if (!p->w_valid[f]) rc = rebuild_w(p, f);
+      if (rc) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        return rc;
+      }
+      // one untimed step, then `steps` timed steps of this group alone
+      for (int s = 0; s <= steps; ++s) {
+        if (s == 1) (void)hipEventRecord(ev0, p->stream);
+        launch_step_row(p, gr, n0);
+        launch_step_col(p, gr, n0);
+      }
+      (void)hipEventRecord(ev1, p->stream);
+      e = hipEventSynchronize(ev1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        return hip_fail(e, "autotune timing");
+      }
+      ++tried;
+      if (ms < best) {
+        best = ms;
+        best_cfg = cf;
       }
     }
-    gr.col_pts = best_c;
-    gr.row_pts = best_r;
+    rc = select(best_cfg);
+    if (rc) {
+      (void)hipEventDestroy(ev0);
+      (void)hipEventDestroy(ev1);
+      return rc;
+    }
   }
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);

@@ -25,12 +25,13 @@ struct FlameDev {
   const float2* tw2;   // twiddles of the length-N2 transform, 16 points per thread
   const float2* tw1_8; // the same for 8 points per thread
   const float2* tw2_8;
+  const float2* tw6;   // twiddles of the length-3N1/4 transform (product grid), or null
   double* part;        // per-workgroup partial sums of the diagnostics
   int n1, n2;
   int m;               // stored k2 columns, N2/4
   int h1;              // stored k1 slots, N1/2
   int tshift;          // log2 of the tile width TQ of Q, A1, A2
-  int pad_;
+  int rows;            // theta rows of the step's product grid: 3 N1/4, or N1
   float s1, s2;        // axis scales of kappa
   float gamma;
   float pad2_;
@@ -59,6 +60,28 @@ struct ColCfg {
   static constexpr int QS = ff::ilog2c(TQ);
   static constexpr int THREADS = T * G;
   static constexpr int LDS_BYTES = ff::Shape<LOGN1>::LDS * T * 8;
+};
+
+// Product grid of the step: |grad Phi|^2 is formed on M1 = 3 N1/4 theta rows
+// instead of N1. The product of two fields with |k1| <= K1 = N1/4 - 1 has
+// |k1| <= 2 K1, and on M1 >= 3 K1 + 1 rows no alias of it lands in
+// |k1| <= K1, so the truncated quadratic term is the same as on N1 rows up to
+// rounding. The column transforms have length M1 = 6 * N1/8 (Shape6: radix-16
+// passes, then radix 6). Used for N1 >= 128.
+constexpr int kMinLogProduct = 7;
+
+template <int LOGN1>
+struct ColCfgP {
+  using S = ff::Shape6<LOGN1 - 3, 16>;
+  static constexpr int M1 = S::N;
+  static constexpr int G = S::G;
+  static constexpr int G16 = ff::Shape<LOGN1>::G;
+  static constexpr int T = col_tile_for(G16);
+  static constexpr int TQ = q_tile_for(G16);
+  static constexpr int QS = ff::ilog2c(TQ);
+  static constexpr int THREADS = T * G;
+  static constexpr int LDS_BYTES = S::LDS * T * 8;
+  static_assert(THREADS % 64 == 0, "whole waves");
 };
 
 // Row kernel: B = max(1, 16*256/N2) row pairs per workgroup, interleaved.

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
-    if constexpr (MODE == COL_STEP) sc = step_scalars(f, n);
+    if constexpr (MODE == COL_STEP) sc = step_scalars(f, n, f.n1);
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     const float kap2c = f.s2 * (float)m;
 #pragma unroll
@@ -185,9 +185,10 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
   const int tid = threadIdx.x;
   const int p = tid % B, t = tid / B;
   const int pair = xcd_swizzle(blockIdx.x, gridDim.x) * B + p;
-  const bool live = pair < f.n1 / 2;
+  // the step runs on the product grid's rows; the other modes on the grid's
+  const int n1 = MODE == ROW_STEP ? f.rows : f.n1, ts = f.tshift, mcols = f.m;
+  const bool live = pair < n1 / 2;
   const int ja = 2 * pair, jb = 2 * pair + 1;
-  const int n1 = f.n1, ts = f.tshift, mcols = f.m;
   float2* my = lds + p;
   const auto tw2 = KernelTw<LOGN2, PTS>::make(PTS == 8 ? f.tw2_8 : f.tw2, t);
   gf2* const Wp = glob(f.Wp);
@@ -306,6 +307,146 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
       st(Q + tiled(ja, k, n1, ts), qa);
       st(Q + tiled(jb, k, n1, ts), qb);
+    }
+  }
+}
+
+// Column kernel of the step on the product grid (M1 = 3 N1/4 theta rows, see
+// ColCfgP): the same work as col_kernel<COL_STEP> (or <COL_FIRST>), with the
+// length-M1 transforms of ff::Shape6. The forward transform leaves the
+// spectrum in the radix-6 output map (position j + r*N6, j = t + G*it); the
+// update is applied there, the kept modes (|k1| <= K1: r in {0, 1}, r in
+// {4, 5} except position 4*N6, which is k1 = -(K1 + 1)) go through LDS back
+// to the natural map t + G*i (the k2 = 0 column symmetrised on the way), the
+// state is stored from that map, and the two inverse transforms start there.
+template <int LOGN1, int MODE>
+__global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
+    colp_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
+  if (nbase) n += *nbase;
+  using Cfg = ColCfgP<LOGN1>;
+  using S6 = typename Cfg::S;
+  constexpr int LOGP = LOGN1 - 3;
+  constexpr int G = S6::G, T = Cfg::T, M1 = S6::N, N6 = S6::N6, IT = S6::IT6, N1 = 1 << LOGN1;
+  constexpr int TQ = Cfg::TQ, QS = Cfg::QS;
+  constexpr int K1 = N1 / 4 - 1;
+  extern __shared__ float2 lds[];
+  const FlameDev f = fls[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int c = tid % T, t = tid / T;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int m = tile * T + c;
+  const bool live = m < f.m;
+  float2* my = lds + c;
+  gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
+  gf2* const Sc = glob(MODE == COL_FIRST && src ? const_cast<float2*>(src) : f.S) + (size_t)m * f.h1 + N1 / 4;
+  const auto tw = KernelTw6<LOGP>::make(f.tw6, t);
+  // k1 of natural position p, and whether it is kept (|k1| <= K1)
+  auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
+  auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
+
+  float2 sv[16];  // spectrum at natural positions t + G*i, zero outside the box
+  if constexpr (MODE == COL_STEP) {
+    float2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
+    // the old state in the radix-6 output map, loaded before the transform
+    constexpr int KR[4] = {0, 1, 4, 5};
+    float2 old[IT][4];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + G * it;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pos = j + KR[q] * N6;
+        const bool ok = live && j < N6 && kept_at(pos);
+        old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+      }
+    }
+    float2 o[IT * 6];
+    fft6<LOGP, false>(v, o, t, my, T, tw);
+    const StepScalars sc = step_scalars(f, n, M1);
+    const float kap2c = f.s2 * (float)m;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + G * it;
+      if (j < N6) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          const int pos = j + r * N6;
+          float2 val = make_float2(0.f, 0.f);
+          if (r != 2 && r != 3 && kept_at(pos)) {
+            const int q = r < 2 ? r : r - 2;
+            const float kap1 = f.s1 * (float)k1_of(pos);
+            const float kk2 = kap1 * kap1 + kap2c * kap2c;
+            const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
+            val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x), e * (old[it][q].y + sc.a * o[it * 6 + r].y));
+          }
+          my[ff::lds_pad(pos) * T] = val;
+        }
+      }
+    }
+    __syncthreads();
+    if (tile == 0) {
+      // symmetrise column k2 = 0 (c == 0): k1 > 0 conjugated onto -k1, Im at k1 = 0 zeroed
+      if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int k1 = t + G * i;
+          if (k1 >= 1 && k1 <= K1) my[ff::lds_pad(M1 - k1) * T] = ff::cconj(my[ff::lds_pad(k1) * T]);
+        }
+        if (t == 0) my[0].y = 0.f;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sv[i] = my[ff::lds_pad(t + G * i) * T];
+    __syncthreads();  // the LDS is reused by the inverse transforms
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int pos = t + G * i;
+        if (kept_at(pos)) st(Sc + k1_of(pos), sv[i]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int pos = t + G * i;
+      sv[i] = live && kept_at(pos) ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+    }
+  }
+
+  const float kap2 = f.s2 * (float)m;
+  gf2* const Wpc = glob(f.Wp);
+  gf2* const Wmc = glob(f.Wm);
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    // pass 0: Z+ = IFFT_k1((i kappa1 - kappa2) Phi~) -> Wp; pass 1: conj(IFFT_k1((i kappa1 + kappa2) Phi~)) -> Wm
+    const float sg = pass == 0 ? -1.f : 1.f;
+    float2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float kap1 = f.s1 * (float)k1_of(t + G * i);
+      v[i] = make_float2(-kap1 * sv[i].y + sg * kap2 * sv[i].x, kap1 * sv[i].x + sg * kap2 * sv[i].y);
+    }
+    float2 o[IT * 6];
+    fft6<LOGP, true>(v, o, t, my, T, tw);
+    if (live) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int j = t + G * it;
+        if (j < N6) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const int j1 = j + r * N6;
+            if (pass == 0)
+              st(Wpc + w_index(j1, m, f.m), o[it * 6 + r]);
+            else
+              st(Wmc + w_index(j1, m, f.m), ff::cconj(o[it * 6 + r]));
+          }
+        }
+      }
     }
   }
 }
@@ -468,6 +609,27 @@ struct RowTable {
   }
 };
 
+template <int LOGN>
+struct ColPTable {
+  static KernelLaunch step_kernel(int mode) {
+    if (mode == COL_FIRST)
+      return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST>), ColCfgP<LOGN>::THREADS,
+                          ColCfgP<LOGN>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP>), ColCfgP<LOGN>::THREADS,
+                        ColCfgP<LOGN>::LDS_BYTES};
+  }
+};
+
+template <int L>
+void dispatch_colp(int logn, int mode, KernelLaunch* out) {
+  if constexpr (L <= kMaxLog) {
+    if (logn == L)
+      *out = ColPTable<L>::step_kernel(mode);
+    else
+      dispatch_colp<L + 1>(logn, mode, out);
+  }
+}
+
 template <template <int> class Tab, int L, class... A>
 void dispatch_log(int logn, A... args) {
   if constexpr (L <= kMaxLog) {
@@ -522,6 +684,25 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
     return;
   }
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
+}
+
+KernelLaunch colp_kernel_info(int logn1, int mode) {
+  KernelLaunch out{nullptr, 0, 0};
+  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, &out);
+  return out;
+}
+
+void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
+                 const void* src, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const KernelLaunch kl = colp_kernel_info(logn1, mode);
+  if (!kl.func) return;
+  const long long* nb = nullptr;
+  const float2* s = static_cast<const float2*>(src);
+  void* args[] = {&fl, &n, &nb, &s};
+  if (ev_start || ev_stop)
+    (void)hipExtLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st, ev_start, ev_stop, 0);
+  else
+    (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
 }
 
 KernelLaunch col_step_kernel(int logn1, int pts) {

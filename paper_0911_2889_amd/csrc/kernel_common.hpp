@@ -76,6 +76,39 @@ struct KernelTw {
   }
 };
 
+// Twiddles of a length 6*2^LOGP transform, cached in registers.
+template <int LOGP>
+struct KernelTw6 {
+  using Type = ff::RegTwS<ff::Shape6<LOGP, 16>, GlobalFetch, kTwCacheMinNs>;
+  static __device__ __forceinline__ Type make(const float2* tw, int t) { return Type(GlobalFetch{(const gf2*)tw}, t); }
+};
+
+// Transform of length 6*2^LOGP (ff::Shape6): on entry v[i] holds the input at
+// position t + G*i; on exit o[it*6 + r] holds the output at position
+// j + r*N6, j = t + G*it (zero where j >= N6). Contains workgroup barriers
+// (all threads must call it), the last one after the radix-6 pass has read
+// LDS, so the caller may write LDS at once.
+template <int LOGP>
+using Out6 = float2[ff::Shape6<LOGP, 16>::IT6 * 6];
+
+template <int LOGP, bool INV, class TW, int P = 0>
+__device__ __forceinline__ void fft6(float2 (&v)[16], Out6<LOGP>& o, int t, float2* lds, int stride, const TW& tw) {
+  using S = ff::Shape6<LOGP, 16>;
+  using F = ff::FftS<S, INV>;
+  if constexpr (P < S::NBF) {
+    F::template butterflies<P, TW, false>(v, t, lds, stride, tw);
+    __syncthreads();
+    if constexpr (P + 1 < S::NBF) {
+      F::gather(v, t, lds, stride);
+      __syncthreads();
+    }
+    fft6<LOGP, INV, TW, P + 1>(v, o, t, lds, stride, tw);
+  } else {
+    F::last6(o, t, lds, stride, tw);
+    __syncthreads();
+  }
+}
+
 struct StepScalars {
   float a;    // dt * c_n / P, multiplies the raw transform of |grad Phi|^2
   float i1;   // int_{t_n}^{t_{n+1}} dt / r0
@@ -85,12 +118,15 @@ struct StepScalars {
 // r0(t) = t (Section 2): c_n = 1/(2 t_n^2), I1 = ln(t_{n+1}/t_n),
 // I2 = 1/t_n - 1/t_{n+1}. The time is formed in double; the scalars need only
 // float accuracy.
-__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n) {
+// `rows` is the number of theta rows of the grid the quadratic term was
+// formed on (N1, or 3 N1/4 on the product grid): the forward transforms are
+// unnormalised, so a carries 1/(rows * N2).
+__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n, int rows) {
   const float t = (float)(f.t0 + (double)n * f.dt);
   const float dt = (float)f.dt;
   const float x = dt / t;
   StepScalars s;
-  s.a = 0.5f * x / (t * (float)f.n1 * (float)f.n2);
+  s.a = 0.5f * x / (t * (float)rows * (float)f.n2);
   s.i1 = log1pf(x);
   s.i2 = x / (t + dt);
   return s;

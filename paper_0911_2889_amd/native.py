@@ -22,7 +22,8 @@ EXPORTS = (
     "flame_get_spectrum", "flame_set_state", "flame_get_state", "flame_state_modified",
     "flame_step_index", "flame_step", "flame_diagnostics", "flame_adjoint_step", "flame_area_gradient",
     "flame_synthesize", "flame_timing_begin", "flame_timing_end", "flame_set_graph_steps",
-    "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_autotune", "flame_destroy",
+    "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
+    "flame_get_product_grid", "flame_autotune", "flame_destroy",
     "flame_last_error",
 )
 
@@ -78,6 +79,8 @@ def load():
         "flame_set_points_per_thread": [P, i32, i32, i32, i32],
         "flame_get_points_per_thread": [P, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "flame_autotune": [P, i32, ctypes.POINTER(i32)],
+        "flame_set_product_grid": [P, i32, i32, i32],
+        "flame_get_product_grid": [P, i32, i32, ctypes.POINTER(i32)],
         "flame_timing_begin": [P],
         "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "flame_destroy": [P],

@@ -153,6 +153,16 @@ class FlameEnsemble:
                                                           ctypes.byref(r)))
         return c.value, r.value
 
+    def set_product_grid(self, n1, n2, enable):
+        """Form the quadratic term on 3*n1/4 theta rows (True) or on n1 rows (False)
+        for the flames of grid n1 x n2; the results agree to rounding."""
+        native.check(self.lib.flame_set_product_grid(self.plan, int(n1), int(n2), int(bool(enable))))
+
+    def product_grid(self, n1, n2):
+        v = ctypes.c_int32()
+        native.check(self.lib.flame_get_product_grid(self.plan, int(n1), int(n2), ctypes.byref(v)))
+        return bool(v.value)
+
     def autotune(self, steps=20):
         """Time every points-per-thread choice per grid group and keep the fastest;
         the simulation state is unchanged. Returns the number of timed configurations."""

@@ -1,6 +1,6 @@
 // Host-side drive of the device FFT engine, thread by thread, for CPU tests.
 //
-// Reads "logn inv stride outer pts" then 2^logn complex64 values from stdin (binary),
+// Reads "logn inv stride outer pts six" then the complex64 values from stdin (binary),
 // runs the Stockham passes of ff::Fft with every thread of one group emulated
 // in turn (all threads finish a pass before any gathers), and writes the
 // 2^logn transformed values to stdout. The LDS array is shared by `stride`
@@ -65,6 +65,65 @@ void run(std::vector<float2>& x, int stride, bool outer) {
     for (int i = 0; i < PTS; ++i) x[t + S::G * i] = v[t].a[i];
 }
 
+// Shape6 (N = 6 * 2^LOGP): the power-of-two passes, then the radix-6 pass
+// read from LDS; output r of round it lands at position j + r*N6.
+template <int LOGP, bool INV, int P>
+void passes6(std::vector<Regs<16>>& v, std::vector<std::vector<float2>>& o, float2* lds, int stride,
+             const float2* tw, bool cached) {
+  using S = ff::Shape6<LOGP, 16>;
+  using F = ff::FftS<S, INV>;
+  if constexpr (P < S::NBF) {
+    for (int t = 0; t < S::G; ++t) {
+      if (cached) {
+        ff::RegTwS<S, TableFetch, 2> rt(TableFetch{tw}, t);
+        F::template butterflies<P, decltype(rt), false>(v[t].a, t, lds, stride, rt);
+      } else {
+        F::template butterflies<P, ff::GlobalTwS<S>, false>(v[t].a, t, lds, stride, ff::GlobalTwS<S>{tw, t});
+      }
+    }
+    if constexpr (P + 1 < S::NBF) {
+      for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
+    }
+    passes6<LOGP, INV, P + 1>(v, o, lds, stride, tw, cached);
+  } else {
+    for (int t = 0; t < S::G; ++t) {
+      float2 out[S::IT6 * 6];
+      if (cached) {
+        ff::RegTwS<S, TableFetch, 2> rt(TableFetch{tw}, t);
+        F::last6(out, t, lds, stride, rt);
+      } else {
+        F::last6(out, t, lds, stride, ff::GlobalTwS<S>{tw, t});
+      }
+      o[t].assign(out, out + S::IT6 * 6);
+    }
+  }
+}
+
+template <int LOGP, bool INV>
+void run6(std::vector<float2>& x, int stride) {
+  using S = ff::Shape6<LOGP, 16>;
+  std::vector<float2> tw(S::TW_SIZE + 1);
+  ff::build_twiddles6(LOGP, tw.data(), 16);
+  std::vector<Regs<16>> v(S::G);
+  for (int t = 0; t < S::G; ++t)
+    for (int i = 0; i < 16; ++i) v[t].a[i] = x[t + S::G * i];
+  std::vector<float2> lds(size_t(S::LDS) * stride, make_float2(1e30f, 1e30f));
+  std::vector<std::vector<float2>> o(S::G);
+  passes6<LOGP, INV, 0>(v, o, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  std::vector<int> seen(S::N, 0);
+  for (int t = 0; t < S::G; ++t)
+    for (int it = 0; it < S::IT6; ++it) {
+      const int j = t + S::G * it;
+      if (j >= S::N6) continue;
+      for (int r = 0; r < 6; ++r) {
+        x[j + r * S::N6] = o[t][it * 6 + r];
+        ++seen[j + r * S::N6];
+      }
+    }
+  for (int i = 0; i < S::N; ++i)
+    if (seen[i] != 1) x[i] = make_float2(1e30f, 1e30f);  // every position exactly once
+}
+
 template <int LOGN>
 bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer, int pts) {
   if constexpr (LOGN > 13) {
@@ -86,14 +145,39 @@ bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer,
   }
 }
 
+template <int LOGP>
+bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride) {
+  if constexpr (LOGP > 10) {
+    return false;
+  } else {
+    if (logp != LOGP) return dispatch6<LOGP + 1>(logp, inv, x, stride);
+    if (inv)
+      run6<LOGP, true>(x, stride);
+    else
+      run6<LOGP, false>(x, stride);
+    return true;
+  }
+}
+
 }  // namespace
 
+// Header: logn inv stride outer pts six. With six = 1 the length is
+// 6 * 2^logn (Shape6, 16 points per thread, outer unused).
 int main() {
-  int hdr[5];
-  if (fread(hdr, sizeof(int), 5, stdin) != 5) return 2;
-  const int logn = hdr[0], inv = hdr[1], stride = hdr[2], outer = hdr[3], pts = hdr[4];
+  int hdr[6];
+  if (fread(hdr, sizeof(int), 6, stdin) != 6) return 2;
+  const int logn = hdr[0], inv = hdr[1], stride = hdr[2], outer = hdr[3], pts = hdr[4], six = hdr[5];
   if (pts != 8 && pts != 16) return 3;
-  if (logn < 4 || logn > 13 || stride < 1) return 3;
+  if (stride < 1) return 3;
+  if (six) {
+    if (logn < 4 || logn > 10 || pts != 16) return 3;
+    std::vector<float2> x(size_t(6) << logn);
+    if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
+    if (!dispatch6<4>(logn, inv, x, stride)) return 5;
+    fwrite(x.data(), sizeof(float2), x.size(), stdout);
+    return 0;
+  }
+  if (logn < 4 || logn > 13) return 3;
   std::vector<float2> x(size_t(1) << logn);
   if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
   if (outer)  // the pruned first pass assumes the middle half of the input is zero

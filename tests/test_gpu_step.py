@@ -213,6 +213,8 @@ def test_points_per_thread_variants_match_oracle(flame, n1, n2, cp, rp):
     w = small_workload(n1, n2, seed=n1 + 3 * n2 + cp + rp, amp=0.05, t0=5.0, dt=0.2)
     half = synth.workload_spectrum(w)
     sim = make_sim(flame, w)
+    if n1 >= 128:
+        sim.set_product_grid(n1, n2, False)  # col_pts applies to the N1-row grid
     sim.set_points_per_thread(n1, n2, cp, rp)
     assert sim.points_per_thread(n1, n2) == (cp, rp)
     sim.set_spectrum(half)
@@ -220,3 +222,60 @@ def test_points_per_thread_variants_match_oracle(flame, n1, n2, cp, rp):
     got = sim.spectrum().cpu().numpy()
     ref = oracle_trajectory(half, oracle_params(w), [3])[3]
     assert rel_l2(got, ref) < 2e-6
+
+
+@pytest.mark.parametrize("n1,n2", [(128, 256), (256, 64), (512, 1024), (1024, 128), (2048, 64), (4096, 32),
+                                   (128, 4096)])
+def test_product_grid_matches_oracle_and_physical_grid(flame, n1, n2):
+    """The quadratic term formed on 3*N1/4 theta rows: one step and 20 steps
+    against the oracle (which forms it on the N1 x N2 augmented grid of
+    Section 3), and against the same run on N1 rows, with the row kernel's
+    16 and 8 points per thread."""
+    w = small_workload(n1, n2, seed=n1 + 5 * n2, amp=0.1, t0=5.0, dt=0.2)
+    half = synth.workload_spectrum(w)
+    p = oracle_params(w)
+    refs = oracle_trajectory(half, p, [1, 20])
+    assert rel_l2(refs[1], half) > 1e-3
+    runs = {}
+    for product in (True, False):
+        for rp in (16, 8):
+            sim = make_sim(flame, w)
+            assert sim.product_grid(n1, n2)  # the default for n1 >= 128
+            sim.set_product_grid(n1, n2, product)
+            sim.set_points_per_thread(n1, n2, 16, rp)
+            assert sim.product_grid(n1, n2) == product
+            sim.set_spectrum(half)
+            sim.step(1)
+            one = sim.spectrum().cpu().numpy()
+            sim.step(19)
+            twenty = sim.spectrum().cpu().numpy()
+            assert rel_l2(one, refs[1]) < 1e-6, (product, rp)
+            assert rel_l2(twenty, refs[20]) < 1e-5, (product, rp)
+            runs[(product, rp)] = twenty
+    assert rel_l2(runs[(True, 16)], runs[(False, 16)]) < 2e-6
+
+
+def test_product_grid_switches_mid_run_and_keeps_diagnostics(flame):
+    """Switching grids between steps rebuilds the intermediates; diagnostics
+    (a grid mean on the N1 x N2 grid) do not disturb the product grid's step."""
+    n1, n2 = 256, 512
+    w = small_workload(n1, n2, seed=77, amp=0.1, t0=5.0, dt=0.2)
+    half = synth.workload_spectrum(w)
+    p = oracle_params(w)
+    refs = oracle_trajectory(half, p, [10, 20, 30])
+    sim = make_sim(flame, w)
+    sim.set_spectrum(half)
+    sim.step(10)
+    d = sim.diagnostics()
+    ref_area = oracle.diagnostics(oracle.half_to_full(refs[10], n1, n2), p, 10)[2]
+    assert abs(d["area_excess"] - ref_area) < 2e-5 * abs(ref_area)
+    sim.step(10)
+    assert rel_l2(sim.spectrum().cpu().numpy(), refs[20]) < 1e-5
+    sim.set_product_grid(n1, n2, False)
+    sim.step(5)
+    sim.set_product_grid(n1, n2, True)
+    sim.step(5)
+    assert rel_l2(sim.spectrum().cpu().numpy(), refs[30]) < 1e-5
+    with pytest.raises(RuntimeError):
+        small = make_sim(flame, small_workload(64, 128, 1))
+        small.set_product_grid(64, 128, True)

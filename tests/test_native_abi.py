@@ -92,9 +92,23 @@ def test_fft_engine_on_host_matches_numpy(tmp_path):
                 x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
                 if outer:
                     x[n // 4: 3 * n // 4] = 0
-                out = subprocess.run([str(exe)], input=struct.pack("5i", logn, inv, stride, outer, pts) + x.tobytes(),
+                out = subprocess.run([str(exe)], input=struct.pack("6i", logn, inv, stride, outer, pts, 0) + x.tobytes(),
                                      capture_output=True, check=True).stdout
                 y = np.frombuffer(out, dtype=np.complex64)
                 xd = x.astype(np.complex128)
                 ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
                 assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logn, inv, stride, outer, pts)
+    # length 6 * 2^logp (radix-16 passes, then the radix-6 pass read from LDS):
+    # every output position written exactly once and equal to the DFT
+    for logp in range(4, 11):
+        for inv in (0, 1):
+            for stride in (1, 2, 3):
+                n = 6 << logp
+                rng = np.random.default_rng(logp * 7 + inv)
+                x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+                out = subprocess.run([str(exe)], input=struct.pack("6i", logp, inv, stride, 0, 16, 1) + x.tobytes(),
+                                     capture_output=True, check=True).stdout
+                y = np.frombuffer(out, dtype=np.complex64)
+                xd = x.astype(np.complex128)
+                ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
+                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logp, inv, stride)
