@@ -24,17 +24,20 @@ KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889
                   "paper_0911_2889_amd/csrc/flame_dev.hpp", "paper_0911_2889_amd/csrc/kernel_common.hpp")
 
 
-def algorithmic_bytes(n1, n2):
-    """Bytes each kernel of one step must move (FP32 complex = 8 bytes).
+def algorithmic_bytes(n1, n2, rows=None):
+    """Bytes each kernel of one step must move (FP32 complex = 8 bytes), with
+    the quadratic term formed on `rows` theta rows (n1, or 3*n1/4 on the
+    product grid; default n1).
 
-    row: read the column-transformed gradient spectrum N1 x (2K2+1), write
-         the row transform of |grad Phi|^2, N1 x (K2+1);
-    col: read that N1 x (K2+1), read and write the state (2K1+1) x (K2+1),
-         write the next gradient spectrum N1 x (2K2+1).
+    row: read the column-transformed gradient spectrum rows x (2K2+1), write
+         the row transform of |grad Phi|^2, rows x (K2+1);
+    col: read that rows x (K2+1), read and write the state (2K1+1) x (K2+1),
+         write the next gradient spectrum rows x (2K2+1).
     """
+    rows = n1 if rows is None else rows
     k1, k2 = (n1 - 1) // 4, (n2 - 1) // 4
-    row = 8 * (n1 * (2 * k2 + 1) + n1 * (k2 + 1))
-    col = 8 * (n1 * (k2 + 1) + 2 * (2 * k1 + 1) * (k2 + 1) + n1 * (2 * k2 + 1))
+    row = 8 * (rows * (2 * k2 + 1) + rows * (k2 + 1))
+    col = 8 * (rows * (k2 + 1) + 2 * (2 * k1 + 1) * (k2 + 1) + rows * (2 * k2 + 1))
     return {"row": row, "col": col}
 
 
@@ -46,16 +49,17 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, pts):
+def measured_traffic(kernel, workload, pts, rows):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources and the same points-per-thread
-    variant of the kernel; else None."""
+    was taken on the current kernel sources and the same variant of the kernel
+    (points per thread, product-grid rows); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_digest") != source_digest() or rec.get("points_per_thread") != pts:
+    if (rec.get("source_digest") != source_digest() or rec.get("points_per_thread") != pts
+            or rec.get("rows") != rows):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -136,11 +140,15 @@ def ensemble_leg(steps, graph_steps):
     ens = FlameEnsemble(descs)
     halves = [synth.workload_spectrum(w) for w in members]
     points = sum(w.points for w in members)
-    nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2).values()) for w in members)
+    nbytes = None  # set after autotuning, which picks each group's grid
     for f, h in enumerate(halves):
         ens.set_spectrum(h, flame=f)
     ens.autotune(steps=10)  # points per thread per grid group
-    tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) for n1, n2 in ((128, 256), (256, 512), (512, 1024))}
+    grids = ((128, 256), (256, 512), (512, 1024))
+    tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) + ["product" if ens.product_grid(n1, n2) else "n1"]
+             for n1, n2 in grids}
+    nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2, 3 * w.n1 // 4 if ens.product_grid(w.n1, w.n2) else w.n1).values())
+                 for w in members)
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
            "points": points, "step_bytes": nbytes, "points_per_thread": tuned}
     for mode, gs in (("graph", graph_steps), ("direct", 0)):
@@ -174,6 +182,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--pts", type=int, nargs=2, metavar=("COL", "ROW"),
                     help="points per thread of the column and row step kernels (default: autotuned)")
+    ap.add_argument("--grid", choices=("product", "n1"),
+                    help="form the quadratic term on 3*N1/4 rows or on N1 rows (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-flame ensemble leg (0 skips it)")
     ap.add_argument("--adjoint-steps", type=int, default=100,
@@ -226,11 +236,15 @@ def main():
 
     # points per thread of the step kernels chosen by the library's autotuner
     sim.set_spectrum(half)
-    if args.pts:
-        sim.set_points_per_thread(w.n1, w.n2, *args.pts)
+    if args.pts or args.grid:
+        if args.grid:
+            sim.set_product_grid(w.n1, w.n2, args.grid == "product")
+        if args.pts:
+            sim.set_points_per_thread(w.n1, w.n2, *args.pts)
     else:
         sim.autotune(steps=20)
     pts = sim.points_per_thread(w.n1, w.n2)
+    rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
 
     # warm-up from the initial condition
     sim.set_spectrum(half)
@@ -257,11 +271,11 @@ def main():
     torch.cuda.synchronize()
     final_diag = diag_buf[0].cpu().tolist()
 
-    nbytes = algorithmic_bytes(w.n1, w.n2)
+    nbytes = algorithmic_bytes(w.n1, w.n2, rows)
     per_launch = {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")}
     dom = max(per_launch, key=per_launch.get)
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1])
+    traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1], rows)
     result = {
         "metric": "flame point-steps/s fwd & adjoint, FP32 vs FP64 oracle at 1e-5; % HBM roofline",
         "value": w.points * args.steps / (ms * 1e-3),
@@ -277,7 +291,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
                    "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}",
-                   "points_per_thread": {"col": pts[0], "row": pts[1]}},
+                   "points_per_thread": {"col": pts[0], "row": pts[1]}, "product_rows": rows},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom}_kernel",

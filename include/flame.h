@@ -182,8 +182,8 @@ int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t
  * its aliases falls inside |k1| <= K1, so the truncated term, and the step,
  * are the same as on N1 rows up to rounding. It moves 3/4 of the
  * intermediate data and does 3/4 of the row transforms. The column
- * transforms then have length 3 N1/4 (radix-16 passes and a radix-6 pass, 16
- * points per thread; col_pts applies to the N1-row grid only). Diagnostics,
+ * transforms then have length 3 N1/4 (radix-col_pts passes and a radix-6
+ * pass). Diagnostics,
  * state I/O, synthesis and the adjoint always use the N1 x N2 grid. Default:
  * enabled for n1 >= 128. Changing it synchronises the stream. */
 int flame_set_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);
@@ -192,8 +192,8 @@ int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* ena
 /* Choose the step kernels of each grid group by timing. For every group of
  * equal grids, each configuration runs one untimed and `steps` timed steps of
  * that group (HIP events on the plan's stream), and the fastest is kept. The
- * configurations are the N1-row grid with (col_pts, row_pts) in {16, 8}^2,
- * and, for n1 >= 128, the product grid with row_pts in {16, 8}. The states
+ * configurations are (col_pts, row_pts) in {16, 8}^2 on the N1-row grid
+ * and, for n1 >= 128, on the product grid. The states
  * and the step index are saved in the workspace and restored afterwards, so
  * the call does not change the simulation; it synchronises the stream.
  * *n_configs_tried (nullable) receives the number of timed configurations. */

@@ -39,7 +39,7 @@ namespace {
 __device__ __forceinline__ float efactor(const FlameDev& f, const StepScalars& sc, int k1, float kap2) {
   const float kap1 = f.s1 * (float)k1;
   const float kk2 = kap1 * kap1 + kap2 * kap2;
-  return expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
+  return growth_factor(kk2, sc, f.gamma);
 }
 
 }  // namespace

@@ -114,7 +114,7 @@ struct Shape6 {
   static constexpr int ns(int p) { return p < NBF ? plan.ns[p] : N6; }
   static constexpr int tw_off(int p) { return p < NBF ? plan.tw_off[p] : TW6; }
   static_assert(LOGP >= 4 && LOGP <= 10, "power-of-two part must be 16..1024");
-  static_assert(PTS == 16, "16 points per thread");
+  static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
 
 // ---------------------------------------------------------------- complex

@@ -93,6 +93,7 @@ struct Layout {
   size_t off_tw[flame::kMaxLog + 1];   // twiddles, 16 points per thread
   size_t off_tw8[flame::kMaxLog + 1];  // twiddles, 8 points per thread
   size_t off_tw6[flame::kMaxLog + 1];  // twiddles of the length-3N1/4 transform (product grid)
+  size_t off_tw6_8[flame::kMaxLog + 1];
   size_t off_dev;
   size_t off_dev_full;  // device flame table whose W is the adjoint scratch (physical-grid W for diagnostics)
   size_t off_counter;  // step index read by graph replays
@@ -135,7 +136,9 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
       off = align_up(off + (size_t)(pp.tw_size > 0 ? pp.tw_size : 1) * sizeof(float2));
     }
     L->off_tw6[l] = off;
-    if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3) * sizeof(float2));
+    if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3, 16) * sizeof(float2));
+    L->off_tw6_8[l] = off;
+    if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3, 8) * sizeof(float2));
   }
   L->off_dev = off;
   off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
@@ -182,7 +185,8 @@ struct flame_plan_s {
   std::vector<flame::FlameDev> hdev;
   std::vector<std::vector<float2>> tw_host;   // host copies of the tables (16 points per thread)
   std::vector<std::vector<float2>> tw_host8;  // 8 points per thread
-  std::vector<std::vector<float2>> tw_host6;  // length-3N1/4 transforms
+  std::vector<std::vector<float2>> tw_host6;  // length-3N1/4 transforms (16 and 8 points per thread)
+  std::vector<std::vector<float2>> tw_host6_8;
   flame::FlameDev* ddev = nullptr;
   flame::FlameDev* ddev_full = nullptr;       // same flames, W in the adjoint scratch
   std::vector<flame::FlameDev> hdev_full;
@@ -293,7 +297,8 @@ int rebuild_w(flame_plan p, int flame) {
   {
     Timed tm(p, KIND_OTHER);
     if (p->groups[p->group_of[flame]].product)
-      flame::launch_colp(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
+      flame::launch_colp(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n, nullptr,
+                         p->groups[p->group_of[flame]].col_pts);
     else
       flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, p->stream, p->ddev + flame, p->n);
   }
@@ -324,7 +329,8 @@ void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 =
 
 void launch_step_col(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (gr.product)
-    flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr, e0,
+    flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
+                       gr.col_pts, e0,
                        e1);
   else
     flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
@@ -351,7 +357,7 @@ int build_graph(flame_plan p) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
       const Group& gr = p->groups[gi];
       const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
-      const flame::KernelLaunch ck = gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP)
+      const flame::KernelLaunch ck = gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts)
                                                 : flame::col_step_kernel(gr.logn1, gr.col_pts);
       if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
       const flame::FlameDev* fl = p->ddev + gr.first;
@@ -472,18 +478,21 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     }
   }
   p->tw_host6.resize(flame::kMaxLog + 1);
+  p->tw_host6_8.resize(flame::kMaxLog + 1);
   for (int l = flame::kMinLogProduct; l <= flame::kMaxLog; ++l) {
     bool used = false;
     for (const Sizes& s : L.sizes) used |= s.logn1 == l;
     if (!used) continue;
-    auto& host = p->tw_host6[l];
-    host.assign(ff::twiddles6_size(l - 3), make_float2(1.f, 0.f));
-    ff::build_twiddles6(l - 3, host.data());
-    e = hipMemcpyAsync(base + L.off_tw6[l], host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice,
-                       p->stream);
-    if (e != hipSuccess) {
-      delete p;
-      return hip_fail(e, "twiddle upload");
+    for (int pts : {16, 8}) {
+      auto& host = pts == 16 ? p->tw_host6[l] : p->tw_host6_8[l];
+      host.assign(ff::twiddles6_size(l - 3, pts), make_float2(1.f, 0.f));
+      ff::build_twiddles6(l - 3, host.data(), pts);
+      e = hipMemcpyAsync(base + (pts == 16 ? L.off_tw6[l] : L.off_tw6_8[l]), host.data(),
+                         host.size() * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+      if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "twiddle upload");
+      }
     }
   }
   // device flame table, ordered so that flames of one grid size are contiguous
@@ -504,7 +513,9 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
     fd.tw1_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn1]);
     fd.tw2_8 = reinterpret_cast<const float2*>(base + L.off_tw8[s.logn2]);
-    fd.tw6 = s.logn1 >= flame::kMinLogProduct ? reinterpret_cast<const float2*>(base + L.off_tw6[s.logn1]) : nullptr;
+    const bool p6 = s.logn1 >= flame::kMinLogProduct;
+    fd.tw6 = p6 ? reinterpret_cast<const float2*>(base + L.off_tw6[s.logn1]) : nullptr;
+    fd.tw6_8 = p6 ? reinterpret_cast<const float2*>(base + L.off_tw6_8[s.logn1]) : nullptr;
     fd.n1 = d.n1;
     fd.n2 = d.n2;
     fd.m = d.n2 / 4;
@@ -853,8 +864,9 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
     std::vector<Cfg> cfgs;
     for (int c : {16, 8})
       for (int r : {16, 8}) cfgs.push_back(Cfg{false, c, r});
-    if (gr.logn1 >= flame::kMinLogProduct)  // the product-grid column kernel has 16 points per thread
-      for (int r : {16, 8}) cfgs.push_back(Cfg{true, gr.col_pts, r});
+    if (gr.logn1 >= flame::kMinLogProduct)
+      for (int c : {16, 8})
+        for (int r : {16, 8}) cfgs.push_back(Cfg{true, c, r});
     float best = 1e30f;
     Cfg best_cfg{gr.product, gr.col_pts, gr.row_pts};
     auto select = [&](const Cfg& cf) -> int {

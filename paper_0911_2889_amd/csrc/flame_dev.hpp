@@ -26,6 +26,7 @@ struct FlameDev {
   const float2* tw1_8; // the same for 8 points per thread
   const float2* tw2_8;
   const float2* tw6;   // twiddles of the length-3N1/4 transform (product grid), or null
+  const float2* tw6_8; // the same for 8 points per thread
   double* part;        // per-workgroup partial sums of the diagnostics
   int n1, n2;
   int m;               // stored k2 columns, N2/4
@@ -66,13 +67,14 @@ struct ColCfg {
 // instead of N1. The product of two fields with |k1| <= K1 = N1/4 - 1 has
 // |k1| <= 2 K1, and on M1 >= 3 K1 + 1 rows no alias of it lands in
 // |k1| <= K1, so the truncated quadratic term is the same as on N1 rows up to
-// rounding. The column transforms have length M1 = 6 * N1/8 (Shape6: radix-16
-// passes, then radix 6). Used for N1 >= 128.
+// rounding. The column transforms have length M1 = 6 * N1/8 (Shape6:
+// radix-PTS passes, then radix 6), with G = M1/PTS threads per column. Used
+// for N1 >= 128.
 constexpr int kMinLogProduct = 7;
 
-template <int LOGN1>
+template <int LOGN1, int PTS = 16>
 struct ColCfgP {
-  using S = ff::Shape6<LOGN1 - 3, 16>;
+  using S = ff::Shape6<LOGN1 - 3, PTS>;
   static constexpr int M1 = S::N;
   static constexpr int G = S::G;
   static constexpr int G16 = ff::Shape<LOGN1>::G;

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
       if constexpr (MODE == COL_STEP) {
         const float kap1 = f.s1 * (float)k1;
         const float kk2 = kap1 * kap1 + kap2c * kap2c;
-        const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
+        const float e = growth_factor(kk2, sc, f.gamma);
         val = make_float2(e * (old[kk].x + sc.a * v[i].x), e * (old[kk].y + sc.a * v[i].y));
       } else {
         val = ff::cscale(v[i], inv_p);
@@ -319,12 +319,13 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
 // {4, 5} except position 4*N6, which is k1 = -(K1 + 1)) go through LDS back
 // to the natural map t + G*i (the k2 = 0 column symmetrised on the way), the
 // state is stored from that map, and the two inverse transforms start there.
-template <int LOGN1, int MODE>
-__global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
+template <int LOGN1, int MODE, int PTS = 16>
+__global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     colp_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
   if (nbase) n += *nbase;
-  using Cfg = ColCfgP<LOGN1>;
+  using Cfg = ColCfgP<LOGN1, PTS>;
   using S6 = typename Cfg::S;
   constexpr int LOGP = LOGN1 - 3;
   constexpr int G = S6::G, T = Cfg::T, M1 = S6::N, N6 = S6::N6, IT = S6::IT6, N1 = 1 << LOGN1;
@@ -340,16 +341,16 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
   float2* my = lds + c;
   gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
   gf2* const Sc = glob(MODE == COL_FIRST && src ? const_cast<float2*>(src) : f.S) + (size_t)m * f.h1 + N1 / 4;
-  const auto tw = KernelTw6<LOGP>::make(f.tw6, t);
+  const auto tw = KernelTw6<LOGP, PTS>::make(PTS == 8 ? f.tw6_8 : f.tw6, t);
   // k1 of natural position p, and whether it is kept (|k1| <= K1)
   auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
   auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
 
-  float2 sv[16];  // spectrum at natural positions t + G*i, zero outside the box
+  float2 sv[PTS];  // spectrum at natural positions t + G*i, zero outside the box
   if constexpr (MODE == COL_STEP) {
-    float2 v[16];
+    float2 v[PTS];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state in the radix-6 output map, loaded before the transform
     constexpr int KR[4] = {0, 1, 4, 5};
     float2 old[IT][4];
@@ -364,7 +365,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
       }
     }
     float2 o[IT * 6];
-    fft6<LOGP, false>(v, o, t, my, T, tw);
+    fft6<LOGP, false, PTS>(v, o, t, my, T, tw);
     const StepScalars sc = step_scalars(f, n, M1);
     const float kap2c = f.s2 * (float)m;
 #pragma unroll
@@ -379,7 +380,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
             const int q = r < 2 ? r : r - 2;
             const float kap1 = f.s1 * (float)k1_of(pos);
             const float kk2 = kap1 * kap1 + kap2c * kap2c;
-            const float e = expf(-kk2 * sc.i2 + 0.5f * f.gamma * sqrtf(kk2) * sc.i1);
+            const float e = growth_factor(kk2, sc, f.gamma);
             val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x), e * (old[it][q].y + sc.a * o[it * 6 + r].y));
           }
           my[ff::lds_pad(pos) * T] = val;
@@ -391,7 +392,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
       // symmetrise column k2 = 0 (c == 0): k1 > 0 conjugated onto -k1, Im at k1 = 0 zeroed
       if (c == 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < PTS; ++i) {
           const int k1 = t + G * i;
           if (k1 >= 1 && k1 <= K1) my[ff::lds_pad(M1 - k1) * T] = ff::cconj(my[ff::lds_pad(k1) * T]);
         }
@@ -400,18 +401,18 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) sv[i] = my[ff::lds_pad(t + G * i) * T];
+    for (int i = 0; i < PTS; ++i) sv[i] = my[ff::lds_pad(t + G * i) * T];
     __syncthreads();  // the LDS is reused by the inverse transforms
     if (live) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < PTS; ++i) {
         const int pos = t + G * i;
         if (kept_at(pos)) st(Sc + k1_of(pos), sv[i]);
       }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < PTS; ++i) {
       const int pos = t + G * i;
       sv[i] = live && kept_at(pos) ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
     }
@@ -424,14 +425,14 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1>::THREADS)) __attribute__((amdg
   for (int pass = 0; pass < 2; ++pass) {
     // pass 0: Z+ = IFFT_k1((i kappa1 - kappa2) Phi~) -> Wp; pass 1: conj(IFFT_k1((i kappa1 + kappa2) Phi~)) -> Wm
     const float sg = pass == 0 ? -1.f : 1.f;
-    float2 v[16];
+    float2 v[PTS];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < PTS; ++i) {
       const float kap1 = f.s1 * (float)k1_of(t + G * i);
       v[i] = make_float2(-kap1 * sv[i].y + sg * kap2 * sv[i].x, kap1 * sv[i].x + sg * kap2 * sv[i].y);
     }
     float2 o[IT * 6];
-    fft6<LOGP, true>(v, o, t, my, T, tw);
+    fft6<LOGP, true, PTS>(v, o, t, my, T, tw);
     if (live) {
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
@@ -611,22 +612,24 @@ struct RowTable {
 
 template <int LOGN>
 struct ColPTable {
-  static KernelLaunch step_kernel(int mode) {
+  template <int PTS>
+  static KernelLaunch info(int mode) {
     if (mode == COL_FIRST)
-      return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST>), ColCfgP<LOGN>::THREADS,
-                          ColCfgP<LOGN>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP>), ColCfgP<LOGN>::THREADS,
-                        ColCfgP<LOGN>::LDS_BYTES};
+      return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST, PTS>),
+                          ColCfgP<LOGN, PTS>::THREADS, ColCfgP<LOGN, PTS>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, PTS>), ColCfgP<LOGN, PTS>::THREADS,
+                        ColCfgP<LOGN, PTS>::LDS_BYTES};
   }
+  static KernelLaunch step_kernel(int mode, int pts) { return pts == 8 ? info<8>(mode) : info<16>(mode); }
 };
 
 template <int L>
-void dispatch_colp(int logn, int mode, KernelLaunch* out) {
+void dispatch_colp(int logn, int mode, int pts, KernelLaunch* out) {
   if constexpr (L <= kMaxLog) {
     if (logn == L)
-      *out = ColPTable<L>::step_kernel(mode);
+      *out = ColPTable<L>::step_kernel(mode, pts);
     else
-      dispatch_colp<L + 1>(logn, mode, out);
+      dispatch_colp<L + 1>(logn, mode, pts, out);
   }
 }
 
@@ -686,15 +689,15 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
 }
 
-KernelLaunch colp_kernel_info(int logn1, int mode) {
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts) {
   KernelLaunch out{nullptr, 0, 0};
-  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, &out);
+  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, pts, &out);
   return out;
 }
 
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                 const void* src, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const KernelLaunch kl = colp_kernel_info(logn1, mode);
+                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
+  const KernelLaunch kl = colp_kernel_info(logn1, mode, pts);
   if (!kl.func) return;
   const long long* nb = nullptr;
   const float2* s = static_cast<const float2*>(src);

@@ -31,9 +31,10 @@ void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const F
 // Column kernel of the step on the product grid (3 N1/4 rows; N1 >= 128),
 // mode COL_STEP or COL_FIRST; colp_kernel_info gives its function and shape
 // (func null for an unsupported size).
-KernelLaunch colp_kernel_info(int logn1, int mode);
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts);
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                 const void* src = nullptr, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                 const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
+                 hipEvent_t ev_stop = nullptr);
 
 // Adjoint kernels (adjoint_kernels.hip); see the modes in flame_dev.hpp.
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,

@@ -77,9 +77,9 @@ struct KernelTw {
 };
 
 // Twiddles of a length 6*2^LOGP transform, cached in registers.
-template <int LOGP>
+template <int LOGP, int PTS>
 struct KernelTw6 {
-  using Type = ff::RegTwS<ff::Shape6<LOGP, 16>, GlobalFetch, kTwCacheMinNs>;
+  using Type = ff::RegTwS<ff::Shape6<LOGP, PTS>, GlobalFetch, kTwCacheMinNs>;
   static __device__ __forceinline__ Type make(const float2* tw, int t) { return Type(GlobalFetch{(const gf2*)tw}, t); }
 };
 
@@ -88,12 +88,14 @@ struct KernelTw6 {
 // j + r*N6, j = t + G*it (zero where j >= N6). Contains workgroup barriers
 // (all threads must call it), the last one after the radix-6 pass has read
 // LDS, so the caller may write LDS at once.
-template <int LOGP>
-using Out6 = float2[ff::Shape6<LOGP, 16>::IT6 * 6];
+template <int LOGP, int PTS>
+using Out6 = float2[ff::Shape6<LOGP, PTS>::IT6 * 6];
+template <int PTS>
+using Regs = float2[PTS];
 
-template <int LOGP, bool INV, class TW, int P = 0>
-__device__ __forceinline__ void fft6(float2 (&v)[16], Out6<LOGP>& o, int t, float2* lds, int stride, const TW& tw) {
-  using S = ff::Shape6<LOGP, 16>;
+template <int LOGP, bool INV, int PTS, class TW, int P = 0>
+__device__ __forceinline__ void fft6(Regs<PTS>& v, Out6<LOGP, PTS>& o, int t, float2* lds, int stride, const TW& tw) {
+  using S = ff::Shape6<LOGP, PTS>;
   using F = ff::FftS<S, INV>;
   if constexpr (P < S::NBF) {
     F::template butterflies<P, TW, false>(v, t, lds, stride, tw);
@@ -102,7 +104,7 @@ __device__ __forceinline__ void fft6(float2 (&v)[16], Out6<LOGP>& o, int t, floa
       F::gather(v, t, lds, stride);
       __syncthreads();
     }
-    fft6<LOGP, INV, TW, P + 1>(v, o, t, lds, stride, tw);
+    fft6<LOGP, INV, PTS, TW, P + 1>(v, o, t, lds, stride, tw);
   } else {
     F::last6(o, t, lds, stride, tw);
     __syncthreads();
@@ -130,6 +132,14 @@ __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long
   s.i1 = log1pf(x);
   s.i2 = x / (t + dt);
   return s;
+}
+
+// Exact linear propagator of one step for |kappa|^2 = kk2 (Eq. (1) linear part
+// integrated over [t_n, t_n+1]): exp(-|kappa|^2 I2 + gamma |kappa| I1 / 2).
+// The hardware exp2 and square root: the exponent's rounding costs a relative
+// error of about |x| 2^-24 in E, which matters only where E << 1.
+__device__ __forceinline__ float growth_factor(float kk2, const StepScalars& sc, float gamma) {
+  return __expf(-kk2 * sc.i2 + 0.5f * gamma * __builtin_amdgcn_sqrtf(kk2) * sc.i1);
 }
 
 // Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm = f.Wp + 2:

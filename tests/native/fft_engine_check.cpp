@@ -67,10 +67,10 @@ void run(std::vector<float2>& x, int stride, bool outer) {
 
 // Shape6 (N = 6 * 2^LOGP): the power-of-two passes, then the radix-6 pass
 // read from LDS; output r of round it lands at position j + r*N6.
-template <int LOGP, bool INV, int P>
-void passes6(std::vector<Regs<16>>& v, std::vector<std::vector<float2>>& o, float2* lds, int stride,
+template <int LOGP, bool INV, int PTS, int P>
+void passes6(std::vector<Regs<PTS>>& v, std::vector<std::vector<float2>>& o, float2* lds, int stride,
              const float2* tw, bool cached) {
-  using S = ff::Shape6<LOGP, 16>;
+  using S = ff::Shape6<LOGP, PTS>;
   using F = ff::FftS<S, INV>;
   if constexpr (P < S::NBF) {
     for (int t = 0; t < S::G; ++t) {
@@ -84,7 +84,7 @@ void passes6(std::vector<Regs<16>>& v, std::vector<std::vector<float2>>& o, floa
     if constexpr (P + 1 < S::NBF) {
       for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
     }
-    passes6<LOGP, INV, P + 1>(v, o, lds, stride, tw, cached);
+    passes6<LOGP, INV, PTS, P + 1>(v, o, lds, stride, tw, cached);
   } else {
     for (int t = 0; t < S::G; ++t) {
       float2 out[S::IT6 * 6];
@@ -99,17 +99,17 @@ void passes6(std::vector<Regs<16>>& v, std::vector<std::vector<float2>>& o, floa
   }
 }
 
-template <int LOGP, bool INV>
+template <int LOGP, bool INV, int PTS>
 void run6(std::vector<float2>& x, int stride) {
-  using S = ff::Shape6<LOGP, 16>;
+  using S = ff::Shape6<LOGP, PTS>;
   std::vector<float2> tw(S::TW_SIZE + 1);
-  ff::build_twiddles6(LOGP, tw.data(), 16);
-  std::vector<Regs<16>> v(S::G);
+  ff::build_twiddles6(LOGP, tw.data(), PTS);
+  std::vector<Regs<PTS>> v(S::G);
   for (int t = 0; t < S::G; ++t)
-    for (int i = 0; i < 16; ++i) v[t].a[i] = x[t + S::G * i];
+    for (int i = 0; i < PTS; ++i) v[t].a[i] = x[t + S::G * i];
   std::vector<float2> lds(size_t(S::LDS) * stride, make_float2(1e30f, 1e30f));
   std::vector<std::vector<float2>> o(S::G);
-  passes6<LOGP, INV, 0>(v, o, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  passes6<LOGP, INV, PTS, 0>(v, o, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
   std::vector<int> seen(S::N, 0);
   for (int t = 0; t < S::G; ++t)
     for (int it = 0; it < S::IT6; ++it) {
@@ -146,15 +146,22 @@ bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer,
 }
 
 template <int LOGP>
-bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride) {
+bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride, int pts) {
   if constexpr (LOGP > 10) {
     return false;
   } else {
-    if (logp != LOGP) return dispatch6<LOGP + 1>(logp, inv, x, stride);
-    if (inv)
-      run6<LOGP, true>(x, stride);
-    else
-      run6<LOGP, false>(x, stride);
+    if (logp != LOGP) return dispatch6<LOGP + 1>(logp, inv, x, stride, pts);
+    if (pts == 8) {
+      if (inv)
+        run6<LOGP, true, 8>(x, stride);
+      else
+        run6<LOGP, false, 8>(x, stride);
+    } else {
+      if (inv)
+        run6<LOGP, true, 16>(x, stride);
+      else
+        run6<LOGP, false, 16>(x, stride);
+    }
     return true;
   }
 }
@@ -162,7 +169,7 @@ bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride) {
 }  // namespace
 
 // Header: logn inv stride outer pts six. With six = 1 the length is
-// 6 * 2^logn (Shape6, 16 points per thread, outer unused).
+// 6 * 2^logn (Shape6, outer unused).
 int main() {
   int hdr[6];
   if (fread(hdr, sizeof(int), 6, stdin) != 6) return 2;
@@ -170,10 +177,10 @@ int main() {
   if (pts != 8 && pts != 16) return 3;
   if (stride < 1) return 3;
   if (six) {
-    if (logn < 4 || logn > 10 || pts != 16) return 3;
+    if (logn < 4 || logn > 10) return 3;
     std::vector<float2> x(size_t(6) << logn);
     if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
-    if (!dispatch6<4>(logn, inv, x, stride)) return 5;
+    if (!dispatch6<4>(logn, inv, x, stride, pts)) return 5;
     fwrite(x.data(), sizeof(float2), x.size(), stdout);
     return 0;
   }

@@ -229,8 +229,8 @@ def test_points_per_thread_variants_match_oracle(flame, n1, n2, cp, rp):
 def test_product_grid_matches_oracle_and_physical_grid(flame, n1, n2):
     """The quadratic term formed on 3*N1/4 theta rows: one step and 20 steps
     against the oracle (which forms it on the N1 x N2 augmented grid of
-    Section 3), and against the same run on N1 rows, with the row kernel's
-    16 and 8 points per thread."""
+    Section 3), and against the same run on N1 rows, for several points per
+    thread of the column and row kernels."""
     w = small_workload(n1, n2, seed=n1 + 5 * n2, amp=0.1, t0=5.0, dt=0.2)
     half = synth.workload_spectrum(w)
     p = oracle_params(w)
@@ -238,21 +238,22 @@ def test_product_grid_matches_oracle_and_physical_grid(flame, n1, n2):
     assert rel_l2(refs[1], half) > 1e-3
     runs = {}
     for product in (True, False):
-        for rp in (16, 8):
+        for cp, rp in ((16, 16), (8, 8), (8, 16)):
             sim = make_sim(flame, w)
             assert sim.product_grid(n1, n2)  # the default for n1 >= 128
             sim.set_product_grid(n1, n2, product)
-            sim.set_points_per_thread(n1, n2, 16, rp)
+            sim.set_points_per_thread(n1, n2, cp, rp)
             assert sim.product_grid(n1, n2) == product
             sim.set_spectrum(half)
             sim.step(1)
             one = sim.spectrum().cpu().numpy()
             sim.step(19)
             twenty = sim.spectrum().cpu().numpy()
-            assert rel_l2(one, refs[1]) < 1e-6, (product, rp)
-            assert rel_l2(twenty, refs[20]) < 1e-5, (product, rp)
-            runs[(product, rp)] = twenty
-    assert rel_l2(runs[(True, 16)], runs[(False, 16)]) < 2e-6
+            assert rel_l2(one, refs[1]) < 1e-6, (product, cp, rp)
+            assert rel_l2(twenty, refs[20]) < 1e-5, (product, cp, rp)
+            runs[(product, cp, rp)] = twenty
+    assert rel_l2(runs[(True, 16, 16)], runs[(False, 16, 16)]) < 2e-6
+    assert rel_l2(runs[(True, 8, 8)], runs[(True, 16, 16)]) < 2e-6
 
 
 def test_product_grid_switches_mid_run_and_keeps_diagnostics(flame):

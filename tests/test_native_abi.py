@@ -102,13 +102,13 @@ def test_fft_engine_on_host_matches_numpy(tmp_path):
     # every output position written exactly once and equal to the DFT
     for logp in range(4, 11):
         for inv in (0, 1):
-            for stride in (1, 2, 3):
+            for stride, pts in ((1, 16), (2, 16), (3, 16), (1, 8), (2, 8)):
                 n = 6 << logp
                 rng = np.random.default_rng(logp * 7 + inv)
                 x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
-                out = subprocess.run([str(exe)], input=struct.pack("6i", logp, inv, stride, 0, 16, 1) + x.tobytes(),
+                out = subprocess.run([str(exe)], input=struct.pack("6i", logp, inv, stride, 0, pts, 1) + x.tobytes(),
                                      capture_output=True, check=True).stdout
                 y = np.frombuffer(out, dtype=np.complex64)
                 xd = x.astype(np.complex128)
                 ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
-                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logp, inv, stride)
+                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logp, inv, stride, pts)
