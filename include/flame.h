@@ -182,8 +182,10 @@ int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t
  * its aliases falls inside |k1| <= K1, so the truncated term, and the step,
  * are the same as on N1 rows up to rounding. It moves 3/4 of the
  * intermediate data and does 3/4 of the row transforms. The column
- * transforms then have length 3 N1/4 (radix-col_pts passes and a radix-6
- * pass). Diagnostics,
+ * transforms then have length 3 N1/4 (radix-16 passes and a radix-6 pass;
+ * col_pts = 8 selects the variant whose forward transform runs on twice the
+ * threads with 8 points each and whose Wp and Wm transforms run side by
+ * side). Diagnostics,
  * state I/O, synthesis and the adjoint always use the N1 x N2 grid. Default:
  * enabled for n1 >= 128. Changing it synchronises the stream. */
 int flame_set_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);

@@ -86,6 +86,27 @@ struct ColCfgP {
   static_assert(THREADS % 64 == 0, "whole waves");
 };
 
+// Split variant of the product-grid column kernel: per column 2G threads
+// (G = M1/16) run the forward transform with 8 points each (Shape6 with
+// PTS 8), then split into two groups of G threads that run the Wp and the Wm
+// inverse transforms side by side with 16 points each, each group in its own
+// LDS buffer. Twice the waves of ColCfgP<., 16> for the same columns.
+template <int LOGN1>
+struct ColCfgQ {
+  using SF = ff::Shape6<LOGN1 - 3, 8>;   // forward
+  using SI = ff::Shape6<LOGN1 - 3, 16>;  // inverse
+  static constexpr int M1 = SF::N;
+  static constexpr int G8 = SF::G, G16 = SI::G;
+  static constexpr int T = ColCfgP<LOGN1, 16>::T;
+  static constexpr int TQ = ColCfgP<LOGN1, 16>::TQ;
+  static constexpr int QS = ColCfgP<LOGN1, 16>::QS;
+  static constexpr int SLOTS = SF::LDS;  // padded slots of one buffer
+  static constexpr int THREADS = T * G8;
+  static constexpr int LDS_BYTES = 2 * SLOTS * T * 8;
+  static_assert(G8 == 2 * G16, "two inverse groups");
+  static_assert(THREADS % 64 == 0, "whole waves");
+};
+
 // Row kernel: B = max(1, 16*256/N2) row pairs per workgroup, interleaved.
 template <int LOGN2, int PTS = ff::kPts>
 struct RowCfg {

@@ -452,6 +452,135 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
   }
 }
 
+// Split variant of colp_kernel (ColCfgQ): the forward transform with 8 points
+// per thread over 2G threads, then the Wp and Wm inverse transforms side by
+// side, 16 points per thread, G threads each. Same results as colp_kernel up
+// to rounding. Every barrier is reached by every thread.
+template <int LOGN1, int MODE>
+__global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
+    colq_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
+  if (nbase) n += *nbase;
+  using Cfg = ColCfgQ<LOGN1>;
+  using SF = typename Cfg::SF;
+  constexpr int LOGP = LOGN1 - 3;
+  constexpr int G8 = Cfg::G8, G16 = Cfg::G16, T = Cfg::T, M1 = Cfg::M1, N6 = SF::N6, N1 = 1 << LOGN1;
+  constexpr int ITF = SF::IT6, ITI = ff::Shape6<LOGP, 16>::IT6;
+  constexpr int TQ = Cfg::TQ, QS = Cfg::QS, K1 = N1 / 4 - 1;
+  extern __shared__ float2 lds[];
+  const FlameDev f = fls[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int c = tid % T, t8 = tid / T;           // forward: lane t8 of 2G
+  const int grp = t8 / G16, t16 = t8 % G16;       // inverse: group (0: Wp, 1: Wm), lane t16 of G
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int m = tile * T + c;
+  const bool live = m < f.m;
+  float2* const buf0 = lds + c;                          // forward exchange, then the updated spectrum
+  float2* const bufg = lds + grp * (Cfg::SLOTS * T) + c;  // this group's inverse exchange
+  gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));
+  gf2* const Sc = glob(MODE == COL_FIRST && src ? const_cast<float2*>(src) : f.S) + (size_t)m * f.h1 + N1 / 4;
+  auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
+  auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
+
+  float2 sv[16];  // spectrum at natural positions t16 + G16*i
+  if constexpr (MODE == COL_STEP) {
+    {
+      const auto twf = KernelTw6<LOGP, 8>::make(f.tw6_8, t8);
+      float2 v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = live ? ld(Qc + (t8 + G8 * i) * TQ) : make_float2(0.f, 0.f);
+      constexpr int KR[4] = {0, 1, 4, 5};
+      float2 old[ITF][4];
+#pragma unroll
+      for (int it = 0; it < ITF; ++it) {
+        const int j = t8 + G8 * it;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int pos = j + KR[q] * N6;
+          old[it][q] = live && j < N6 && kept_at(pos) ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+        }
+      }
+      float2 o[ITF * 6];
+      fft6<LOGP, false, 8>(v, o, t8, buf0, T, twf);
+      const StepScalars sc = step_scalars(f, n, M1);
+      const float kap2c = f.s2 * (float)m;
+#pragma unroll
+      for (int it = 0; it < ITF; ++it) {
+        const int j = t8 + G8 * it;
+        if (j < N6) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) {
+            const int pos = j + r * N6;
+            float2 val = make_float2(0.f, 0.f);
+            if (r != 2 && r != 3 && kept_at(pos)) {
+              const int q = r < 2 ? r : r - 2;
+              const float kap1 = f.s1 * (float)k1_of(pos);
+              const float e = growth_factor(kap1 * kap1 + kap2c * kap2c, sc, f.gamma);
+              val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x),
+                                e * (old[it][q].y + sc.a * o[it * 6 + r].y));
+            }
+            buf0[ff::lds_pad(pos) * T] = val;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tile == 0) {
+      // symmetrise column k2 = 0: k1 > 0 conjugated onto -k1, Im at k1 = 0 zeroed
+      if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k1 = t8 + G8 * i;
+          if (k1 >= 1 && k1 <= K1) buf0[ff::lds_pad(M1 - k1) * T] = ff::cconj(buf0[ff::lds_pad(k1) * T]);
+        }
+        if (t8 == 0) buf0[0].y = 0.f;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sv[i] = buf0[ff::lds_pad(t16 + G16 * i) * T];
+    __syncthreads();  // both groups have read the spectrum before buffer 0 is reused
+    if (live && grp == 0) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int pos = t16 + G16 * i;
+        if (kept_at(pos)) st(Sc + k1_of(pos), sv[i]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int pos = t16 + G16 * i;
+      sv[i] = live && kept_at(pos) ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+    }
+  }
+
+  // group 0: Z+ = IFFT_k1((i kappa1 - kappa2) Phi~) -> Wp; group 1: conj(IFFT_k1((i kappa1 + kappa2) Phi~)) -> Wm
+  const auto twi = KernelTw6<LOGP, 16>::make(f.tw6, t16);
+  const float kap2 = f.s2 * (float)m * (grp == 0 ? -1.f : 1.f);
+  float2 v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const float kap1 = f.s1 * (float)k1_of(t16 + G16 * i);
+    v[i] = make_float2(-kap1 * sv[i].y + kap2 * sv[i].x, kap1 * sv[i].x + kap2 * sv[i].y);
+  }
+  float2 o[ITI * 6];
+  fft6<LOGP, true, 16>(v, o, t16, bufg, T, twi);
+  if (live) {
+    gf2* const dst = glob(grp == 0 ? f.Wp : f.Wm);
+    const float cs = grp == 0 ? 1.f : -1.f;  // Wm holds the conjugate
+#pragma unroll
+    for (int it = 0; it < ITI; ++it) {
+      const int j = t16 + G16 * it;
+      if (j < N6) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+          st(dst + w_index(j + r * N6, m, f.m), make_float2(o[it * 6 + r].x, cs * o[it * 6 + r].y));
+      }
+    }
+  }
+}
+
 // Canonical half spectrum -> state, with the k2 = 0 symmetrisation.
 __global__ void set_spectrum_kernel(const FlameDev* __restrict__ fls, int flame, const float2* __restrict__ half) {
   const FlameDev f = fls[flame];
@@ -620,7 +749,15 @@ struct ColPTable {
     return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, PTS>), ColCfgP<LOGN, PTS>::THREADS,
                         ColCfgP<LOGN, PTS>::LDS_BYTES};
   }
-  static KernelLaunch step_kernel(int mode, int pts) { return pts == 8 ? info<8>(mode) : info<16>(mode); }
+  static KernelLaunch split(int mode) {
+    if (mode == COL_FIRST)
+      return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_FIRST>), ColCfgQ<LOGN>::THREADS,
+                          ColCfgQ<LOGN>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP>), ColCfgQ<LOGN>::THREADS,
+                        ColCfgQ<LOGN>::LDS_BYTES};
+  }
+  // pts 16: colp_kernel<., 16>; pts 8: the split kernel (8 points per thread in the forward transform)
+  static KernelLaunch step_kernel(int mode, int pts) { return pts == 8 ? split(mode) : info<16>(mode); }
 };
 
 template <int L>
