@@ -12,7 +12,8 @@
 // The area excess J = (1/P) sum sqrt(1 + |grad Phi|^2/r0^2) - 1 has
 //     dJ/dPhi = -Pi div( grad Phi / (P r0^2 sqrt(1 + |grad Phi|^2/r0^2)) ).
 //
-// One adjoint step is three kernels:
+// One adjoint step is three kernels (on the step's grid: N1 rows, or the
+// 3 N1/4-row product grid with adjp_col in place of adj_col):
 //  * adj_col<ADJ_A>: mu = E lambda per column; column inverse transforms of mu
 //    (-> Q) and of (i kappa1 -+ kappa2) Phi~^n (-> Wp, Wm, as the forward step);
 //  * adj_row<ROW_ADJ>: per row pair, m (one packed real synthesis for two
@@ -178,6 +179,153 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   }
 }
 
+// adj_col on the product grid (ColCfgP, M1 = 3 N1/4 rows; see colp_kernel):
+// ADJ_A and ADJ_C with the length-M1 transforms. ADJ_A's inputs are in the
+// natural map, so its three inverse transforms need no remap; ADJ_C's forward
+// transforms leave A1 and A2 in the radix-6 output map, where the update is
+// formed; the kept modes go through LDS to the natural map (column k2 = 0
+// symmetrised on the way) and are stored from there.
+template <int LOGN1, int MODE>
+__global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
+    adjp_col_kernel(const FlameDev* __restrict__ fls, long long n, const float2* state, const float2* lam_in,
+                    float2* lam_out) {
+  static_assert(MODE == ADJ_A || MODE == ADJ_C, "product-grid adjoint modes");
+  using Cfg = ColCfgP<LOGN1, 16>;
+  using S6 = typename Cfg::S;
+  constexpr int LOGP = LOGN1 - 3;
+  constexpr int G = S6::G, T = Cfg::T, M1 = S6::N, N6 = S6::N6, IT = S6::IT6, N1 = 1 << LOGN1;
+  constexpr int TQ = Cfg::TQ, QS = Cfg::QS, K1 = N1 / 4 - 1;
+  extern __shared__ float2 lds[];
+  const FlameDev f = fls[blockIdx.y];
+  const int tid = threadIdx.x;
+  const int c = tid % T, t = tid / T;
+  const int tile = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int m = tile * T + c;
+  const bool live = m < f.m;
+  float2* my = lds + c;
+  const size_t tile_base = ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));  // column m of Q, A1, A2
+  const size_t col = (size_t)m * f.h1 + N1 / 4;  // element k1 of column m at col + k1
+  const auto tw = KernelTw6<LOGP, 16>::make(f.tw6, t);
+  const float kap2 = f.s2 * (float)m;
+  const StepScalars sc = step_scalars(f, n, M1);
+  auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
+  auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
+  gf2* const lin = glob(const_cast<float2*>(lam_in));
+
+  if constexpr (MODE == ADJ_A) {
+    float2 sv[16], v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int pos = t + G * i;
+      const bool ok = live && kept_at(pos);
+      const float2 lam = ok ? ld(lin + col + k1_of(pos)) : make_float2(0.f, 0.f);
+      sv[i] = ok ? ld(glob(const_cast<float2*>(state)) + col + k1_of(pos)) : make_float2(0.f, 0.f);
+      v[i] = ok ? ff::cscale(lam, efactor(f, sc, k1_of(pos), kap2)) : make_float2(0.f, 0.f);  // mu = E lambda
+    }
+    float2 o[IT * 6];
+    fft6<LOGP, true, 16>(v, o, t, my, T, tw);  // M = column synthesis of mu -> Q
+    if (live) {
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int j = t + G * it;
+        if (j < N6) {
+#pragma unroll
+          for (int r = 0; r < 6; ++r) st(glob(f.Q) + tile_base + (size_t)(j + r * N6) * TQ, o[it * 6 + r]);
+        }
+      }
+    }
+    // Z+ and Z- of the state, as the forward column kernel
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+      const float sgn = pass == 0 ? -1.f : 1.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float kap1 = f.s1 * (float)k1_of(t + G * i);
+        v[i] = make_float2(-kap1 * sv[i].y + sgn * kap2 * sv[i].x, kap1 * sv[i].x + sgn * kap2 * sv[i].y);
+      }
+      fft6<LOGP, true, 16>(v, o, t, my, T, tw);
+      if (live) {
+        gf2* dst = glob(pass == 0 ? f.Wp : f.Wm);
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+          const int j = t + G * it;
+          if (j < N6) {
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+              st(dst + w_index(j + r * N6, m, f.m), pass == 0 ? o[it * 6 + r] : ff::cconj(o[it * 6 + r]));
+          }
+        }
+      }
+    }
+  } else {
+    // lambda^{n+1} at the kept modes, in the radix-6 output map
+    constexpr int KR[4] = {0, 1, 4, 5};
+    float2 lam[IT][4];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + G * it;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int pos = j + KR[q] * N6;
+        lam[it][q] = live && j < N6 && kept_at(pos) ? ld(lin + col + k1_of(pos)) : make_float2(0.f, 0.f);
+      }
+    }
+    // forward column transforms of the row transforms of w1 and i kappa2 w2
+    float2 ou[IT * 6], ow[IT * 6];
+    {
+      float2 v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = live ? ld(glob(f.A1) + tile_base + (size_t)(t + G * i) * TQ) : make_float2(0.f, 0.f);
+      fft6<LOGP, false, 16>(v, ou, t, my, T, tw);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = live ? ld(glob(f.A2) + tile_base + (size_t)(t + G * i) * TQ) : make_float2(0.f, 0.f);
+      fft6<LOGP, false, 16>(v, ow, t, my, T, tw);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + G * it;
+      if (j < N6) {
+#pragma unroll
+        for (int r = 0; r < 6; ++r) {
+          const int pos = j + r * N6;
+          float2 val = make_float2(0.f, 0.f);
+          if (r != 2 && r != 3 && kept_at(pos)) {
+            const int q = r < 2 ? r : r - 2;
+            const int k1 = k1_of(pos);
+            const float kap1 = f.s1 * (float)k1;
+            const float2 u = ou[it * 6 + r], w = ow[it * 6 + r];
+            // raw divergence i kappa1 U1 + V2 (sums without the 1/P factors)
+            const float2 div = make_float2(-kap1 * u.y + w.x, kap1 * u.x + w.y);
+            const float e = efactor(f, sc, k1, kap2);
+            val = make_float2(e * lam[it][q].x - 2.f * sc.a * div.x, e * lam[it][q].y - 2.f * sc.a * div.y);
+          }
+          my[ff::lds_pad(pos) * T] = val;
+        }
+      }
+    }
+    __syncthreads();
+    if (tile == 0) {  // symmetrise column k2 = 0: k1 > 0 conjugated onto -k1, Im at k1 = 0 zeroed
+      if (c == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int k1 = t + G * i;
+          if (k1 >= 1 && k1 <= K1) my[ff::lds_pad(M1 - k1) * T] = ff::cconj(my[ff::lds_pad(k1) * T]);
+        }
+        if (t == 0) my[0].y = 0.f;
+      }
+      __syncthreads();
+    }
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int pos = t + G * i;
+        if (kept_at(pos)) st(glob(lam_out) + col + k1_of(pos), my[ff::lds_pad(pos) * T]);
+      }
+    }
+  }
+}
+
 template <int LOGN2, int MODE>
 __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_waves_per_eu(ADJ_ROW_WAVES_PER_EU)))
     adj_row_kernel(const FlameDev* __restrict__ fls, long long n) {
@@ -188,9 +336,10 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
   const int tid = threadIdx.x;
   const int p = tid % B, t = tid / B;
   const int pair = xcd_swizzle(blockIdx.x, gridDim.x) * B + p;
-  const bool live = pair < f.n1 / 2;
+  // the adjoint step runs on the step's product grid; the seed on the grid's rows
+  const int n1 = MODE == ROW_ADJ ? f.rows : f.n1, ts = f.tshift, mcols = f.m;
+  const bool live = pair < n1 / 2;
   const int ja = 2 * pair, jb = 2 * pair + 1;
-  const int n1 = f.n1, ts = f.tshift, mcols = f.m;
   float2* my = lds + p;
   const auto tw2 = KernelTw<LOGN2>::make(f.tw2, t);
   gf2* const Wp = glob(f.Wp);
@@ -322,6 +471,26 @@ void dispatch_adj(int logn, A... args) {
 }
 
 }  // namespace
+
+template <int L>
+void dispatch_adjp(int logn, int mode, dim3 grid, hipStream_t st, const FlameDev* fl, long long n, const float2* s,
+                   const float2* li, float2* lo) {
+  if constexpr (L <= kMaxLog) {
+    if (logn != L) return dispatch_adjp<L + 1>(logn, mode, grid, st, fl, n, s, li, lo);
+    constexpr int th = ColCfgP<L, 16>::THREADS, lds = ColCfgP<L, 16>::LDS_BYTES;
+    if (mode == ADJ_A)
+      hipLaunchKernelGGL((adjp_col_kernel<L, ADJ_A>), grid, dim3(th), lds, st, fl, n, s, li, lo);
+    else
+      hipLaunchKernelGGL((adjp_col_kernel<L, ADJ_C>), grid, dim3(th), lds, st, fl, n, s, li, lo);
+  }
+}
+
+void launch_adjp_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
+                     const void* state, const void* lam_in, void* lam_out) {
+  if (logn1 < kMinLogProduct || (mode != ADJ_A && mode != ADJ_C)) return;
+  dispatch_adjp<kMinLogProduct>(logn1, mode, dim3(tiles, 1), st, fl, n, static_cast<const float2*>(state),
+                                static_cast<const float2*>(lam_in), static_cast<float2*>(lam_out));
+}
 
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
                     const void* state, const void* lam_in, void* lam_out) {

@@ -713,9 +713,16 @@ int flame_adjoint_step(flame_plan p, int32_t flame, int64_t n, const void* state
   DeviceGuard g(p->device);
   const Sizes& s = p->layout.sizes[flame];
   flame::FlameDev* fd = p->ddev + flame;
-  flame::launch_adj_col(s.logn1, flame::ADJ_A, s.tiles, p->stream, fd, n, state_n, lam_in, nullptr);
-  flame::launch_adj_row(s.logn2, flame::ROW_ADJ, s.rgroups, p->stream, fd, n);
-  flame::launch_adj_col(s.logn1, flame::ADJ_C, s.tiles, p->stream, fd, n, nullptr, lam_in, lam_out);
+  const Group& gr = p->groups[p->group_of[flame]];
+  if (gr.product) {  // the transpose of the step on its product grid
+    flame::launch_adjp_col(s.logn1, flame::ADJ_A, s.tiles, p->stream, fd, n, state_n, lam_in, nullptr);
+    flame::launch_adj_row(s.logn2, flame::ROW_ADJ, gr.rgroups(), p->stream, fd, n);
+    flame::launch_adjp_col(s.logn1, flame::ADJ_C, s.tiles, p->stream, fd, n, nullptr, lam_in, lam_out);
+  } else {
+    flame::launch_adj_col(s.logn1, flame::ADJ_A, s.tiles, p->stream, fd, n, state_n, lam_in, nullptr);
+    flame::launch_adj_row(s.logn2, flame::ROW_ADJ, s.rgroups, p->stream, fd, n);
+    flame::launch_adj_col(s.logn1, flame::ADJ_C, s.tiles, p->stream, fd, n, nullptr, lam_in, lam_out);
+  }
   p->w_valid[flame] = 0;
   return last_launch("adjoint step launch");
 }

@@ -40,6 +40,9 @@ void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const 
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
                     const void* state, const void* lam_in, void* lam_out);
 void launch_adj_row(int logn2, int mode, int groups, hipStream_t st, const FlameDev* fl, long long n);
+// ADJ_A / ADJ_C on the product grid (3 N1/4 rows; N1 >= 128), with ROW_ADJ reading the step's row count.
+void launch_adjp_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,
+                     const void* state, const void* lam_in, void* lam_out);
 
 // Row kernel over `groups` groups of B row pairs for `nfl` flames of one size.
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,

@@ -97,3 +97,26 @@ def test_checkpointed_gradient_matches_oracle(n1, n2, nsteps, every):
     ref = oracle.synthesize(lam).real
     assert abs(J.item() - jref) < 1e-5 * abs(jref)
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+
+
+@pytest.mark.parametrize("n1,n2", [(256, 512), (1024, 128), (128, 2048)])
+def test_adjoint_step_on_both_grids_matches_oracle(n1, n2):
+    """The adjoint step on the 3*N1/4-row product grid (the transpose of the
+    step the product grid takes) and on N1 rows, against the oracle's
+    transposed step."""
+    t0, dt, n = 5.0, 0.2, 2
+    state = spectrum(n1, n2, 31 + n1, 0.3)
+    lam = spectrum(n1, n2, 32 + n2, 1.0)
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    sf = oracle.half_to_full(state.astype(np.complex128), n1, n2)
+    lf = oracle.half_to_full(lam.astype(np.complex128), n1, n2)
+    ref = oracle.full_to_half(oracle.step_adjoint(sf, lf, p, n), n1, n2)
+    got = {}
+    for product in (True, False):
+        sim = make(n1, n2, t0, dt)
+        sim.set_product_grid(n1, n2, product)
+        lo = sim.new_cotangent()
+        sim.adjoint_step(n, to_internal(state, n1, n2), to_internal(lam, n1, n2), lo)
+        got[product] = from_internal(lo, n1, n2)
+        assert rel_l2(got[product], ref) < 1e-5, product
+    assert rel_l2(got[True], got[False]) < 2e-6
