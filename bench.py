@@ -182,6 +182,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--pts", type=int, nargs=2, metavar=("COL", "ROW"),
                     help="points per thread of the column and row step kernels (default: autotuned)")
+    ap.add_argument("--no-graph", action="store_true", help="launch every step directly (no hipGraph replays)")
     ap.add_argument("--grid", choices=("product", "n1"),
                     help="form the quadratic term on 3*N1/4 rows or on N1 rows (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
@@ -246,13 +247,17 @@ def main():
     pts = sim.points_per_thread(w.n1, w.n2)
     rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
 
-    # warm-up from the initial condition
+    # steps between diagnostics run as one hipGraph replay
+    graph_steps = 0 if args.no_graph else args.diag_every
+    sim.set_graph_steps(graph_steps)
+
+    # warm-up from the initial condition (instantiates the graph)
     sim.set_spectrum(half)
-    run_steps(args.warmup, False)
+    run_steps(max(args.warmup, graph_steps), False)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
-    # timed region 1: plain launches -> value
+    # timed region 1: the step as the library runs it (graph replays between diagnostics) -> value
     sim.set_spectrum(half)
     sim.step(0)
     torch.cuda.synchronize()
@@ -263,7 +268,9 @@ def main():
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
 
-    # timed region 2: the same steps with HIP events around every kernel -> roofline
+    # timed region 2: the same steps launched directly, every step kernel carrying
+    # its own start/stop events -> per-kernel durations for the roofline
+    sim.set_graph_steps(0)
     sim.set_spectrum(half)
     sim.step(0)
     torch.cuda.synchronize()
@@ -291,7 +298,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
                    "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}",
-                   "points_per_thread": {"col": pts[0], "row": pts[1]}, "product_rows": rows},
+                   "points_per_thread": {"col": pts[0], "row": pts[1]}, "product_rows": rows,
+                   "graph_steps": graph_steps},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom}_kernel",
