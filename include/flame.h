@@ -135,8 +135,9 @@ int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
  * For the step n -> n+1 taken from state_n (the state at step index n):
  *   lam_out = mu - 2 dt c_n Pi div(m grad Phi^n),  mu = E^n lam_in,
  * m the grid field of mu, c_n = 1/(2 r0(t_n)^2). lam_out may equal lam_in;
- * state_n must not alias lam_out. Uses the plan's workspace, so the next
- * flame_step rebuilds its intermediates. */
+ * state_n must not alias lam_out. Runs on the grid flame_step uses for this
+ * flame (see flame_set_product_grid: the transpose of that step). Uses the
+ * plan's workspace, so the next flame_step rebuilds its intermediates. */
 int flame_adjoint_step(flame_plan plan, int32_t flame, int64_t n, const void* state_n, const void* lam_in,
                        void* lam_out);
 

@@ -160,8 +160,9 @@ __device__ __forceinline__ void ld_pair(const gf2* p, float2& a, float2& b) {
   b = make_float2(v.z, v.w);
 }
 
-// Offset of element (j1, m) in the tiled [m/T][j1][m%T] layout of Q (and of
-// the adjoint scratch A1, A2).
+// Offset of element (j1, m) in the tiled [m/TQ][j1][m%TQ] layout of Q (and of
+// the adjoint scratch A1, A2); n1 is the number of rows j1 of the grid the
+// array holds (N1, or 3 N1/4 on the product grid), tshift = log2(TQ).
 __device__ __forceinline__ int tiled(int j1, int m, int n1, int tshift) {
   return (((m >> tshift) * n1 + j1) << tshift) + (m & ((1 << tshift) - 1));
 }

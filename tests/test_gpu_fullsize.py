@@ -28,8 +28,11 @@ def load_fixture(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["flame512x1024", "flame2048x4096"])
-def test_full_size_trajectory_matches_oracle_sample(name):
+@pytest.mark.parametrize("name,product", [("flame512x1024", True), ("flame2048x4096", True),
+                                          ("flame2048x4096", False)])
+def test_full_size_trajectory_matches_oracle_sample(name, product):
+    """product: the quadratic term on 3*N1/4 rows (the default), or on N1 rows
+    as in the oracle; both must match the oracle's trajectory."""
     from paper_0911_2889_amd import FlameSim
 
     fx = load_fixture(name)
@@ -37,6 +40,7 @@ def test_full_size_trajectory_matches_oracle_sample(name):
     assert fx["grid"] == [w.n1, w.n2] and fx["seed"] == w.seed
     half = synth.workload_spectrum(w)
     sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
+    sim.set_product_grid(w.n1, w.n2, product)
     sim.set_spectrum(half)
     rows, cols = np.array(fx["rows"]), np.array(fx["cols"])
     done = 0
@@ -48,7 +52,7 @@ def test_full_size_trajectory_matches_oracle_sample(name):
         want = np.array(ref["re"]) + 1j * np.array(ref["im"])
         sample = got[rows, cols]
         err = np.linalg.norm(sample - want) / np.linalg.norm(want)
-        assert err < 1e-5, (name, step, err)
+        assert err < 1e-5, (name, product, step, err)
         wgt = np.full(got.shape, 2.0)
         wgt[:, 0] = 1.0
         norm_sq = float((wgt * np.abs(got) ** 2).sum())
