@@ -8,7 +8,8 @@ What it follows (V. Karlin, "Global communications in multiprocessor
 simulations of flames"):
 
 * Section 2, Eq. (1): the Fourier-space evolution equation for the flame
-  perturbation, with the reference radius r0(t) = t and no forcing.
+  perturbation, with the reference radius r0(t) = t (or a given law) and no
+  forcing.
 * Section 2, truncation paragraph: harmonics beyond K are dropped and the
   quadratic term is a circular convolution evaluated with FFTs.
 * Section 3, augmented-array paragraph: the K_Psi = 4K + k0 + 1 padded array,

@@ -28,7 +28,7 @@ x = |grad Phi|^2 / r0^2, whose gradient is
 import numpy as np
 
 from .diagnostics import gradient_fields
-from .model import growth_exponent, r0, run, step, step_scalars
+from .model import growth_exponent, run, step, step_scalars
 from .spectral import analyse, box_mask, synthesize
 
 
@@ -40,7 +40,7 @@ def _div(w1, w2, p):
 
 def area_excess(full, p, n):
     """J at step n, the cancellation-free grid mean of sqrt(1 + x) - 1."""
-    rr = r0(p.time(n))
+    rr = p.r0(p.time(n))
     g1, g2 = gradient_fields(full, p)
     x = (g1 * g1 + g2 * g2) / (rr * rr)
     return float((x / (1.0 + np.sqrt(1.0 + x))).mean())
@@ -48,7 +48,7 @@ def area_excess(full, p, n):
 
 def area_gradient(full, p, n):
     """Coefficients of dJ/dPhi (grid-value gradient) at step n."""
-    rr = r0(p.time(n))
+    rr = p.r0(p.time(n))
     g1, g2 = gradient_fields(full, p)
     x = (g1 * g1 + g2 * g2) / (rr * rr)
     scale = 1.0 / (p.n1 * p.n2 * rr * rr * np.sqrt(1.0 + x))

@@ -16,7 +16,6 @@ The readings used here:
 
 import numpy as np
 
-from .model import r0
 from .spectral import synthesize
 
 
@@ -31,7 +30,7 @@ def gradient_fields(full, p):
 def diagnostics(full, p, n):
     """(mean radius, averaged velocity <Phi_t>, area excess J) at step n."""
     t = p.time(n)
-    rr = r0(t)
+    rr = p.r0(t)
     g1, g2 = gradient_fields(full, p)
     q = g1 * g1 + g2 * g2
     mean_radius = rr + full[0, 0].real

@@ -6,8 +6,8 @@ Eq. (1) (Section 2) for the Fourier components of the flame perturbation:
                  - theta^2/(2 r0^2) * sum_l l.(k-l) Phi~_l Phi~_{k-l} + f~_k(t),
     sigma_k(t) = -theta^2 |k|^2 / r0^2 + gamma*theta*|k| / (2 r0),
 
-with r0(t) = t (Section 2, choice of the reference radius) and f~ = 0 (the
-paper's runs apply no forcing). Writing kappa = (s1 k1, s2 k2) with the axis
+with r0(t) = t (Section 2, choice of the reference radius; another law can
+be given) and f~ = 0 (the paper's runs apply no forcing). Writing kappa = (s1 k1, s2 k2) with the axis
 scales s1 = s2 = theta_pi gives the literal equation; other scales are an
 option of this implementation (anisotropic reading of the segment), in which
 sigma_k = -|kappa|^2/r0^2 + gamma |kappa| / (2 r0) and the sum carries
@@ -42,6 +42,8 @@ class Params:
     t0: float = 200.0           # Section 2, initial time of the runs
     dt: float = 0.25
     axis_scale: tuple = field(default=None)
+    # reference radius law t -> r0(t); None is the paper's r0(t) = t (Section 2)
+    r0_law: object = field(default=None)
 
     def scales(self):
         if self.axis_scale is None:
@@ -58,6 +60,9 @@ class Params:
     def time(self, n):
         return self.t0 + n * self.dt
 
+    def r0(self, t):
+        return r0(t) if self.r0_law is None else float(self.r0_law(t))
+
 
 def r0(t):
     """Reference radius law of Section 2: r0(t) = t."""
@@ -69,13 +74,20 @@ def step_scalars(p, n):
 
     c_n = 1/(2 r0(t_n)^2) is the coefficient of the quadratic term once the
     theta_pi factors are carried by kappa; I1 = int r0^-1 dt and
-    I2 = int r0^-2 dt over [t_n, t_{n+1}] for r0 = t.
+    I2 = int r0^-2 dt over [t_n, t_{n+1}]: in closed form for r0 = t, by
+    adaptive Gauss-Kronrod quadrature in FP64 for any other law.
     """
     t = p.time(n)
     t1 = t + p.dt
-    c = 1.0 / (2.0 * r0(t) ** 2)
-    i1 = np.log1p(p.dt / t)
-    i2 = p.dt / (t * t1)
+    c = 1.0 / (2.0 * p.r0(t) ** 2)
+    if p.r0_law is None:
+        i1 = np.log1p(p.dt / t)
+        i2 = p.dt / (t * t1)
+    else:
+        from scipy.integrate import quad
+
+        i1 = quad(lambda s: 1.0 / p.r0(s), t, t1, epsabs=0.0, epsrel=1e-13)[0]
+        i2 = quad(lambda s: 1.0 / p.r0(s) ** 2, t, t1, epsabs=0.0, epsrel=1e-13)[0]
     return c, i1, i2
 
 
@@ -113,7 +125,7 @@ def rhs(full, p, t):
     """Right-hand side of Eq. (1) at time t with f = 0 (full array)."""
     k1, k2 = p.kappa()
     kap = np.sqrt(k1 * k1 + k2 * k2)
-    rr = r0(t)
+    rr = p.r0(t)
     sigma = -kap * kap / rr ** 2 + p.gamma * kap / (2.0 * rr)
     return (sigma * full - convolution_sum(full, p) / (2.0 * rr ** 2)) * box_mask(p.n1, p.n2)
 

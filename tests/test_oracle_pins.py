@@ -155,3 +155,38 @@ def test_gradient_is_band_limited():
     assert np.all(lam[~oracle.box_mask(n1, n2)] == 0)
     grid = oracle.synthesize(lam)
     assert np.abs(grid.imag).max() < 1e-12 * np.abs(grid.real).max()
+
+
+def test_general_r0_law_scalars_match_closed_forms():
+    """A user reference-radius law goes through FP64 adaptive quadrature; for
+    r0 = t and for a linear law r0 = a + b t the integrals have closed forms."""
+    for n in (0, 7, 123):
+        p0 = oracle.Params(16, 16, t0=200.0, dt=0.3)
+        pq = oracle.Params(16, 16, t0=200.0, dt=0.3, r0_law=lambda t: t)
+        c0, a0, b0 = oracle.step_scalars(p0, n)
+        cq, aq, bq = oracle.step_scalars(pq, n)
+        assert abs(cq - c0) <= 1e-15 * c0 and abs(aq - a0) <= 1e-13 * a0 and abs(bq - b0) <= 1e-13 * b0
+    a, b, dt, t0 = 150.0, 0.5, 0.4, 3.0
+    p = oracle.Params(16, 16, t0=t0, dt=dt, r0_law=lambda t: a + b * t)
+    for n in (0, 11):
+        t, t1 = t0 + n * dt, t0 + (n + 1) * dt
+        c, i1, i2 = oracle.step_scalars(p, n)
+        assert abs(c - 1.0 / (2.0 * (a + b * t) ** 2)) <= 1e-15 * c
+        assert abs(i1 - np.log1p(b * dt / (a + b * t)) / b) <= 1e-13 * i1
+        assert abs(i2 - dt / ((a + b * t) * (a + b * t1))) <= 1e-13 * i2
+
+
+def test_constant_radius_linear_growth_is_exponential():
+    """With r0 = R fixed, a small single mode grows by exactly
+    exp(n dt (-|k|^2/R^2 + gamma |k| / (2R))) (the linear part is integrated
+    exactly by the scheme; the quadratic term is negligible at amplitude 1e-30)."""
+    R, n1, n2, dt, steps = 30.0, 32, 64, 0.5, 40
+    p = oracle.Params(n1, n2, t0=1.0, dt=dt, gamma=0.8, r0_law=lambda t: R)
+    full = np.zeros((n1, n2), dtype=np.complex128)
+    full[3, 5] = 1e-30 * (0.6 + 0.8j)
+    full[-3, -5] = np.conj(full[3, 5])
+    out = oracle.run(full, p, steps)
+    kap = np.hypot(3.0, 5.0)
+    sigma = -kap ** 2 / R ** 2 + 0.8 * kap / (2.0 * R)
+    want = full[3, 5] * np.exp(steps * dt * sigma)
+    assert abs(out[3, 5] - want) <= 1e-12 * abs(want)
