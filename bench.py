@@ -80,6 +80,10 @@ def cpu_oracle_baseline(w, half, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or steps >= w.steps:
             break
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
     return {
         "value": w.points * steps / el,
         "unit": "point-steps/s",
@@ -87,7 +91,28 @@ def cpu_oracle_baseline(w, half, seconds):
         "kind": "oracle",
         "sample": f"first {steps} steps of {w.name} from its initial condition, FP64 numpy "
                   f"(single-threaded pocketfft), {el:.1f} s",
+        "host_cpu_count": os.cpu_count(),
+        "host_affinity": affinity,
     }, steps, oracle.full_to_half(cur, w.n1, w.n2)
+
+
+def copy_bandwidth(nbytes, reps=20):
+    """Read + write GB/s of a plain device copy of nbytes (torch copy kernel), HIP events."""
+    import torch
+
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def adjoint_leg(steps, every, reps=2):
@@ -315,6 +340,13 @@ def main():
         "step_bytes": nbytes["row"] + nbytes["col"],
         "step_hbm_frac": (nbytes["row"] + nbytes["col"]) / (ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "diagnostics_at_first_checkpoint": final_diag,
+    }
+    # the same step bytes against a plain device copy measured on this GPU
+    copy_gbs = copy_bandwidth(256 << 20)
+    result["copy_bandwidth"] = {
+        "GB_s": copy_gbs, "bytes": 256 << 20,
+        "step_frac": (nbytes["row"] + nbytes["col"]) / (ms / args.steps * 1e-3) / 1e9 / copy_gbs,
+        "dominant_kernel_frac": achieved / copy_gbs,
     }
 
     if args.adjoint_steps > 0:

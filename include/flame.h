@@ -65,9 +65,11 @@ typedef struct {
   int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 4096] */
   double gamma;           /* density contrast 1 - rho_b/rho_u, >= 0 */
   double theta_pi;        /* segment integer theta_pi, > 0 */
-  double t0;              /* time of step index 0, > 0 (r0(t) = t) */
+  double t0;              /* time of step index 0, > 0 */
   double dt;              /* time step, > 0 */
   double axis_scale[2];   /* wavenumber scale per axis; {0, 0} means {theta_pi, theta_pi} */
+  int32_t r0_law;         /* reference radius: 0 r0(t) = t (Section 2); 1 a table (flame_set_r0_table) */
+  int32_t reserved;       /* 0 */
 } flame_desc;
 
 /* Bytes of one flame's state buffer (complex64 S, see the layout above). */
@@ -146,6 +148,18 @@ int flame_adjoint_step(flame_plan plan, int32_t flame, int64_t n, const void* st
  * written as a cotangent (see flame_adjoint_step):
  *   lam_out = -Pi div( grad Phi / (P r0^2 sqrt(1 + |grad Phi|^2 / r0^2)) ). */
 int flame_area_gradient(flame_plan plan, int32_t flame, int64_t n, const void* state, void* lam_out);
+
+/* Reference-radius table of flame `flame` (r0_law = 1): `table` (dev, FP64,
+ * caller-owned, n_entries x 3, entry n = {r0(t_n), I1_n, I2_n} with
+ * t_n = t0 + n dt, I1_n = int_{t_n}^{t_{n+1}} ds / r0(s) and
+ * I2_n = int ds / r0(s)^2) gives the coefficients of Eq. (1) at step n:
+ * c_n = 1/(2 r0(t_n)^2), the exact linear propagator
+ * exp(-|kappa|^2 I2_n + gamma |kappa| I1_n / 2), and r0 for the diagnostics.
+ * It stays bound until replaced or flame_destroy. A step, adjoint step or
+ * diagnostic at step index n needs n < n_entries; calls that would go beyond
+ * the table, or reach a flame with r0_law = 1 and no table, fail with
+ * FLAME_ERR_INVALID_ARG before launching anything. */
+int flame_set_r0_table(flame_plan plan, int32_t flame, const double* table, int64_t n_entries);
 
 /* Grid field of any spectrum in the state layout (a state or a cotangent):
  * phi(x_j) = sum_k spec~_k exp(i k.x_j) (dev, float32, n1 x n2 row-major). */

@@ -348,8 +348,8 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
   gf2* const A1 = glob(f.A1);
   gf2* const A2 = glob(f.A2);
   const float inv_r2 = [&] {
-    const double tt = f.t0 + (double)n * f.dt;
-    return (float)(1.0 / (tt * tt));
+    const double r = r0_at(f, n);
+    return (float)(1.0 / (r * r));
   }();
 
   float ma[ff::kPts], mb[ff::kPts];

@@ -69,6 +69,8 @@ int check_desc(const flame_desc* d, Sizes* s) {
       return fail(FLAME_ERR_INVALID_ARG, "axis_scale must be finite and >= 0");
   if ((d->axis_scale[0] == 0.0) != (d->axis_scale[1] == 0.0))
     return fail(FLAME_ERR_INVALID_ARG, "axis_scale must be both zero (use theta_pi) or both positive");
+  if (d->r0_law != 0 && d->r0_law != 1) return fail(FLAME_ERR_INVALID_ARG, "r0_law must be 0 (r0 = t) or 1 (table)");
+  if (d->reserved != 0) return fail(FLAME_ERR_INVALID_ARG, "reserved must be 0");
   if (s) {
     s->logn1 = l1;
     s->logn2 = l2;
@@ -220,6 +222,19 @@ namespace {
 int check_plan(flame_plan p, int flame = 0) {
   if (!p) return fail(FLAME_ERR_INVALID_ARG, "null plan");
   if (flame < 0 || flame >= p->nfl) return fail(FLAME_ERR_INVALID_ARG, "flame index %d out of range [0, %d)", flame, p->nfl);
+  return FLAME_OK;
+}
+
+// Every step index in [n_first, n_last] of flames [f0, f1) with a tabulated
+// reference radius must have a table entry (the kernels index it by n).
+int check_r0(flame_plan p, int f0, int f1, long long n_first, long long n_last) {
+  for (int f = f0; f < f1; ++f) {
+    if (p->descs[f].r0_law != 1) continue;
+    if (!p->hdev[f].r0tab) return fail(FLAME_ERR_INVALID_ARG, "flame %d: r0_law = 1 but no r0 table set", f);
+    if (n_first < 0 || n_last >= p->hdev[f].r0n)
+      return fail(FLAME_ERR_INVALID_ARG, "flame %d: step index %lld is beyond its r0 table of %lld entries", f,
+                  n_first < 0 ? n_first : n_last, p->hdev[f].r0n);
+  }
   return FLAME_OK;
 }
 
@@ -640,6 +655,10 @@ int flame_step(flame_plan p, int32_t nsteps) {
   int rc = check_plan(p);
   if (rc) return rc;
   if (nsteps < 0) return fail(FLAME_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (nsteps > 0) {
+    rc = check_r0(p, 0, p->nfl, p->n, p->n + nsteps - 1);
+    if (rc) return rc;
+  }
   DeviceGuard g(p->device);
   for (int f = 0; f < p->nfl; ++f)
     if (!p->w_valid[f]) {
@@ -682,6 +701,8 @@ int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
   int rc = check_plan(p, flame);
   if (rc) return rc;
   if (!out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  rc = check_r0(p, flame, flame + 1, p->n, p->n);
+  if (rc) return rc;
   DeviceGuard g(p->device);
   const Sizes& s = p->layout.sizes[flame];
   // the area is a grid mean on the physical N1 x N2 grid: with the product
@@ -710,6 +731,8 @@ int flame_adjoint_step(flame_plan p, int32_t flame, int64_t n, const void* state
   if (rc) return rc;
   if (!state_n || !lam_in || !lam_out) return fail(FLAME_ERR_INVALID_ARG, "null state or cotangent pointer");
   if (state_n == lam_out) return fail(FLAME_ERR_INVALID_ARG, "state_n must not alias lam_out");
+  rc = check_r0(p, flame, flame + 1, n, n);
+  if (rc) return rc;
   DeviceGuard g(p->device);
   const Sizes& s = p->layout.sizes[flame];
   flame::FlameDev* fd = p->ddev + flame;
@@ -732,6 +755,8 @@ int flame_area_gradient(flame_plan p, int32_t flame, int64_t n, const void* stat
   if (rc) return rc;
   if (!state || !lam_out) return fail(FLAME_ERR_INVALID_ARG, "null state or cotangent pointer");
   if (state == lam_out) return fail(FLAME_ERR_INVALID_ARG, "state must not alias lam_out");
+  rc = check_r0(p, flame, flame + 1, n, n);
+  if (rc) return rc;
   DeviceGuard g(p->device);
   const Sizes& s = p->layout.sizes[flame];
   flame::FlameDev* fd = p->ddev + flame;
@@ -740,6 +765,27 @@ int flame_area_gradient(flame_plan p, int32_t flame, int64_t n, const void* stat
   flame::launch_adj_col(s.logn1, flame::SEED_C, s.tiles, p->stream, fd, n, nullptr, nullptr, lam_out);
   p->w_valid[flame] = 0;
   return last_launch("area gradient launch");
+}
+
+int flame_set_r0_table(flame_plan p, int32_t flame, const double* table, int64_t n_entries) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (p->descs[flame].r0_law != 1) return fail(FLAME_ERR_INVALID_ARG, "flame %d has r0_law = 0 (r0 = t)", flame);
+  if (!table || n_entries <= 0) return fail(FLAME_ERR_INVALID_ARG, "need a table of at least one entry");
+  if (reinterpret_cast<uintptr_t>(table) % 8) return fail(FLAME_ERR_INVALID_ARG, "table must be 8-byte aligned");
+  DeviceGuard g(p->device);
+  p->hdev[flame].r0tab = table;
+  p->hdev[flame].r0n = n_entries;
+  p->hdev_full[flame].r0tab = table;
+  p->hdev_full[flame].r0n = n_entries;
+  hipError_t e = hipMemcpyAsync(p->ddev + flame, &p->hdev[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
+                                p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ddev_full + flame, &p->hdev_full[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
+                       p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host entries may change again
+  if (e != hipSuccess) return hip_fail(e, "r0 table update");
+  return FLAME_OK;
 }
 
 int flame_synthesize(flame_plan p, int32_t flame, const void* spec, float* phi) {
@@ -841,6 +887,8 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
   if (steps <= 0) return fail(FLAME_ERR_INVALID_ARG, "steps must be > 0");
+  rc = check_r0(p, 0, p->nfl, p->n, p->n);  // every timed step runs at the current index
+  if (rc) return rc;
   DeviceGuard g(p->device);
   // save every state in its flame's adjoint scratch (each at least 2x the state)
   hipError_t e;

@@ -28,6 +28,8 @@ struct FlameDev {
   const float2* tw6;   // twiddles of the length-3N1/4 transform (product grid), or null
   const float2* tw6_8; // the same for 8 points per thread
   double* part;        // per-workgroup partial sums of the diagnostics
+  const double* r0tab; // reference-radius table {r0(t_n), I1_n, I2_n} (r0_law = 1), or null for r0 = t
+  long long r0n;       // its entries
   int n1, n2;
   int m;               // stored k2 columns, N2/4
   int h1;              // stored k1 slots, N1/2

@@ -201,8 +201,8 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
     float qa[PTS];
     double area = 0.0;
     const float inv_r2 = [&] {
-      const double t0 = f.t0 + (double)n * f.dt;
-      return (float)(1.0 / (t0 * t0));
+      const double r = r0_at(f, n);
+      return (float)(1.0 / (r * r));
     }();
     // both rows' inputs come in one 16-byte load per register (w_index layout)
     float2 vr[2][PTS];
@@ -673,10 +673,10 @@ __global__ void __launch_bounds__(kDiagThreads)
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double t = f.t0 + (double)n * f.dt;
+    const double r = r0_at(f, n);
     const float2 s00 = f.S[f.n1 / 4];
-    out[0] = t + (double)s00.x;
-    out[1] = rs[0] / (2.0 * t * t);
+    out[0] = r + (double)s00.x;
+    out[1] = rs[0] / (2.0 * r * r);
     out[2] = ra[0] / ((double)f.n1 * (double)f.n2);
     out[3] = (rb[0] == 0.0 && isfinite(out[2])) ? 1.0 : 0.0;
   }

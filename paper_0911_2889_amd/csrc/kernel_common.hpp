@@ -117,17 +117,36 @@ struct StepScalars {
   float i2;   // int_{t_n}^{t_{n+1}} dt / r0^2
 };
 
-// r0(t) = t (Section 2): c_n = 1/(2 t_n^2), I1 = ln(t_{n+1}/t_n),
-// I2 = 1/t_n - 1/t_{n+1}. The time is formed in double; the scalars need only
-// float accuracy.
+// Entry of the reference-radius table for step index n (clamped to the
+// table; the host checks the range before every launch).
+__device__ __forceinline__ const double* r0_entry(const FlameDev& f, long long n) {
+  const long long i = n < 0 ? 0 : (n >= f.r0n ? f.r0n - 1 : n);
+  return f.r0tab + 3 * i;
+}
+
+// r0(t_n): the table's, or t_n for the paper's law r0(t) = t (Section 2).
+__device__ __forceinline__ double r0_at(const FlameDev& f, long long n) {
+  return f.r0tab ? r0_entry(f, n)[0] : f.t0 + (double)n * f.dt;
+}
+
+// Scalars of step n: c_n = 1/(2 r0(t_n)^2), I1 = int r0^-1, I2 = int r0^-2
+// over [t_n, t_{n+1}]: for r0(t) = t in closed form, I1 = ln(t_{n+1}/t_n),
+// I2 = 1/t_n - 1/t_{n+1} (the time formed in double); else from the table.
 // `rows` is the number of theta rows of the grid the quadratic term was
 // formed on (N1, or 3 N1/4 on the product grid): the forward transforms are
-// unnormalised, so a carries 1/(rows * N2).
+// unnormalised, so a = dt c_n / (rows N2).
 __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n, int rows) {
+  StepScalars s;
+  if (f.r0tab) {
+    const double* e = r0_entry(f, n);
+    s.a = (float)(f.dt / (2.0 * e[0] * e[0] * (double)rows * (double)f.n2));
+    s.i1 = (float)e[1];
+    s.i2 = (float)e[2];
+    return s;
+  }
   const float t = (float)(f.t0 + (double)n * f.dt);
   const float dt = (float)f.dt;
   const float x = dt / t;
-  StepScalars s;
   s.a = 0.5f * x / (t * (float)rows * (float)f.n2);
   s.i1 = log1pf(x);
   s.i2 = x / (t + dt);

@@ -23,7 +23,7 @@ EXPORTS = (
     "flame_step_index", "flame_step", "flame_diagnostics", "flame_adjoint_step", "flame_area_gradient",
     "flame_synthesize", "flame_timing_begin", "flame_timing_end", "flame_set_graph_steps",
     "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
-    "flame_get_product_grid", "flame_autotune", "flame_destroy",
+    "flame_get_product_grid", "flame_set_r0_table", "flame_autotune", "flame_destroy",
     "flame_last_error",
 )
 
@@ -37,6 +37,8 @@ class FlameDesc(ctypes.Structure):
         ("t0", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("axis_scale", ctypes.c_double * 2),
+        ("r0_law", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -80,6 +82,7 @@ def load():
         "flame_get_points_per_thread": [P, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "flame_autotune": [P, i32, ctypes.POINTER(i32)],
         "flame_set_product_grid": [P, i32, i32, i32],
+        "flame_set_r0_table": [P, i32, ctypes.c_void_p, ctypes.c_int64],
         "flame_get_product_grid": [P, i32, i32, ctypes.POINTER(i32)],
         "flame_timing_begin": [P],
         "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
@@ -102,12 +105,13 @@ def check(rc):
     return rc
 
 
-def make_desc(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25, axis_scale=None):
+def make_desc(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25, axis_scale=None, r0_law=0):
     d = FlameDesc()
     d.n1, d.n2 = int(n1), int(n2)
     d.gamma, d.theta_pi, d.t0, d.dt = float(gamma), float(theta_pi), float(t0), float(dt)
     sc = (0.0, 0.0) if axis_scale is None else (float(axis_scale[0]), float(axis_scale[1]))
     d.axis_scale[0], d.axis_scale[1] = sc
+    d.r0_law, d.reserved = int(r0_law), 0
     return d
 
 

@@ -19,7 +19,9 @@ class FlameEnsemble:
     """A plan over one or more flames (possibly of different grids).
 
     descs: list of dicts with keys n1, n2 and optionally gamma, theta_pi, t0,
-    dt, axis_scale. The plan is bound to the current torch stream of `device`.
+    dt, axis_scale, r0_law (1: the reference radius comes from a table given
+    with set_r0_table). The plan is bound to the current torch stream of
+    `device`.
     """
 
     def __init__(self, descs, device="cuda", ws_fill=None):
@@ -152,6 +154,20 @@ class FlameEnsemble:
         native.check(self.lib.flame_get_points_per_thread(self.plan, int(n1), int(n2), ctypes.byref(c),
                                                           ctypes.byref(r)))
         return c.value, r.value
+
+    def set_r0_table(self, table, flame=0):
+        """Reference-radius table of a flame with r0_law = 1: a float64 tensor of
+        shape (n, 3) on the plan's device, row n = (r0(t_n), int_{t_n}^{t_n+1} ds/r0,
+        int ds/r0^2). The tensor is kept alive by this object."""
+        self._check_flame(flame)
+        if table.dtype != torch.float64 or table.dim() != 2 or table.shape[1] != 3 or table.device != self.device:
+            raise ValueError("table must be a float64 (n, 3) tensor on the plan's device")
+        table = table.contiguous()
+        native.check(self.lib.flame_set_r0_table(self.plan, int(flame), ctypes.c_void_p(table.data_ptr()),
+                                                 int(table.shape[0])))
+        if not hasattr(self, "_r0_tables"):
+            self._r0_tables = {}
+        self._r0_tables[flame] = table
 
     def set_product_grid(self, n1, n2, enable):
         """Form the quadratic term on 3*n1/4 theta rows (True) or on n1 rows (False)

@@ -280,3 +280,62 @@ def test_product_grid_switches_mid_run_and_keeps_diagnostics(flame):
     with pytest.raises(RuntimeError):
         small = make_sim(flame, small_workload(64, 128, 1))
         small.set_product_grid(64, 128, True)
+
+
+def r0_table(p, n_entries):
+    """The oracle's reference-radius scalars as the library's table rows
+    (r0(t_n), I1_n, I2_n); I1, I2 by the oracle's FP64 quadrature."""
+    rows = []
+    for n in range(n_entries):
+        _, i1, i2 = oracle.step_scalars(p, n)
+        rows.append((p.r0(p.time(n)), i1, i2))
+    return torch.tensor(rows, dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n1,n2,product", [(64, 128, False), (256, 512, True), (256, 512, False)])
+def test_tabulated_reference_radius_matches_oracle(flame, n1, n2, product):
+    """A reference radius other than the paper's r0 = t (here r0 = 2 + 0.5 t),
+    given to the library as a table: steps, diagnostics and the adjoint step
+    against the oracle integrating the same law by quadrature."""
+    law = lambda t: 2.0 + 0.5 * t  # noqa: E731
+    t0, dt, steps = 4.0, 0.2, 30
+    w = small_workload(n1, n2, seed=n1 + 11, amp=0.05, t0=t0, dt=dt)
+    half = synth.workload_spectrum(w)
+    p = oracle.Params(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=t0, dt=dt, r0_law=law)
+    refs = oracle_trajectory(half, p, [steps])
+    p_t = oracle.Params(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=t0, dt=dt)
+    assert rel_l2(refs[steps], oracle_trajectory(half, p_t, [steps])[steps]) > 1e-3  # the law matters
+    sim = flame.FlameSim(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=t0, dt=dt, r0_law=1)
+    if n1 >= 128:
+        sim.set_product_grid(n1, n2, product)
+    sim.set_spectrum(half)
+    with pytest.raises(flame.native.FlameError):
+        sim.step(1)  # no table yet
+    sim.set_r0_table(r0_table(p, steps + 1))
+    sim.step(steps)
+    got = sim.spectrum().cpu().numpy()
+    assert rel_l2(got, refs[steps]) < 1e-5
+    d = sim.diagnostics()
+    mr, vel, area = oracle.diagnostics(oracle.half_to_full(refs[steps], n1, n2), p, steps)
+    # r_bar = r0(t) + Re Phi~_0: the FP32 mean mode within the parity budget
+    phi0 = mr - law(p.time(steps))
+    assert abs(d["mean_radius"] - mr) < 1e-5 * abs(phi0) + 1e-12 * mr
+    assert abs(d["velocity"] - vel) < 2e-5 * abs(vel)
+    assert abs(d["area_excess"] - area) < 2e-5 * abs(area)
+    with pytest.raises(flame.native.FlameError):
+        sim.step(2)  # the second step needs entry 31, beyond the table
+    assert sim.step_index == steps
+    # one adjoint step at n = 5 with the law's scalars
+    lam = synth.workload_spectrum(small_workload(n1, n2, seed=n2 + 1, amp=1.0, t0=t0, dt=dt))
+    st = sim.new_cotangent()
+    st.copy_(sim.states[0])
+    li = sim.new_cotangent()
+    sim.set_spectrum(lam, n=steps)
+    li.copy_(sim.states[0])
+    lo = sim.new_cotangent()
+    sim.adjoint_step(5, st, li, lo)
+    sf = oracle.half_to_full(got.astype(np.complex128), n1, n2)
+    lf = oracle.half_to_full(lam.astype(np.complex128), n1, n2)
+    ref = oracle.full_to_half(oracle.step_adjoint(sf, lf, p, 5), n1, n2)
+    sim.states[0].copy_(lo)
+    assert rel_l2(sim.spectrum().cpu().numpy(), ref) < 1e-5

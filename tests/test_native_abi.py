@@ -52,9 +52,13 @@ def test_state_and_workspace_sizes(native):
     (dict(n1=64, n2=128, gamma=float("nan")), -1),
     (dict(n1=64, n2=128, theta_pi=0.0), -1),
     (dict(n1=64, n2=128, axis_scale=(1.0, 0.0)), -1),
+    (dict(n1=64, n2=128, r0_law=2), -1),
+    (dict(n1=64, n2=128, r0_law=-1), -1),
 ])
 def test_bad_descriptors_are_rejected(native, kw, code):
     d = native.make_desc(**kw)
+    assert native.load().flame_state_bytes(ctypes.byref(native.make_desc(64, 128, r0_law=1)),
+                                           ctypes.byref(ctypes.c_size_t())) == 0
     out = ctypes.c_size_t()
     rc = native.load().flame_state_bytes(ctypes.byref(d), ctypes.byref(out))
     assert rc == code
