@@ -7,7 +7,7 @@ Eq. (1) (Section 2) for the Fourier components of the flame perturbation:
     sigma_k(t) = -theta^2 |k|^2 / r0^2 + gamma*theta*|k| / (2 r0),
 
 with r0(t) = t (Section 2, choice of the reference radius; another law can
-be given) and f~ = 0 (the paper's runs apply no forcing). Writing kappa = (s1 k1, s2 k2) with the axis
+be given) and f~ = 0 as in the paper's runs (a forcing can be given). Writing kappa = (s1 k1, s2 k2) with the axis
 scales s1 = s2 = theta_pi gives the literal equation; other scales are an
 option of this implementation (anisotropic reading of the segment), in which
 sigma_k = -|kappa|^2/r0^2 + gamma |kappa| / (2 r0) and the sum carries
@@ -44,6 +44,14 @@ class Params:
     axis_scale: tuple = field(default=None)
     # reference radius law t -> r0(t); None is the paper's r0(t) = t (Section 2)
     r0_law: object = field(default=None)
+    # forcing f~_k(t) of Eq. (1): None (the paper's runs), a full Hermitian
+    # coefficient array, or a function t -> such an array
+    forcing: object = field(default=None)
+
+    def forcing_at(self, t):
+        if self.forcing is None:
+            return None
+        return self.forcing(t) if callable(self.forcing) else self.forcing
 
     def scales(self):
         if self.axis_scale is None:
@@ -122,12 +130,16 @@ def convolution_sum(full, p):
 
 
 def rhs(full, p, t):
-    """Right-hand side of Eq. (1) at time t with f = 0 (full array)."""
+    """Right-hand side of Eq. (1) at time t (full array), with the forcing if given."""
     k1, k2 = p.kappa()
     kap = np.sqrt(k1 * k1 + k2 * k2)
     rr = p.r0(t)
     sigma = -kap * kap / rr ** 2 + p.gamma * kap / (2.0 * rr)
-    return (sigma * full - convolution_sum(full, p) / (2.0 * rr ** 2)) * box_mask(p.n1, p.n2)
+    out = sigma * full - convolution_sum(full, p) / (2.0 * rr ** 2)
+    f = p.forcing_at(t)
+    if f is not None:
+        out = out + f
+    return out * box_mask(p.n1, p.n2)
 
 
 def symmetrise(full):
@@ -145,11 +157,18 @@ def symmetrise(full):
 
 
 def step(full, p, n):
-    """One integrating-factor Euler step n -> n+1 of Eq. (1) (full array)."""
+    """One integrating-factor Euler step n -> n+1 of Eq. (1) (full array).
+
+    The forcing, like the quadratic term, is taken explicitly at t_n:
+    Phi~^{n+1} = E_k (Phi~^n + dt (N_k(Phi~^n, t_n) + f~_k(t_n))).
+    """
     c, _, _ = step_scalars(p, n)
     e = np.exp(growth_exponent(p, n))
-    nonlinear = -c * convolution_sum(full, p)
-    new = e * (full + p.dt * nonlinear) * box_mask(p.n1, p.n2)
+    rhs_n = -c * convolution_sum(full, p)
+    f = p.forcing_at(p.time(n))
+    if f is not None:
+        rhs_n = rhs_n + f
+    new = e * (full + p.dt * rhs_n) * box_mask(p.n1, p.n2)
     return symmetrise(new)
 
 

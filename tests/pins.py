@@ -335,3 +335,23 @@ def pin_trajectory_gradient_fd(n1=16, n2=24, seed=7, t0=3.0, dt=0.2, nsteps=10, 
 
 def pin_convolution_direct_anisotropic():
     return pin_convolution_direct(16, 24, seed=40, s=(2.0, 0.5))
+
+
+def pin_forcing_geometric_series(R=30.0, n1=32, n2=64, dt=0.5, steps=25, mode=(2, 3)):
+    """Constant radius R, constant forcing F on one small mode, zero start.
+
+    Eq. (1) is then linear in that mode with a constant rate sigma_k, and the
+    integrating-factor step Phi^{n+1} = E (Phi^n + dt F) sums to the geometric
+    series dt F E (1 - E^n) / (1 - E), E = exp(dt sigma_k), written by hand;
+    the mirror mode must hold the conjugate.
+    """
+    f = np.zeros((n1, n2), dtype=np.complex128)
+    a, b = mode
+    f[a, b] = 1e-28 * (0.3 - 0.4j)
+    f[-a, -b] = np.conj(f[a, b])
+    p = oracle.Params(n1, n2, t0=1.0, dt=dt, gamma=GAMMA, r0_law=lambda t: R, forcing=f)
+    out = oracle.run(np.zeros((n1, n2), dtype=np.complex128), p, steps)
+    kap = np.hypot(float(a), float(b))
+    e = np.exp(dt * (-kap ** 2 / R ** 2 + GAMMA * kap / (2.0 * R)))
+    want = dt * f[a, b] * e * (1.0 - e ** steps) / (1.0 - e)
+    return max(abs(out[a, b] - want), abs(out[-a, -b] - np.conj(want))) / abs(want)

@@ -27,6 +27,7 @@ THRESHOLDS = {
     "pin_diagnostics_single_cosine": 1e-12,
     "pin_adjoint_dot_product": 1e-10,
     "pin_trajectory_gradient_fd": 1e-5,
+    "pin_forcing_geometric_series": 1e-12,
 }
 
 
@@ -176,11 +177,24 @@ def _adjoint_without_decay(monkeypatch):
     monkeypatch.setattr(oadj, "step_adjoint", adj)
 
 
+def _forcing_outside_integrating_factor(monkeypatch):
+    # the forcing added after the decay/growth factor instead of inside it
+    def step(full, p, n):
+        c, _, _ = om.step_scalars(p, n)
+        e = np.exp(om.growth_exponent(p, n))
+        new = e * (full - p.dt * c * om.convolution_sum(full, p))
+        f = p.forcing_at(p.time(n))
+        if f is not None:
+            new = new + p.dt * f
+        return om.symmetrise(new * oracle.box_mask(p.n1, p.n2))
+    monkeypatch.setattr(om, "step", step)
+
+
 MUTATIONS = [
     _flip_nonlinear_sign, _drop_instability_term, _euler_radius_integral, _missing_half_in_c,
     _transposed_kappa, _cross_term_dropped, _aliased_grid, _nonlinear_at_new_time,
     _velocity_without_half, _area_without_sqrt, _adjoint_missing_factor_two,
-    _adjoint_without_decay,
+    _adjoint_without_decay, _forcing_outside_integrating_factor,
 ]
 
 

@@ -190,3 +190,42 @@ def test_constant_radius_linear_growth_is_exponential():
     sigma = -kap ** 2 / R ** 2 + 0.8 * kap / (2.0 * R)
     want = full[3, 5] * np.exp(steps * dt * sigma)
     assert abs(out[3, 5] - want) <= 1e-12 * abs(want)
+
+
+def test_constant_forcing_response_is_a_geometric_series():
+    """With a constant radius, a constant forcing on one small mode and a zero
+    initial state the scheme sums a geometric series (the mirror mode holds
+    the conjugate)."""
+    assert pins.pin_forcing_geometric_series() < 1e-12
+    assert pins.pin_forcing_geometric_series(R=12.0, dt=0.2, steps=40, mode=(5, 1)) < 1e-12
+
+
+def test_forcing_enters_the_exact_solution_of_eq1():
+    """The forced step converges at first order to the ODE solution of Eq. (1)
+    with the same forcing (DOP853 on the literal right-hand side)."""
+    from scipy.integrate import solve_ivp
+
+    n1 = n2 = 16
+    rng = np.random.default_rng(3)
+    half = (rng.standard_normal((2 * 3 + 1, 4)) + 1j * rng.standard_normal((2 * 3 + 1, 4))) * 1e-2
+    full0 = oracle.symmetrise(oracle.half_to_full(half, n1, n2))  # real fields: Hermitian arrays
+    force = oracle.symmetrise(oracle.half_to_full(
+        (rng.standard_normal((7, 4)) + 1j * rng.standard_normal((7, 4))) * 1e-3, n1, n2))
+    forcing = lambda t: force * np.cos(0.3 * t)  # noqa: E731
+    t0, T = 5.0, 2.0
+    mask = oracle.box_mask(n1, n2)
+
+    def f(t, y):
+        full = y.reshape(n1, n2)
+        pp = oracle.Params(n1, n2, t0=t0, dt=1.0, forcing=forcing)
+        return (oracle.rhs(full, pp, t) * mask).ravel()
+
+    ref = solve_ivp(f, (t0, t0 + T), (full0 * mask).ravel().astype(np.complex128), method="DOP853",
+                    rtol=1e-11, atol=1e-16).y[:, -1].reshape(n1, n2)
+    errs = []
+    for nsteps in (20, 40, 80):
+        p = oracle.Params(n1, n2, t0=t0, dt=T / nsteps, forcing=forcing)
+        errs.append(np.linalg.norm(oracle.run(full0, p, nsteps) - ref) / np.linalg.norm(ref))
+    assert errs[-1] < 1e-3
+    for a, b in zip(errs, errs[1:]):
+        assert 1.6 < a / b < 2.4
