@@ -24,7 +24,7 @@ KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889
                   "paper_0911_2889_amd/csrc/flame_dev.hpp", "paper_0911_2889_amd/csrc/kernel_common.hpp")
 
 
-def algorithmic_bytes(n1, n2, rows=None):
+def algorithmic_bytes(n1, n2, rows=None, forcing=False):
     """Bytes each kernel of one step must move (FP32 complex = 8 bytes), with
     the quadratic term formed on `rows` theta rows (n1, or 3*n1/4 on the
     product grid; default n1).
@@ -32,12 +32,13 @@ def algorithmic_bytes(n1, n2, rows=None):
     row: read the column-transformed gradient spectrum rows x (2K2+1), write
          the row transform of |grad Phi|^2, rows x (K2+1);
     col: read that rows x (K2+1), read and write the state (2K1+1) x (K2+1),
-         write the next gradient spectrum rows x (2K2+1).
+         write the next gradient spectrum rows x (2K2+1); with a forcing,
+         also read the forcing spectrum (2K1+1) x (K2+1).
     """
     rows = n1 if rows is None else rows
     k1, k2 = (n1 - 1) // 4, (n2 - 1) // 4
     row = 8 * (rows * (2 * k2 + 1) + rows * (k2 + 1))
-    col = 8 * (rows * (k2 + 1) + 2 * (2 * k1 + 1) * (k2 + 1) + rows * (2 * k2 + 1))
+    col = 8 * (rows * (k2 + 1) + (3 if forcing else 2) * (2 * k1 + 1) * (k2 + 1) + rows * (2 * k2 + 1))
     return {"row": row, "col": col}
 
 
@@ -152,6 +153,49 @@ def adjoint_leg(steps, every, reps=2):
     }
 
 
+def forced_leg(sim, w, half, steps, graph_steps, run_steps, unforced_ms, rows):
+    """The same flame with a seeded forcing f~ bound (every mode of the box,
+    amplitude 1e-5/|k|): HIP-event time of `steps` steps in the launch
+    configuration of the main measurement, then per-kernel times of direct
+    launches. The forcing is removed afterwards."""
+    import torch
+
+    import synth
+
+    sim.set_forcing(synth.forcing_spectrum(w, amp=1e-5))
+    sim.set_spectrum(half)
+    run_steps(max(steps // 4, graph_steps), False)  # warm-up
+    sim.set_spectrum(half)
+    sim.step(0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    run_steps(steps, False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    saved = graph_steps
+    sim.set_graph_steps(0)
+    sim.set_spectrum(half)
+    sim.step(0)
+    kt = run_steps(steps, True)
+    torch.cuda.synchronize()
+    sim.set_graph_steps(saved)
+    sim.set_forcing(None)
+    nbytes = algorithmic_bytes(w.n1, w.n2, rows, forcing=True)
+    col_ms = kt["col"][0] / max(1, kt["col"][1])
+    return {
+        "forcing": "every mode of the box, amp 1e-5/|k|, seed workload seed + 7919",
+        "steps": steps, "ms_per_step": ms, "point_steps_per_s": w.points / (ms * 1e-3),
+        "over_unforced": ms / unforced_ms,
+        "step_bytes": nbytes["row"] + nbytes["col"],
+        "step_hbm_frac": (nbytes["row"] + nbytes["col"]) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "col_kernel_ms": col_ms, "col_kernel_GB_s": nbytes["col"] / (col_ms * 1e-3) / 1e9,
+        "kernels_ms_per_step": {k: kt[k][0] / max(1, steps) for k in ("row", "col", "diag")},
+    }
+
+
 def ensemble_leg(steps, graph_steps):
     """The batched ensemble (256 flames of three grids) stepped in graphs of
     graph_steps steps, and with direct launches, timed with HIP events."""
@@ -212,6 +256,8 @@ def main():
                     help="form the quadratic term on 3*N1/4 rows or on N1 rows (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-flame ensemble leg (0 skips it)")
+    ap.add_argument("--forcing-steps", type=int, default=200,
+                    help="steps of the forced-step leg (a seeded forcing bound to the same flame); 0 skips it")
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the checkpointed adjoint leg on 1024x2048 (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -348,6 +394,10 @@ def main():
         "step_frac": (nbytes["row"] + nbytes["col"]) / (ms / args.steps * 1e-3) / 1e9 / copy_gbs,
         "dominant_kernel_frac": achieved / copy_gbs,
     }
+
+    if args.forcing_steps > 0:
+        result["forced"] = forced_leg(sim, w, half, args.forcing_steps, graph_steps, run_steps,
+                                      ms / args.steps, rows)
 
     if args.adjoint_steps > 0:
         result["adjoint"] = adjoint_leg(args.adjoint_steps, 50)

@@ -161,6 +161,25 @@ int flame_area_gradient(flame_plan plan, int32_t flame, int64_t n, const void* s
  * FLAME_ERR_INVALID_ARG before launching anything. */
 int flame_set_r0_table(flame_plan plan, int32_t flame, const double* table, int64_t n_entries);
 
+/* Forcing f~_k(t) of Eq. (1) (Section 2; zero in the paper's runs) for flame
+ * `flame`: `forcing` (dev, complex64, caller-owned, flame_state_bytes, in the
+ * state layout above) holds f~_k for the stored half of the box, or is null
+ * for no forcing (the default). Each step n -> n+1 then takes it explicitly,
+ * inside the propagator like the quadratic term:
+ *   Phi~^{n+1} = E (Phi~^n + dt (f~ - c_n N(Phi~^n))),
+ * before the k2 = 0 column is symmetrised, so its k1 < 0 entries and
+ * Im f~_0 have no effect; entries outside the box are ignored. The buffer is
+ * read by every later step until replaced or flame_destroy: for a forcing
+ * that varies in time, rewrite it (stream-ordered) between calls of
+ * flame_step, which then uses one forcing for all of its nsteps steps. The
+ * adjoint and gradient calls do not depend on it. A grid-size group steps
+ * with a column-kernel variant that reads the forcing while any of its
+ * flames has one bound (members without one are stepped unforced by it);
+ * binding the first or removing the last forcing of a group rebuilds the
+ * step graph at the next flame_step. Waits for the plan's stream. Fails with
+ * FLAME_ERR_INVALID_ARG for a pointer not 8-byte aligned. */
+int flame_set_forcing(flame_plan plan, int32_t flame, const void* forcing);
+
 /* Grid field of any spectrum in the state layout (a state or a cotangent):
  * phi(x_j) = sum_k spec~_k exp(i k.x_j) (dev, float32, n1 x n2 row-major). */
 int flame_synthesize(flame_plan plan, int32_t flame, const void* spec, float* phi);

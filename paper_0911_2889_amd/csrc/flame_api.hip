@@ -156,6 +156,7 @@ struct Group {
   int logn1, logn2, first, count, tiles, rpairs;
   int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
   bool product = false;                        // step on the 3N1/4-row product grid
+  bool forced = false;                         // some flame of the group has a forcing bound
   int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
   int rgroups() const { return (rows() / 2 + rpairs - 1) / rpairs; }
 };
@@ -345,11 +346,10 @@ void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 =
 void launch_step_col(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (gr.product)
     flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                       gr.col_pts, e0,
-                       e1);
+                       gr.col_pts, e0, e1, gr.forced);
   else
     flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                      gr.col_pts, e0, e1);
+                      gr.col_pts, e0, e1, gr.forced);
 }
 
 void drop_graph(flame_plan p) {
@@ -372,8 +372,9 @@ int build_graph(flame_plan p) {
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
       const Group& gr = p->groups[gi];
       const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
-      const flame::KernelLaunch ck = gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts)
-                                                : flame::col_step_kernel(gr.logn1, gr.col_pts);
+      const flame::KernelLaunch ck = gr.product
+                                         ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts, gr.forced)
+                                         : flame::col_step_kernel(gr.logn1, gr.col_pts, gr.forced);
       if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
       const flame::FlameDev* fl = p->ddev + gr.first;
       long long n = s;
@@ -767,6 +768,19 @@ int flame_area_gradient(flame_plan p, int32_t flame, int64_t n, const void* stat
   return last_launch("area gradient launch");
 }
 
+// Rewrite the device copies of flame's two descriptors (step grid and full
+// grid) from the host copies; waits, so the host copies may change again.
+static int upload_dev(flame_plan p, int32_t flame, const char* what) {
+  hipError_t e = hipMemcpyAsync(p->ddev + flame, &p->hdev[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
+                                p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->ddev_full + flame, &p->hdev_full[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
+                       p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return FLAME_OK;
+}
+
 int flame_set_r0_table(flame_plan p, int32_t flame, const double* table, int64_t n_entries) {
   int rc = check_plan(p, flame);
   if (rc) return rc;
@@ -778,13 +792,27 @@ int flame_set_r0_table(flame_plan p, int32_t flame, const double* table, int64_t
   p->hdev[flame].r0n = n_entries;
   p->hdev_full[flame].r0tab = table;
   p->hdev_full[flame].r0n = n_entries;
-  hipError_t e = hipMemcpyAsync(p->ddev + flame, &p->hdev[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
-                                p->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->ddev_full + flame, &p->hdev_full[flame], sizeof(flame::FlameDev), hipMemcpyHostToDevice,
-                       p->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);  // the host entries may change again
-  if (e != hipSuccess) return hip_fail(e, "r0 table update");
+  return upload_dev(p, flame, "r0 table update");
+}
+
+int flame_set_forcing(flame_plan p, int32_t flame, const void* forcing) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (reinterpret_cast<uintptr_t>(forcing) % 8) return fail(FLAME_ERR_INVALID_ARG, "forcing must be 8-byte aligned");
+  DeviceGuard g(p->device);
+  const float2* fp = static_cast<const float2*>(forcing);
+  p->hdev[flame].F = fp;
+  p->hdev_full[flame].F = fp;
+  rc = upload_dev(p, flame, "forcing update");
+  if (rc) return rc;
+  // the group's steps use the forced column kernel while any member has a forcing
+  Group& gr = p->groups[p->group_of[flame]];
+  bool any = false;
+  for (int f = gr.first; f < gr.first + gr.count; ++f) any = any || p->hdev[f].F != nullptr;
+  if (any != gr.forced) {
+    gr.forced = any;
+    drop_graph(p);
+  }
   return FLAME_OK;
 }
 

@@ -30,6 +30,7 @@ struct FlameDev {
   double* part;        // per-workgroup partial sums of the diagnostics
   const double* r0tab; // reference-radius table {r0(t_n), I1_n, I2_n} (r0_law = 1), or null for r0 = t
   long long r0n;       // its entries
+  const float2* F;     // forcing f~ of Eq. (1) in the state layout [M][H1], or null (f~ = 0)
   int n1, n2;
   int m;               // stored k2 columns, N2/4
   int h1;              // stored k1 slots, N1/2

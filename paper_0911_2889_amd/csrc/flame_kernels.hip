@@ -30,7 +30,7 @@
 
 namespace flame {
 
-template <int LOGN1, int MODE, int PTS = ff::kPts>
+template <int LOGN1, int MODE, int PTS = ff::kPts, bool FORCED = false>
 __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   if (nbase) n += *nbase;  // graph replays read the step index from device memory
@@ -63,18 +63,20 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int i = 0; i < PTS; ++i)
       v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state is loaded before the transform so its latency is hidden
-    float2 old[KEEP];
+    float2 old[KEEP], frc[KEEP];  // frc: the forcing (forced variant only)
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
       const int i = kept_reg<PTS>(kk);
       const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
       old[kk] = (MODE == COL_STEP && live) ? ld(Sc + k1) : make_float2(0.f, 0.f);
+      frc[kk] = (FORCED && live) ? forcing_at(f, m, k1) : make_float2(0.f, 0.f);
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
     if constexpr (MODE == COL_STEP) sc = step_scalars(f, n, f.n1);
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     const float kap2c = f.s2 * (float)m;
+    const float dtf = (float)f.dt;
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
       const int i = kept_reg<PTS>(kk);
@@ -85,7 +87,8 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
         const float kap1 = f.s1 * (float)k1;
         const float kk2 = kap1 * kap1 + kap2c * kap2c;
         const float e = growth_factor(kk2, sc, f.gamma);
-        val = make_float2(e * (old[kk].x + sc.a * v[i].x), e * (old[kk].y + sc.a * v[i].y));
+        val = make_float2(e * (old[kk].x + sc.a * v[i].x + dtf * frc[kk].x),
+                          e * (old[kk].y + sc.a * v[i].y + dtf * frc[kk].y));
       } else {
         val = ff::cscale(v[i], inv_p);
       }
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
 // {4, 5} except position 4*N6, which is k1 = -(K1 + 1)) go through LDS back
 // to the natural map t + G*i (the k2 = 0 column symmetrised on the way), the
 // state is stored from that map, and the two inverse transforms start there.
-template <int LOGN1, int MODE, int PTS = 16>
+template <int LOGN1, int MODE, int PTS = 16, bool FORCED = false>
 __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     colp_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
@@ -353,7 +356,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     for (int i = 0; i < PTS; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state in the radix-6 output map, loaded before the transform
     constexpr int KR[4] = {0, 1, 4, 5};
-    float2 old[IT][4];
+    float2 old[IT][4], frc[IT][4];  // frc: the forcing (forced variant only)
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int j = t + G * it;
@@ -362,12 +365,14 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
         const int pos = j + KR[q] * N6;
         const bool ok = live && j < N6 && kept_at(pos);
         old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+        frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
       }
     }
     float2 o[IT * 6];
     fft6<LOGP, false, PTS>(v, o, t, my, T, tw);
     const StepScalars sc = step_scalars(f, n, M1);
     const float kap2c = f.s2 * (float)m;
+    const float dtf = (float)f.dt;
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int j = t + G * it;
@@ -381,7 +386,8 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
             const float kap1 = f.s1 * (float)k1_of(pos);
             const float kk2 = kap1 * kap1 + kap2c * kap2c;
             const float e = growth_factor(kk2, sc, f.gamma);
-            val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x), e * (old[it][q].y + sc.a * o[it * 6 + r].y));
+            val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
+                              e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
           }
           my[ff::lds_pad(pos) * T] = val;
         }
@@ -456,7 +462,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
 // per thread over 2G threads, then the Wp and Wm inverse transforms side by
 // side, 16 points per thread, G threads each. Same results as colp_kernel up
 // to rounding. Every barrier is reached by every thread.
-template <int LOGN1, int MODE>
+template <int LOGN1, int MODE, bool FORCED = false>
 __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
     colq_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
@@ -490,20 +496,23 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = live ? ld(Qc + (t8 + G8 * i) * TQ) : make_float2(0.f, 0.f);
       constexpr int KR[4] = {0, 1, 4, 5};
-      float2 old[ITF][4];
+      float2 old[ITF][4], frc[ITF][4];  // frc: the forcing (forced variant only)
 #pragma unroll
       for (int it = 0; it < ITF; ++it) {
         const int j = t8 + G8 * it;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int pos = j + KR[q] * N6;
-          old[it][q] = live && j < N6 && kept_at(pos) ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+          const bool ok = live && j < N6 && kept_at(pos);
+          old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
+          frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
         }
       }
       float2 o[ITF * 6];
       fft6<LOGP, false, 8>(v, o, t8, buf0, T, twf);
       const StepScalars sc = step_scalars(f, n, M1);
       const float kap2c = f.s2 * (float)m;
+      const float dtf = (float)f.dt;
 #pragma unroll
       for (int it = 0; it < ITF; ++it) {
         const int j = t8 + G8 * it;
@@ -516,8 +525,8 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
               const int q = r < 2 ? r : r - 2;
               const float kap1 = f.s1 * (float)k1_of(pos);
               const float e = growth_factor(kap1 * kap1 + kap2c * kap2c, sc, f.gamma);
-              val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x),
-                                e * (old[it][q].y + sc.a * o[it * 6 + r].y));
+              val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
+                                e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
             }
             buf0[ff::lds_pad(pos) * T] = val;
           }
@@ -702,12 +711,16 @@ struct ColTable {
       default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, nb, src); break;
     }
   }
-  static KernelLaunch step_kernel(int pts) {
+  template <bool FORCED>
+  static KernelLaunch step_kernel_f(int pts) {
     if (pts == 8)
-      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8>), ColCfg<LOGN, 8>::THREADS,
-                          ColCfg<LOGN, 8>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP>), ColCfg<LOGN>::THREADS,
-                        ColCfg<LOGN>::LDS_BYTES};
+      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, FORCED>),
+                          ColCfg<LOGN, 8>::THREADS, ColCfg<LOGN, 8>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, ff::kPts, FORCED>),
+                        ColCfg<LOGN>::THREADS, ColCfg<LOGN>::LDS_BYTES};
+  }
+  static KernelLaunch step_kernel(int pts, bool forced) {
+    return forced ? step_kernel_f<true>(pts) : step_kernel_f<false>(pts);
   }
 };
 
@@ -741,32 +754,36 @@ struct RowTable {
 
 template <int LOGN>
 struct ColPTable {
-  template <int PTS>
+  template <int PTS, bool FORCED>
   static KernelLaunch info(int mode) {
     if (mode == COL_FIRST)
       return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST, PTS>),
                           ColCfgP<LOGN, PTS>::THREADS, ColCfgP<LOGN, PTS>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, PTS>), ColCfgP<LOGN, PTS>::THREADS,
-                        ColCfgP<LOGN, PTS>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, PTS, FORCED>),
+                        ColCfgP<LOGN, PTS>::THREADS, ColCfgP<LOGN, PTS>::LDS_BYTES};
   }
+  template <bool FORCED>
   static KernelLaunch split(int mode) {
     if (mode == COL_FIRST)
       return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_FIRST>), ColCfgQ<LOGN>::THREADS,
                           ColCfgQ<LOGN>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP>), ColCfgQ<LOGN>::THREADS,
+    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP, FORCED>), ColCfgQ<LOGN>::THREADS,
                         ColCfgQ<LOGN>::LDS_BYTES};
   }
   // pts 16: colp_kernel<., 16>; pts 8: the split kernel (8 points per thread in the forward transform)
-  static KernelLaunch step_kernel(int mode, int pts) { return pts == 8 ? split(mode) : info<16>(mode); }
+  static KernelLaunch step_kernel(int mode, int pts, bool forced) {
+    if (forced) return pts == 8 ? split<true>(mode) : info<16, true>(mode);
+    return pts == 8 ? split<false>(mode) : info<16, false>(mode);
+  }
 };
 
 template <int L>
-void dispatch_colp(int logn, int mode, int pts, KernelLaunch* out) {
+void dispatch_colp(int logn, int mode, int pts, bool forced, KernelLaunch* out) {
   if constexpr (L <= kMaxLog) {
     if (logn == L)
-      *out = ColPTable<L>::step_kernel(mode, pts);
+      *out = ColPTable<L>::step_kernel(mode, pts, forced);
     else
-      dispatch_colp<L + 1>(logn, mode, pts, out);
+      dispatch_colp<L + 1>(logn, mode, pts, forced, out);
   }
 }
 
@@ -780,13 +797,13 @@ void dispatch_log(int logn, A... args) {
   }
 }
 
-template <template <int> class Tab, int L>
-void dispatch_info(int logn, int pts, KernelLaunch* out) {
+template <template <int> class Tab, int L, class... A>
+void dispatch_info(int logn, KernelLaunch* out, A... args) {
   if constexpr (L <= kMaxLog) {
     if (logn == L)
-      *out = Tab<L>::step_kernel(pts);
+      *out = Tab<L>::step_kernel(args...);
     else
-      dispatch_info<Tab, L + 1>(logn, pts, out);
+      dispatch_info<Tab, L + 1>(logn, out, args...);
   }
 }
 
@@ -796,9 +813,9 @@ void dispatch_info(int logn, int pts, KernelLaunch* out) {
 // use hipExtLaunchKernel, which records the events in the kernel's own
 // dispatch (kernel start and end, no extra queue packets).
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  if (mode == COL_STEP && (pts != ff::kPts || ev_start || ev_stop)) {
-    const KernelLaunch kl = col_step_kernel(logn1, pts);
+                const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool forced) {
+  if (mode == COL_STEP && (forced || pts != ff::kPts || ev_start || ev_stop)) {
+    const KernelLaunch kl = col_step_kernel(logn1, pts, forced);
     const long long* nb = nullptr;
     const float2* s = static_cast<const float2*>(src);
     void* args[] = {&fl, &n, &nb, &s};
@@ -826,15 +843,15 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
 }
 
-KernelLaunch colp_kernel_info(int logn1, int mode, int pts) {
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts, bool forced) {
   KernelLaunch out{nullptr, 0, 0};
-  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, pts, &out);
+  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, pts, forced, &out);
   return out;
 }
 
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  const KernelLaunch kl = colp_kernel_info(logn1, mode, pts);
+                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool forced) {
+  const KernelLaunch kl = colp_kernel_info(logn1, mode, pts, forced);
   if (!kl.func) return;
   const long long* nb = nullptr;
   const float2* s = static_cast<const float2*>(src);
@@ -845,15 +862,15 @@ void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const 
     (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
 }
 
-KernelLaunch col_step_kernel(int logn1, int pts) {
+KernelLaunch col_step_kernel(int logn1, int pts, bool forced) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<ColTable, kMinLog>(logn1, pts, &out);
+  dispatch_info<ColTable, kMinLog>(logn1, &out, pts, forced);
   return out;
 }
 
 KernelLaunch row_step_kernel(int logn2, int pts) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<RowTable, kMinLog>(logn2, pts, &out);
+  dispatch_info<RowTable, kMinLog>(logn2, &out, pts);
   return out;
 }
 

@@ -16,25 +16,28 @@ struct KernelLaunch {
 };
 
 // The step kernels for a transform length (arguments: fls, n, nbase, src / in, out).
-KernelLaunch col_step_kernel(int logn1, int pts);
+// forced: the column kernel variant that adds each flame's bound forcing
+// spectrum (it steps flames without one unforced).
+KernelLaunch col_step_kernel(int logn1, int pts, bool forced = false);
 KernelLaunch row_step_kernel(int logn2, int pts);
 void launch_set_step(hipStream_t st, long long* counter, long long value);
 
 // Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
 // (fl points at their consecutive FlameDev entries in device memory). src,
 // if not null, replaces the state read by COL_FIRST and COL_SYNTH.
-// With ev_start/ev_stop (step mode only) the events mark the kernel's start and end.
+// With ev_start/ev_stop (step mode only) the events mark the kernel's start and end;
+// forced selects the step variant that adds the forcing.
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                 const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
-                hipEvent_t ev_stop = nullptr);
+                hipEvent_t ev_stop = nullptr, bool forced = false);
 
 // Column kernel of the step on the product grid (3 N1/4 rows; N1 >= 128),
 // mode COL_STEP or COL_FIRST; colp_kernel_info gives its function and shape
 // (func null for an unsupported size).
-KernelLaunch colp_kernel_info(int logn1, int mode, int pts);
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts, bool forced = false);
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                  const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
-                 hipEvent_t ev_stop = nullptr);
+                 hipEvent_t ev_stop = nullptr, bool forced = false);
 
 // Adjoint kernels (adjoint_kernels.hip); see the modes in flame_dev.hpp.
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,

@@ -161,6 +161,15 @@ __device__ __forceinline__ float growth_factor(float kk2, const StepScalars& sc,
   return __expf(-kk2 * sc.i2 + 0.5f * gamma * __builtin_amdgcn_sqrtf(kk2) * sc.i1);
 }
 
+// f~_k of Eq. (1) for stored column m and wavenumber k1, read from the bound
+// forcing spectrum (state layout), or zero when none is bound. The update
+// takes dt f~ inside the propagator, like the quadratic term:
+// E (Phi~ + dt (f~ - c N)). m must be a stored column.
+__device__ __forceinline__ float2 forcing_at(const FlameDev& f, int m, int k1) {
+  if (!f.F) return make_float2(0.f, 0.f);
+  return ld((const gf2*)f.F + (size_t)m * f.h1 + (f.n1 >> 2) + k1);
+}
+
 // Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm = f.Wp + 2:
 // [j1/2][m][Wp, Wm][j1%2], so that the spectra of a row pair are one
 // contiguous run (the row kernel reads both rows of Wp or Wm with one 16-byte

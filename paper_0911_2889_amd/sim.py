@@ -169,6 +169,34 @@ class FlameEnsemble:
             self._r0_tables = {}
         self._r0_tables[flame] = table
 
+    def set_forcing(self, half, flame=0):
+        """Forcing f~_k of Eq. (1) for a flame, taken by every later step: a
+        canonical half spectrum (complex64, shape (2K1+1, K2+1), the layout of
+        set_spectrum), or None for no forcing. The values are copied, on the
+        plan's stream, into a state-layout buffer that this object keeps and
+        the library reads; calling again between steps gives a forcing that
+        varies in time."""
+        self._check_flame(flame)
+        if not hasattr(self, "_forcing"):
+            self._forcing = {}
+        if half is None:
+            native.check(self.lib.flame_set_forcing(self.plan, int(flame), None))
+            self._forcing.pop(flame, None)
+            return
+        with torch.cuda.stream(self.stream):
+            h = _dev_tensor(half, torch.complex64, self.device)
+            if tuple(h.shape) != self.half_shape(flame):
+                raise ValueError(f"forcing has shape {tuple(h.shape)}, expected {self.half_shape(flame)}")
+            buf = self._forcing.get(flame)
+            if buf is None:
+                d = self.descs[flame]
+                # state layout [k2][k1 + n1/4]; the slot k1 = -n1/4 lies outside the box
+                buf = torch.zeros((d.n2 // 4, d.n1 // 2), dtype=torch.complex64, device=self.device)
+            buf[:, 1:].copy_(h.t())
+        if flame not in self._forcing:
+            native.check(self.lib.flame_set_forcing(self.plan, int(flame), ctypes.c_void_p(buf.data_ptr())))
+            self._forcing[flame] = buf
+
     def set_product_grid(self, n1, n2, enable):
         """Form the quadratic term on 3*n1/4 theta rows (True) or on n1 rows (False)
         for the flames of grid n1 x n2; the results agree to rounding."""

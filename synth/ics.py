@@ -160,3 +160,12 @@ def ensemble_members():
 def workload_spectrum(w, seed=None):
     k1, k2, a, psi = w.modes(seed)
     return modal_spectrum(w.n1, w.n2, k1, k2, a, psi)
+
+
+def forcing_spectrum(w, amp=1e-5, seed=None):
+    """Seeded forcing f~_k of Eq. (1) for workload w (the paper's runs use f~ = 0):
+    every mode of the retained box, a_k = amp * xi_k / |k| with random phases
+    (the "all" rule above), drawn with seed w.seed + 7919 unless given;
+    canonical half array, complex64."""
+    k1, k2, a, psi = mode_table(w.n1, w.n2, "all", amp, -1.0, w.seed + 7919 if seed is None else seed)
+    return modal_spectrum(w.n1, w.n2, k1, k2, a, psi)
