@@ -20,6 +20,11 @@ notes):
   (Lawson) Euler. The linear part is integrated exactly over the step,
   E_k = exp(int_{t_n}^{t_{n+1}} sigma_k dt); the quadratic term is taken
   explicitly at t_n:  Phi~^{n+1} = E_k (Phi~^n + dt * N_k(Phi~^n, t_n)).
+  A second-order option is the integrating-factor form of Heun's method
+  (Lawson's RK2): with v = Phi~ / E_k(t_n, t), the trapezoid rule on
+  dv/dt = E^-1 N(E v, t) gives the Euler predictor Phi* above and
+  Phi~^{n+1} = (Phi* + E_k Phi~^n + dt N_k(Phi*, t_{n+1})) / 2,
+  both stages symmetrised.
 * With r0 = t:  int r0^-2 dt = 1/t_n - 1/t_{n+1},  int r0^-1 dt = ln(t_{n+1}/t_n).
 * Truncation is the box |k_i| <= K_i (Section 2 and Section 3).
 * Symmetrisation copies the upper half H = {k2 > 0} or {k2 = 0, k1 > 0} onto
@@ -47,6 +52,9 @@ class Params:
     # forcing f~_k(t) of Eq. (1): None (the paper's runs), a full Hermitian
     # coefficient array, or a function t -> such an array
     forcing: object = field(default=None)
+    # time integrator: "euler" (integrating-factor Euler) or "rk2"
+    # (integrating-factor Heun, second order)
+    integrator: str = "euler"
 
     def forcing_at(self, t):
         if self.forcing is None:
@@ -156,19 +164,34 @@ def symmetrise(full):
     return out
 
 
-def step(full, p, n):
-    """One integrating-factor Euler step n -> n+1 of Eq. (1) (full array).
-
-    The forcing, like the quadratic term, is taken explicitly at t_n:
-    Phi~^{n+1} = E_k (Phi~^n + dt (N_k(Phi~^n, t_n) + f~_k(t_n))).
-    """
+def explicit_terms(full, p, n):
+    """N_k(Phi~, t_n) + f~_k(t_n): the quadratic term of Eq. (1) with c_n =
+    1/(2 r0(t_n)^2), plus the forcing if given (full array)."""
     c, _, _ = step_scalars(p, n)
-    e = np.exp(growth_exponent(p, n))
-    rhs_n = -c * convolution_sum(full, p)
+    out = -c * convolution_sum(full, p)
     f = p.forcing_at(p.time(n))
     if f is not None:
-        rhs_n = rhs_n + f
-    new = e * (full + p.dt * rhs_n) * box_mask(p.n1, p.n2)
+        out = out + f
+    return out
+
+
+def step(full, p, n):
+    """One step n -> n+1 of Eq. (1) (full array).
+
+    Integrating-factor Euler: the forcing, like the quadratic term, is taken
+    explicitly at t_n: Phi~^{n+1} = E_k (Phi~^n + dt (N_k(Phi~^n, t_n) + f~_k(t_n))).
+    Integrating-factor Heun ("rk2"): that Euler step is the predictor Phi*
+    (symmetrised), and Phi~^{n+1} = (Phi* + E_k Phi~^n + dt (N_k(Phi*, t_{n+1})
+    + f~_k(t_{n+1}))) / 2.
+    """
+    e = np.exp(growth_exponent(p, n))
+    mask = box_mask(p.n1, p.n2)
+    pred = symmetrise(e * (full + p.dt * explicit_terms(full, p, n)) * mask)
+    if p.integrator == "euler":
+        return pred
+    if p.integrator != "rk2":
+        raise ValueError(f"unknown integrator {p.integrator!r}")
+    new = 0.5 * (pred + e * full + p.dt * explicit_terms(pred, p, n + 1)) * mask
     return symmetrise(new)
 
 

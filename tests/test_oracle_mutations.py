@@ -44,6 +44,14 @@ def failing_pins():
     conv = pins.pin_convergence()
     if not (conv[-1] < 5e-3 and all(1.8 < a / b < 2.2 for a, b in zip(conv, conv[1:]))):
         bad.append("pin_convergence")
+    conv2 = pins.pin_convergence(integrator="rk2")
+    if not (conv2[-1] < 1e-4 and all(3.5 < a / b < 4.5 for a, b in zip(conv2, conv2[1:]))):
+        bad.append("pin_convergence_rk2")
+    try:
+        if not pins.pin_forcing_geometric_series(integrator="rk2") < 1e-12:
+            bad.append("pin_forcing_geometric_series_rk2")
+    except Exception:
+        bad.append("pin_forcing_geometric_series_rk2")
     return bad
 
 
@@ -190,11 +198,36 @@ def _forcing_outside_integrating_factor(monkeypatch):
     monkeypatch.setattr(om, "step", step)
 
 
+def _heun_corrector_at_old_time(monkeypatch):
+    # the corrector's quadratic term and forcing taken at t_n instead of t_{n+1}
+    def step(full, p, n):
+        e = np.exp(om.growth_exponent(p, n))
+        mask = oracle.box_mask(p.n1, p.n2)
+        pred = om.symmetrise(e * (full + p.dt * om.explicit_terms(full, p, n)) * mask)
+        if p.integrator == "euler":
+            return pred
+        return om.symmetrise(0.5 * (pred + e * full + p.dt * om.explicit_terms(pred, p, n)) * mask)
+    monkeypatch.setattr(om, "step", step)
+
+
+def _heun_propagator_on_corrector(monkeypatch):
+    # E applied to the corrector's explicit terms as well
+    def step(full, p, n):
+        e = np.exp(om.growth_exponent(p, n))
+        mask = oracle.box_mask(p.n1, p.n2)
+        pred = om.symmetrise(e * (full + p.dt * om.explicit_terms(full, p, n)) * mask)
+        if p.integrator == "euler":
+            return pred
+        return om.symmetrise(0.5 * (pred + e * (full + p.dt * om.explicit_terms(pred, p, n + 1))) * mask)
+    monkeypatch.setattr(om, "step", step)
+
+
 MUTATIONS = [
     _flip_nonlinear_sign, _drop_instability_term, _euler_radius_integral, _missing_half_in_c,
     _transposed_kappa, _cross_term_dropped, _aliased_grid, _nonlinear_at_new_time,
     _velocity_without_half, _area_without_sqrt, _adjoint_missing_factor_two,
-    _adjoint_without_decay, _forcing_outside_integrating_factor,
+    _adjoint_without_decay, _forcing_outside_integrating_factor, _heun_corrector_at_old_time,
+    _heun_propagator_on_corrector,
 ]
 
 

@@ -229,3 +229,50 @@ def test_forcing_enters_the_exact_solution_of_eq1():
     assert errs[-1] < 1e-3
     for a, b in zip(errs, errs[1:]):
         assert 1.6 < a / b < 2.4
+
+
+def test_heun_is_exact_for_the_linear_part():
+    assert pins.pin_linear_growth(dt=1.0, nsteps=50, integrator="rk2") < 1e-12
+    assert pins.pin_linear_growth(dt=10.0, nsteps=5, integrator="rk2") < 1e-12
+
+
+def test_heun_converges_at_second_order_to_eq1_solution():
+    errs = pins.pin_convergence(integrator="rk2")
+    euler = pins.pin_convergence()
+    assert errs[-1] < 1e-4 and errs[-1] < 0.05 * euler[-1]
+    for a, b in zip(errs, errs[1:]):
+        assert 3.5 < a / b < 4.5
+
+
+def test_heun_constant_forcing_sums_its_series():
+    assert pins.pin_forcing_geometric_series(integrator="rk2") < 1e-12
+    assert pins.pin_forcing_geometric_series(R=12.0, dt=0.2, steps=40, mode=(5, 1), integrator="rk2") < 1e-12
+
+
+def test_heun_with_time_dependent_forcing_converges_at_second_order():
+    """Heun with f~(t) = cos(0.3 t) F against DOP853 on the forced Eq. (1):
+    the forcing enters the corrector at t_{n+1}."""
+    from scipy.integrate import solve_ivp
+
+    n1 = n2 = 16
+    rng = np.random.default_rng(3)
+    half = (rng.standard_normal((7, 4)) + 1j * rng.standard_normal((7, 4))) * 1e-2
+    full0 = oracle.symmetrise(oracle.half_to_full(half, n1, n2))
+    force = oracle.symmetrise(oracle.half_to_full(
+        (rng.standard_normal((7, 4)) + 1j * rng.standard_normal((7, 4))) * 1e-3, n1, n2))
+    forcing = lambda t: force * np.cos(0.3 * t)  # noqa: E731
+    t0, T = 5.0, 2.0
+    mask = oracle.box_mask(n1, n2)
+
+    def f(t, y):
+        pp = oracle.Params(n1, n2, t0=t0, dt=1.0, forcing=forcing)
+        return (oracle.rhs(y.reshape(n1, n2), pp, t) * mask).ravel()
+
+    ref = solve_ivp(f, (t0, t0 + T), (full0 * mask).ravel().astype(np.complex128), method="DOP853",
+                    rtol=1e-12, atol=1e-17).y[:, -1].reshape(n1, n2)
+    errs = []
+    for nsteps in (10, 20, 40):
+        p = oracle.Params(n1, n2, t0=t0, dt=T / nsteps, forcing=forcing, integrator="rk2")
+        errs.append(np.linalg.norm(oracle.run(full0, p, nsteps) - ref) / np.linalg.norm(ref))
+    for a, b in zip(errs, errs[1:]):
+        assert 3.4 < a / b < 4.6, errs
