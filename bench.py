@@ -196,6 +196,65 @@ def forced_leg(sim, w, half, steps, graph_steps, run_steps, unforced_ms, rows):
     }
 
 
+def heun_leg(w, half, steps, graph_steps, diag_every, euler_ms):
+    """The same workload stepped with integrating-factor Heun (two row and two
+    column kernels per step) on its own plan, autotuned, graph replays between
+    diagnostics: HIP-event time of `steps` steps, then per-kernel times of
+    direct launches."""
+    import torch
+
+    from paper_0911_2889_amd import FlameSim
+
+    sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt, integrator=1)
+    sim.set_spectrum(half)
+    sim.autotune(steps=10)
+    pts = sim.points_per_thread(w.n1, w.n2)
+    rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
+    diag = torch.zeros(4, dtype=torch.float64, device=sim.device)
+
+    def run(k, timed):
+        if timed:
+            sim.timing_begin()
+        done = 0
+        while done < k:
+            chunk = min(diag_every - (done % diag_every), k - done)
+            sim.step(chunk)
+            done += chunk
+            if done % diag_every == 0:
+                sim.diagnostics(out=diag)
+        return sim.timing_end() if timed else None
+
+    sim.set_graph_steps(graph_steps)
+    sim.set_spectrum(half)
+    run(max(graph_steps, 10), False)  # warm-up (builds the graph)
+    sim.set_spectrum(half)
+    sim.step(0)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    run(steps, False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    sim.set_graph_steps(0)
+    sim.set_spectrum(half)
+    sim.step(0)
+    kt = run(steps, True)
+    torch.cuda.synchronize()
+    nb = algorithmic_bytes(w.n1, w.n2, rows)
+    k1, k2 = (w.n1 - 1) // 4, (w.n2 - 1) // 4
+    step_bytes = 2 * nb["row"] + 2 * nb["col"] + 8 * (2 * k1 + 1) * (k2 + 1)  # the corrector also reads Phi*
+    return {
+        "integrator": "integrating-factor Heun (2 row + 2 column kernels per step)",
+        "steps": steps, "graph_steps": graph_steps, "points_per_thread": {"col": pts[0], "row": pts[1]},
+        "product_rows": rows, "ms_per_step": ms, "point_steps_per_s": w.points / (ms * 1e-3),
+        "over_euler": ms / euler_ms, "step_bytes": step_bytes,
+        "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels_ms_per_launch": {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")},
+    }
+
+
 def ensemble_leg(steps, graph_steps):
     """The batched ensemble (256 flames of three grids) stepped in graphs of
     graph_steps steps, and with direct launches, timed with HIP events."""
@@ -258,6 +317,8 @@ def main():
                     help="steps of the 256-flame ensemble leg (0 skips it)")
     ap.add_argument("--forcing-steps", type=int, default=200,
                     help="steps of the forced-step leg (a seeded forcing bound to the same flame); 0 skips it")
+    ap.add_argument("--heun-steps", type=int, default=200,
+                    help="steps of the integrating-factor Heun leg on the same workload; 0 skips it")
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the checkpointed adjoint leg on 1024x2048 (0 skips it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -398,6 +459,9 @@ def main():
     if args.forcing_steps > 0:
         result["forced"] = forced_leg(sim, w, half, args.forcing_steps, graph_steps, run_steps,
                                       ms / args.steps, rows)
+
+    if args.heun_steps > 0:
+        result["heun"] = heun_leg(w, half, args.heun_steps, graph_steps, args.diag_every, ms / args.steps)
 
     if args.adjoint_steps > 0:
         result["adjoint"] = adjoint_leg(args.adjoint_steps, 50)

@@ -69,7 +69,9 @@ typedef struct {
   double dt;              /* time step, > 0 */
   double axis_scale[2];   /* wavenumber scale per axis; {0, 0} means {theta_pi, theta_pi} */
   int32_t r0_law;         /* reference radius: 0 r0(t) = t (Section 2); 1 a table (flame_set_r0_table) */
-  int32_t reserved;       /* 0 */
+  int32_t integrator;     /* time integrator (see flame_step): 0 integrating-factor Euler;
+                             1 integrating-factor Heun. Flames of one grid are launched
+                             together only when their integrators agree. */
 } flame_desc;
 
 /* Bytes of one flame's state buffer (complex64 S, see the layout above). */
@@ -113,10 +115,17 @@ int flame_state_modified(flame_plan plan, int64_t n);
 /* Step index of the plan (time of flame f is t0_f + index * dt_f). */
 int flame_step_index(flame_plan plan, int64_t* n);
 
-/* Advance every bound flame by nsteps integrating-factor Euler steps of
- * Eq. (1): Phi~ <- E_k (Phi~ + dt N_k), E_k = exp(int sigma_k dt) over the
- * step, N_k = (1/(2 r0(t_n)^2)) DFT_k[|grad Phi|^2] / P on the box, followed by
- * the symmetrisation of Section 3. nsteps >= 0. */
+/* Advance every bound flame by nsteps steps of Eq. (1) (the paper leaves the
+ * integrator to its references). With integrator 0, integrating-factor Euler:
+ *   Phi~ <- E_k (Phi~ + dt (f~_k + N_k(Phi~, t_n))),
+ * E_k = exp(int sigma_k dt) over the step, N_k = (1/(2 r0(t_n)^2))
+ * DFT_k[|grad Phi|^2] / P on the box, f~ the bound forcing (zero by default),
+ * followed by the symmetrisation of Section 3. With integrator 1,
+ * integrating-factor Heun (second order): that Euler step is the predictor
+ * Phi* (symmetrised, kept in the workspace), and
+ *   Phi~ <- (Phi* + E_k Phi~ + dt (f~_k + N_k(Phi*, t_{n+1}))) / 2,
+ * symmetrised; it runs the row and column kernels twice per step, and with
+ * r0_law = 1 it also reads table entry n + 1. nsteps >= 0. */
 int flame_step(flame_plan plan, int32_t nsteps);
 
 /* Integral diagnostics of flame `flame` at the current step (the averages of
@@ -139,7 +148,9 @@ int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
  * m the grid field of mu, c_n = 1/(2 r0(t_n)^2). lam_out may equal lam_in;
  * state_n must not alias lam_out. Runs on the grid flame_step uses for this
  * flame (see flame_set_product_grid: the transpose of that step). Uses the
- * plan's workspace, so the next flame_step rebuilds its intermediates. */
+ * plan's workspace, so the next flame_step rebuilds its intermediates. It is
+ * the transpose of integrating-factor Euler: a flame with integrator 1 gets
+ * FLAME_ERR_INVALID_ARG. */
 int flame_adjoint_step(flame_plan plan, int32_t flame, int64_t n, const void* state_n, const void* lam_in,
                        void* lam_out);
 
@@ -236,8 +247,9 @@ int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* ena
 int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
 
 /* Run flame_step in graphs of `steps` steps (0: direct launches, the default).
- * The graph holds, for every group of flames with equal grids, the chain
- * row kernel -> column kernel for each step; chains of different groups have
+ * The graph holds, for every group of flames with equal grids (and equal
+ * integrators), the chain row kernel -> column kernel for each step (twice
+ * per step for integrating-factor Heun); chains of different groups have
  * no edges between them, so a mixed ensemble runs its groups concurrently.
  * flame_step(n) launches floor(n / steps) graphs and the remainder directly.
  * The graph is built on first use and replayed; the step index is read from

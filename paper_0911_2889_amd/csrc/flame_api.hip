@@ -70,7 +70,8 @@ int check_desc(const flame_desc* d, Sizes* s) {
   if ((d->axis_scale[0] == 0.0) != (d->axis_scale[1] == 0.0))
     return fail(FLAME_ERR_INVALID_ARG, "axis_scale must be both zero (use theta_pi) or both positive");
   if (d->r0_law != 0 && d->r0_law != 1) return fail(FLAME_ERR_INVALID_ARG, "r0_law must be 0 (r0 = t) or 1 (table)");
-  if (d->reserved != 0) return fail(FLAME_ERR_INVALID_ARG, "reserved must be 0");
+  if (d->integrator != 0 && d->integrator != 1)
+    return fail(FLAME_ERR_INVALID_ARG, "integrator must be 0 (IF-Euler) or 1 (IF-Heun)");
   if (s) {
     s->logn1 = l1;
     s->logn2 = l2;
@@ -157,6 +158,13 @@ struct Group {
   int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
   bool product = false;                        // step on the 3N1/4-row product grid
   bool forced = false;                         // some flame of the group has a forcing bound
+  int integrator = 0;                          // 0: IF-Euler (one pass per step); 1: IF-Heun (two passes)
+  int passes() const { return integrator == 1 ? 2 : 1; }
+  // the column kernel's variant in pass 0 or 1 of a step
+  int col_var(int pass) const {
+    if (integrator == 1) return pass == 0 ? flame::VAR_HEUN_P : flame::VAR_HEUN_C;
+    return forced ? flame::VAR_EULER_F : flame::VAR_EULER;
+  }
   int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
   int rgroups() const { return (rows() / 2 + rpairs - 1) / rpairs; }
 };
@@ -228,13 +236,17 @@ int check_plan(flame_plan p, int flame = 0) {
 
 // Every step index in [n_first, n_last] of flames [f0, f1) with a tabulated
 // reference radius must have a table entry (the kernels index it by n).
-int check_r0(flame_plan p, int f0, int f1, long long n_first, long long n_last) {
+// Steps n_first .. n_last (or diagnostics / adjoint at those indices) need
+// table entries up to n_last; a Heun step n also reads entry n + 1 when
+// `stepping` is set.
+int check_r0(flame_plan p, int f0, int f1, long long n_first, long long n_last, bool stepping = false) {
   for (int f = f0; f < f1; ++f) {
     if (p->descs[f].r0_law != 1) continue;
     if (!p->hdev[f].r0tab) return fail(FLAME_ERR_INVALID_ARG, "flame %d: r0_law = 1 but no r0 table set", f);
-    if (n_first < 0 || n_last >= p->hdev[f].r0n)
+    const long long last = n_last + (stepping && p->descs[f].integrator == 1 ? 1 : 0);
+    if (n_first < 0 || last >= p->hdev[f].r0n)
       return fail(FLAME_ERR_INVALID_ARG, "flame %d: step index %lld is beyond its r0 table of %lld entries", f,
-                  n_first < 0 ? n_first : n_last, p->hdev[f].r0n);
+                  n_first < 0 ? n_first : last, p->hdev[f].r0n);
   }
   return FLAME_OK;
 }
@@ -343,13 +355,14 @@ void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 =
                     nullptr, gr.row_pts, e0, e1);
 }
 
-void launch_step_col(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+void launch_step_col(flame_plan p, const Group& gr, long long n, int pass, hipEvent_t e0 = nullptr,
+                     hipEvent_t e1 = nullptr) {
   if (gr.product)
     flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                       gr.col_pts, e0, e1, gr.forced);
+                       gr.col_pts, e0, e1, gr.col_var(pass));
   else
     flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                      gr.col_pts, e0, e1, gr.forced);
+                      gr.col_pts, e0, e1, gr.col_var(pass));
 }
 
 void drop_graph(flame_plan p) {
@@ -368,43 +381,49 @@ int build_graph(flame_plan p) {
   hipError_t e = hipGraphCreate(&p->graph, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
   std::vector<hipGraphNode_t> last(p->groups.size(), nullptr);
-  for (int s = 0; s < p->graph_steps; ++s) {
-    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-      const Group& gr = p->groups[gi];
-      const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
-      const flame::KernelLaunch ck = gr.product
-                                         ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts, gr.forced)
-                                         : flame::col_step_kernel(gr.logn1, gr.col_pts, gr.forced);
-      if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
-      const flame::FlameDev* fl = p->ddev + gr.first;
-      long long n = s;
-      const long long* nb = p->counter;
-      const float* in = nullptr;
-      float* outp = nullptr;
-      const float2* src = nullptr;
-      void* rargs[] = {&fl, &n, &nb, &in, &outp};
-      void* cargs[] = {&fl, &n, &nb, &src};
-      hipKernelNodeParams rp{};
-      rp.func = const_cast<void*>(rk.func);
-      rp.gridDim = dim3(gr.rgroups(), gr.count);
-      rp.blockDim = dim3(rk.threads);
-      rp.sharedMemBytes = rk.lds;
-      rp.kernelParams = rargs;
-      hipGraphNode_t rn;
-      e = hipGraphAddKernelNode(&rn, p->graph, last[gi] ? &last[gi] : nullptr, last[gi] ? 1 : 0, &rp);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (row)");
-      hipKernelNodeParams cp{};
-      cp.func = const_cast<void*>(ck.func);
-      cp.gridDim = dim3(gr.tiles, gr.count);
-      cp.blockDim = dim3(ck.threads);
-      cp.sharedMemBytes = ck.lds;
-      cp.kernelParams = cargs;
-      hipGraphNode_t cn;
-      e = hipGraphAddKernelNode(&cn, p->graph, &rn, 1, &cp);
-      if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (col)");
-      last[gi] = cn;
-    }
-  }
+  // one pass of group gi at step offset s: row node, then column node, chained after the group's last node
+  auto add_pass = [&](size_t gi, int s, int pass) -> int {
+    const Group& gr = p->groups[gi];
+    const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
+    const flame::KernelLaunch ck =
+        gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts, gr.col_var(pass))
+                   : flame::col_step_kernel(gr.logn1, gr.col_pts, gr.col_var(pass));
+    if (!rk.func || !ck.func) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no step kernel for this grid");
+    const flame::FlameDev* fl = p->ddev + gr.first;
+    long long n = s;
+    const long long* nb = p->counter;
+    const float* in = nullptr;
+    float* outp = nullptr;
+    const float2* src = nullptr;
+    void* rargs[] = {&fl, &n, &nb, &in, &outp};
+    void* cargs[] = {&fl, &n, &nb, &src};
+    hipKernelNodeParams rp{};
+    rp.func = const_cast<void*>(rk.func);
+    rp.gridDim = dim3(gr.rgroups(), gr.count);
+    rp.blockDim = dim3(rk.threads);
+    rp.sharedMemBytes = rk.lds;
+    rp.kernelParams = rargs;
+    hipGraphNode_t rn;
+    e = hipGraphAddKernelNode(&rn, p->graph, last[gi] ? &last[gi] : nullptr, last[gi] ? 1 : 0, &rp);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (row)");
+    hipKernelNodeParams cp{};
+    cp.func = const_cast<void*>(ck.func);
+    cp.gridDim = dim3(gr.tiles, gr.count);
+    cp.blockDim = dim3(ck.threads);
+    cp.sharedMemBytes = ck.lds;
+    cp.kernelParams = cargs;
+    hipGraphNode_t cn;
+    e = hipGraphAddKernelNode(&cn, p->graph, &rn, 1, &cp);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (col)");
+    last[gi] = cn;
+    return FLAME_OK;
+  };
+  for (int s = 0; s < p->graph_steps; ++s)
+    for (size_t gi = 0; gi < p->groups.size(); ++gi)
+      for (int pass = 0; pass < p->groups[gi].passes(); ++pass) {
+        const int rc = add_pass(gi, s, pass);
+        if (rc) return rc;
+      }
   e = hipGraphInstantiate(&p->graph_exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   return FLAME_OK;
@@ -524,6 +543,7 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     fd.Q = reinterpret_cast<float2*>(base + L.off_q[f]);
     fd.A1 = reinterpret_cast<float2*>(base + L.off_a1[f]);
     fd.A2 = reinterpret_cast<float2*>(base + L.off_a2[f]);
+    fd.S2 = fd.A2;  // Heun's predictor: A2 is free between the calls that use it
     fd.part = reinterpret_cast<double*>(base + L.off_part[f]);
     fd.tw1 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn1]);
     fd.tw2 = reinterpret_cast<const float2*>(base + L.off_tw[s.logn2]);
@@ -549,11 +569,13 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
   p->group_of.resize(n_flames);
   for (int f = 0; f < n_flames; ++f) {
     const Sizes& s = L.sizes[f];
-    if (!p->groups.empty() && p->groups.back().logn1 == s.logn1 && p->groups.back().logn2 == s.logn2) {
+    if (!p->groups.empty() && p->groups.back().logn1 == s.logn1 && p->groups.back().logn2 == s.logn2 &&
+        p->groups.back().integrator == descs[f].integrator) {
       p->groups.back().count++;
     } else {
       Group gr{s.logn1, s.logn2, f, 1, s.tiles, s.rpairs};
       gr.product = s.logn1 >= flame::kMinLogProduct;
+      gr.integrator = descs[f].integrator;
       p->groups.push_back(gr);
     }
     p->group_of[f] = (int)p->groups.size() - 1;
@@ -657,7 +679,7 @@ int flame_step(flame_plan p, int32_t nsteps) {
   if (rc) return rc;
   if (nsteps < 0) return fail(FLAME_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (nsteps > 0) {
-    rc = check_r0(p, 0, p->nfl, p->n, p->n + nsteps - 1);
+    rc = check_r0(p, 0, p->nfl, p->n, p->n + nsteps - 1, true);
     if (rc) return rc;
   }
   DeviceGuard g(p->device);
@@ -684,14 +706,20 @@ int flame_step(flame_plan p, int32_t nsteps) {
     }
   }
   break_chain(p);
+  int max_passes = 1;
+  for (const Group& gr : p->groups) max_passes = std::max(max_passes, gr.passes());
   for (int s = 0; s < nsteps; ++s) {
-    for (const Group& gr : p->groups) {
-      KernelEvents ev(p, KIND_ROW);
-      launch_step_row(p, gr, p->n, ev.start, ev.stop);
-    }
-    for (const Group& gr : p->groups) {
-      KernelEvents ev(p, KIND_COL);
-      launch_step_col(p, gr, p->n, ev.start, ev.stop);
+    for (int pass = 0; pass < max_passes; ++pass) {
+      for (const Group& gr : p->groups) {
+        if (pass >= gr.passes()) continue;
+        KernelEvents ev(p, KIND_ROW);
+        launch_step_row(p, gr, p->n, ev.start, ev.stop);
+      }
+      for (const Group& gr : p->groups) {
+        if (pass >= gr.passes()) continue;
+        KernelEvents ev(p, KIND_COL);
+        launch_step_col(p, gr, p->n, pass, ev.start, ev.stop);
+      }
     }
     p->n += 1;
   }
@@ -732,6 +760,8 @@ int flame_adjoint_step(flame_plan p, int32_t flame, int64_t n, const void* state
   if (rc) return rc;
   if (!state_n || !lam_in || !lam_out) return fail(FLAME_ERR_INVALID_ARG, "null state or cotangent pointer");
   if (state_n == lam_out) return fail(FLAME_ERR_INVALID_ARG, "state_n must not alias lam_out");
+  if (p->descs[flame].integrator != 0)
+    return fail(FLAME_ERR_INVALID_ARG, "flame %d: the adjoint step is the transpose of IF-Euler (integrator 0)", flame);
   rc = check_r0(p, flame, flame + 1, n, n);
   if (rc) return rc;
   DeviceGuard g(p->device);
@@ -915,7 +945,7 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
   if (steps <= 0) return fail(FLAME_ERR_INVALID_ARG, "steps must be > 0");
-  rc = check_r0(p, 0, p->nfl, p->n, p->n);  // every timed step runs at the current index
+  rc = check_r0(p, 0, p->nfl, p->n, p->n, true);  // every timed step runs at the current index
   if (rc) return rc;
   DeviceGuard g(p->device);
   // save every state in its flame's adjoint scratch (each at least 2x the state)
@@ -973,8 +1003,10 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
       // one untimed step, then `steps` timed steps of this group alone
       for (int s = 0; s <= steps; ++s) {
         if (s == 1) (void)hipEventRecord(ev0, p->stream);
-        launch_step_row(p, gr, n0);
-        launch_step_col(p, gr, n0);
+        for (int pass = 0; pass < gr.passes(); ++pass) {
+          launch_step_row(p, gr, n0);
+          launch_step_col(p, gr, n0, pass);
+        }
       }
       (void)hipEventRecord(ev1, p->stream);
       e = hipEventSynchronize(ev1);

@@ -31,6 +31,7 @@ struct FlameDev {
   const double* r0tab; // reference-radius table {r0(t_n), I1_n, I2_n} (r0_law = 1), or null for r0 = t
   long long r0n;       // its entries
   const float2* F;     // forcing f~ of Eq. (1) in the state layout [M][H1], or null (f~ = 0)
+  float2* S2;          // Heun's predictor Phi* in the state layout (workspace; the A2 scratch)
   int n1, n2;
   int m;               // stored k2 columns, N2/4
   int h1;              // stored k1 slots, N1/2
@@ -125,6 +126,12 @@ constexpr int q_tile(int logn1) { return q_tile_for((1 << logn1) / ff::kPts); }
 constexpr int row_pairs(int logn2) { return (1 << logn2) / ff::kPts >= 256 ? 1 : 256 / ((1 << logn2) / ff::kPts); }
 
 enum ColMode : int { COL_STEP = 0, COL_FIRST = 1, COL_PROJECT = 2, COL_SYNTH = 3 };
+// Variants of the step's column kernel (COL_STEP): integrating-factor Euler
+// without the forcing term (compiled out) or with it, and the two stages of
+// integrating-factor Heun, which read the forcing when one is bound:
+//   VAR_HEUN_P: predictor Phi* = E (Phi~^n + dt (f~ - c_n N(Phi~^n))) -> S2;
+//   VAR_HEUN_C: corrector Phi~^{n+1} = (Phi* + E Phi~^n + dt (f~ - c_{n+1} N(Phi*))) / 2 -> S.
+enum StepVar : int { VAR_EULER = 0, VAR_EULER_F = 1, VAR_HEUN_P = 2, VAR_HEUN_C = 3 };
 enum RowMode : int { ROW_STEP = 0, ROW_FORWARD = 1, ROW_SYNTH = 2, ROW_DIAG = 3 };
 // Adjoint column kernel: ADJ_A forms mu = E lambda and the column transforms
 // of mu and of the state's packed gradient; ADJ_C / SEED_C form the

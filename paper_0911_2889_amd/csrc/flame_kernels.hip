@@ -30,7 +30,7 @@
 
 namespace flame {
 
-template <int LOGN1, int MODE, int PTS = ff::kPts, bool FORCED = false>
+template <int LOGN1, int MODE, int PTS = ff::kPts, int VAR = VAR_EULER>
 __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   if (nbase) n += *nbase;  // graph replays read the step index from device memory
@@ -53,6 +53,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   // spectrum in the same layout (src), the other modes update the state
   gf2* const Sc = glob((MODE == COL_FIRST || MODE == COL_SYNTH) && src ? const_cast<float2*>(src) : f.S) +
                   (size_t)m * f.h1 + N1 / 4;
+  gf2* const Pc = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)m * f.h1 + N1 / 4;  // Heun's predictor
   const auto tw1 = KernelTw<LOGN1, PTS>::make(PTS == 8 ? f.tw1_8 : f.tw1, t);
 
   float2 v[PTS];
@@ -63,17 +64,22 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int i = 0; i < PTS; ++i)
       v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state is loaded before the transform so its latency is hidden
-    float2 old[KEEP], frc[KEEP];  // frc: the forcing (forced variant only)
+    // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
+    constexpr bool FORCED = MODE == COL_STEP && VAR != VAR_EULER;
+    float2 old[KEEP], frc[KEEP], prd[KEEP];
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
       const int i = kept_reg<PTS>(kk);
       const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
       old[kk] = (MODE == COL_STEP && live) ? ld(Sc + k1) : make_float2(0.f, 0.f);
       frc[kk] = (FORCED && live) ? forcing_at(f, m, k1) : make_float2(0.f, 0.f);
+      prd[kk] = (MODE == COL_STEP && VAR == VAR_HEUN_C && live) ? ld(Pc + k1) : make_float2(0.f, 0.f);
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
+    float ac = 0.f;  // the corrector's dt c_{n+1} / P
     if constexpr (MODE == COL_STEP) sc = step_scalars(f, n, f.n1);
+    if constexpr (MODE == COL_STEP && VAR == VAR_HEUN_C) ac = step_scalars(f, n + 1, f.n1).a;
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     const float kap2c = f.s2 * (float)m;
     const float dtf = (float)f.dt;
@@ -87,8 +93,12 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
         const float kap1 = f.s1 * (float)k1;
         const float kk2 = kap1 * kap1 + kap2c * kap2c;
         const float e = growth_factor(kk2, sc, f.gamma);
-        val = make_float2(e * (old[kk].x + sc.a * v[i].x + dtf * frc[kk].x),
-                          e * (old[kk].y + sc.a * v[i].y + dtf * frc[kk].y));
+        if constexpr (VAR == VAR_HEUN_C)
+          val = make_float2(0.5f * (prd[kk].x + e * old[kk].x + ac * v[i].x + dtf * frc[kk].x),
+                            0.5f * (prd[kk].y + e * old[kk].y + ac * v[i].y + dtf * frc[kk].y));
+        else
+          val = make_float2(e * (old[kk].x + sc.a * v[i].x + dtf * frc[kk].x),
+                            e * (old[kk].y + sc.a * v[i].y + dtf * frc[kk].y));
       } else {
         val = ff::cscale(v[i], inv_p);
       }
@@ -116,11 +126,12 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
       __syncthreads();
     }
     if (live) {
+      gf2* const Dc = VAR == VAR_HEUN_P ? Pc : Sc;  // the predictor goes to S2
 #pragma unroll
       for (int kk = 0; kk < KEEP; ++kk) {
         const int i = kept_reg<PTS>(kk);
         const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
-        st(Sc + k1, sv[kk]);
+        st(Dc + k1, sv[kk]);
       }
     }
   } else {
@@ -322,7 +333,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
 // {4, 5} except position 4*N6, which is k1 = -(K1 + 1)) go through LDS back
 // to the natural map t + G*i (the k2 = 0 column symmetrised on the way), the
 // state is stored from that map, and the two inverse transforms start there.
-template <int LOGN1, int MODE, int PTS = 16, bool FORCED = false>
+template <int LOGN1, int MODE, int PTS = 16, int VAR = VAR_EULER>
 __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     colp_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
@@ -344,6 +355,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
   float2* my = lds + c;
   gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
   gf2* const Sc = glob(MODE == COL_FIRST && src ? const_cast<float2*>(src) : f.S) + (size_t)m * f.h1 + N1 / 4;
+  gf2* const Pc = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)m * f.h1 + N1 / 4;  // Heun's predictor
   const auto tw = KernelTw6<LOGP, PTS>::make(PTS == 8 ? f.tw6_8 : f.tw6, t);
   // k1 of natural position p, and whether it is kept (|k1| <= K1)
   auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
@@ -356,7 +368,9 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     for (int i = 0; i < PTS; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
     // the old state in the radix-6 output map, loaded before the transform
     constexpr int KR[4] = {0, 1, 4, 5};
-    float2 old[IT][4], frc[IT][4];  // frc: the forcing (forced variant only)
+    // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
+    constexpr bool FORCED = VAR != VAR_EULER;
+    float2 old[IT][4], frc[IT][4], prd[IT][4];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int j = t + G * it;
@@ -366,11 +380,13 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
         const bool ok = live && j < N6 && kept_at(pos);
         old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
         frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
+        prd[it][q] = VAR == VAR_HEUN_C && ok ? ld(Pc + k1_of(pos)) : make_float2(0.f, 0.f);
       }
     }
     float2 o[IT * 6];
     fft6<LOGP, false, PTS>(v, o, t, my, T, tw);
     const StepScalars sc = step_scalars(f, n, M1);
+    const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1).a : 0.f;  // the corrector's dt c_{n+1} / P
     const float kap2c = f.s2 * (float)m;
     const float dtf = (float)f.dt;
 #pragma unroll
@@ -386,8 +402,13 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
             const float kap1 = f.s1 * (float)k1_of(pos);
             const float kk2 = kap1 * kap1 + kap2c * kap2c;
             const float e = growth_factor(kk2, sc, f.gamma);
-            val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
-                              e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
+            if constexpr (VAR == VAR_HEUN_C)
+              val = make_float2(
+                  0.5f * (prd[it][q].x + e * old[it][q].x + ac * o[it * 6 + r].x + dtf * frc[it][q].x),
+                  0.5f * (prd[it][q].y + e * old[it][q].y + ac * o[it * 6 + r].y + dtf * frc[it][q].y));
+            else
+              val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
+                                e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
           }
           my[ff::lds_pad(pos) * T] = val;
         }
@@ -410,10 +431,11 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     for (int i = 0; i < PTS; ++i) sv[i] = my[ff::lds_pad(t + G * i) * T];
     __syncthreads();  // the LDS is reused by the inverse transforms
     if (live) {
+      gf2* const Dc = VAR == VAR_HEUN_P ? Pc : Sc;  // the predictor goes to S2
 #pragma unroll
       for (int i = 0; i < PTS; ++i) {
         const int pos = t + G * i;
-        if (kept_at(pos)) st(Sc + k1_of(pos), sv[i]);
+        if (kept_at(pos)) st(Dc + k1_of(pos), sv[i]);
       }
     }
   } else {
@@ -462,7 +484,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
 // per thread over 2G threads, then the Wp and Wm inverse transforms side by
 // side, 16 points per thread, G threads each. Same results as colp_kernel up
 // to rounding. Every barrier is reached by every thread.
-template <int LOGN1, int MODE, bool FORCED = false>
+template <int LOGN1, int MODE, int VAR = VAR_EULER>
 __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
     colq_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
@@ -485,6 +507,7 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
   float2* const bufg = lds + grp * (Cfg::SLOTS * T) + c;  // this group's inverse exchange
   gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));
   gf2* const Sc = glob(MODE == COL_FIRST && src ? const_cast<float2*>(src) : f.S) + (size_t)m * f.h1 + N1 / 4;
+  gf2* const Pc = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)m * f.h1 + N1 / 4;  // Heun's predictor
   auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
   auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
 
@@ -496,7 +519,9 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = live ? ld(Qc + (t8 + G8 * i) * TQ) : make_float2(0.f, 0.f);
       constexpr int KR[4] = {0, 1, 4, 5};
-      float2 old[ITF][4], frc[ITF][4];  // frc: the forcing (forced variant only)
+      // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
+      constexpr bool FORCED = VAR != VAR_EULER;
+      float2 old[ITF][4], frc[ITF][4], prd[ITF][4];
 #pragma unroll
       for (int it = 0; it < ITF; ++it) {
         const int j = t8 + G8 * it;
@@ -506,11 +531,13 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
           const bool ok = live && j < N6 && kept_at(pos);
           old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
           frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
+          prd[it][q] = VAR == VAR_HEUN_C && ok ? ld(Pc + k1_of(pos)) : make_float2(0.f, 0.f);
         }
       }
       float2 o[ITF * 6];
       fft6<LOGP, false, 8>(v, o, t8, buf0, T, twf);
       const StepScalars sc = step_scalars(f, n, M1);
+      const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1).a : 0.f;  // the corrector's dt c_{n+1} / P
       const float kap2c = f.s2 * (float)m;
       const float dtf = (float)f.dt;
 #pragma unroll
@@ -525,8 +552,13 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
               const int q = r < 2 ? r : r - 2;
               const float kap1 = f.s1 * (float)k1_of(pos);
               const float e = growth_factor(kap1 * kap1 + kap2c * kap2c, sc, f.gamma);
-              val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
-                                e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
+              if constexpr (VAR == VAR_HEUN_C)
+                val = make_float2(
+                    0.5f * (prd[it][q].x + e * old[it][q].x + ac * o[it * 6 + r].x + dtf * frc[it][q].x),
+                    0.5f * (prd[it][q].y + e * old[it][q].y + ac * o[it * 6 + r].y + dtf * frc[it][q].y));
+              else
+                val = make_float2(e * (old[it][q].x + sc.a * o[it * 6 + r].x + dtf * frc[it][q].x),
+                                  e * (old[it][q].y + sc.a * o[it * 6 + r].y + dtf * frc[it][q].y));
             }
             buf0[ff::lds_pad(pos) * T] = val;
           }
@@ -550,10 +582,11 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
     for (int i = 0; i < 16; ++i) sv[i] = buf0[ff::lds_pad(t16 + G16 * i) * T];
     __syncthreads();  // both groups have read the spectrum before buffer 0 is reused
     if (live && grp == 0) {
+      gf2* const Dc = VAR == VAR_HEUN_P ? Pc : Sc;  // the predictor goes to S2
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int pos = t16 + G16 * i;
-        if (kept_at(pos)) st(Sc + k1_of(pos), sv[i]);
+        if (kept_at(pos)) st(Dc + k1_of(pos), sv[i]);
       }
     }
   } else {
@@ -711,16 +744,21 @@ struct ColTable {
       default: hipLaunchKernelGGL((col_kernel<LOGN, COL_SYNTH>), grid, dim3(th), lds, st, fl, n, nb, src); break;
     }
   }
-  template <bool FORCED>
-  static KernelLaunch step_kernel_f(int pts) {
+  template <int VAR>
+  static KernelLaunch step_kernel_v(int pts) {
     if (pts == 8)
-      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, FORCED>),
+      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, VAR>),
                           ColCfg<LOGN, 8>::THREADS, ColCfg<LOGN, 8>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, ff::kPts, FORCED>),
+    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, ff::kPts, VAR>),
                         ColCfg<LOGN>::THREADS, ColCfg<LOGN>::LDS_BYTES};
   }
-  static KernelLaunch step_kernel(int pts, bool forced) {
-    return forced ? step_kernel_f<true>(pts) : step_kernel_f<false>(pts);
+  static KernelLaunch step_kernel(int pts, int var) {
+    switch (var) {
+      case VAR_EULER_F: return step_kernel_v<VAR_EULER_F>(pts);
+      case VAR_HEUN_P: return step_kernel_v<VAR_HEUN_P>(pts);
+      case VAR_HEUN_C: return step_kernel_v<VAR_HEUN_C>(pts);
+      default: return step_kernel_v<VAR_EULER>(pts);
+    }
   }
 };
 
@@ -754,36 +792,42 @@ struct RowTable {
 
 template <int LOGN>
 struct ColPTable {
-  template <int PTS, bool FORCED>
+  template <int VAR>
   static KernelLaunch info(int mode) {
     if (mode == COL_FIRST)
-      return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST, PTS>),
-                          ColCfgP<LOGN, PTS>::THREADS, ColCfgP<LOGN, PTS>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, PTS, FORCED>),
-                        ColCfgP<LOGN, PTS>::THREADS, ColCfgP<LOGN, PTS>::LDS_BYTES};
+      return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_FIRST, 16>),
+                          ColCfgP<LOGN, 16>::THREADS, ColCfgP<LOGN, 16>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&colp_kernel<LOGN, COL_STEP, 16, VAR>),
+                        ColCfgP<LOGN, 16>::THREADS, ColCfgP<LOGN, 16>::LDS_BYTES};
   }
-  template <bool FORCED>
+  template <int VAR>
   static KernelLaunch split(int mode) {
     if (mode == COL_FIRST)
       return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_FIRST>), ColCfgQ<LOGN>::THREADS,
                           ColCfgQ<LOGN>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP, FORCED>), ColCfgQ<LOGN>::THREADS,
+    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP, VAR>), ColCfgQ<LOGN>::THREADS,
                         ColCfgQ<LOGN>::LDS_BYTES};
   }
+  template <int VAR>
+  static KernelLaunch pick(int mode, int pts) { return pts == 8 ? split<VAR>(mode) : info<VAR>(mode); }
   // pts 16: colp_kernel<., 16>; pts 8: the split kernel (8 points per thread in the forward transform)
-  static KernelLaunch step_kernel(int mode, int pts, bool forced) {
-    if (forced) return pts == 8 ? split<true>(mode) : info<16, true>(mode);
-    return pts == 8 ? split<false>(mode) : info<16, false>(mode);
+  static KernelLaunch step_kernel(int mode, int pts, int var) {
+    switch (var) {
+      case VAR_EULER_F: return pick<VAR_EULER_F>(mode, pts);
+      case VAR_HEUN_P: return pick<VAR_HEUN_P>(mode, pts);
+      case VAR_HEUN_C: return pick<VAR_HEUN_C>(mode, pts);
+      default: return pick<VAR_EULER>(mode, pts);
+    }
   }
 };
 
 template <int L>
-void dispatch_colp(int logn, int mode, int pts, bool forced, KernelLaunch* out) {
+void dispatch_colp(int logn, int mode, int pts, int var, KernelLaunch* out) {
   if constexpr (L <= kMaxLog) {
     if (logn == L)
-      *out = ColPTable<L>::step_kernel(mode, pts, forced);
+      *out = ColPTable<L>::step_kernel(mode, pts, var);
     else
-      dispatch_colp<L + 1>(logn, mode, pts, forced, out);
+      dispatch_colp<L + 1>(logn, mode, pts, var, out);
   }
 }
 
@@ -813,9 +857,9 @@ void dispatch_info(int logn, KernelLaunch* out, A... args) {
 // use hipExtLaunchKernel, which records the events in the kernel's own
 // dispatch (kernel start and end, no extra queue packets).
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool forced) {
-  if (mode == COL_STEP && (forced || pts != ff::kPts || ev_start || ev_stop)) {
-    const KernelLaunch kl = col_step_kernel(logn1, pts, forced);
+                const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, int var) {
+  if (mode == COL_STEP && (var != VAR_EULER || pts != ff::kPts || ev_start || ev_stop)) {
+    const KernelLaunch kl = col_step_kernel(logn1, pts, var);
     const long long* nb = nullptr;
     const float2* s = static_cast<const float2*>(src);
     void* args[] = {&fl, &n, &nb, &s};
@@ -843,15 +887,15 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
   dispatch_log<RowTable, kMinLog>(logn2, mode, dim3(groups, nfl), st, fl, n, in, out);
 }
 
-KernelLaunch colp_kernel_info(int logn1, int mode, int pts, bool forced) {
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts, int var) {
   KernelLaunch out{nullptr, 0, 0};
-  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, pts, forced, &out);
+  if (logn1 >= kMinLogProduct) dispatch_colp<kMinLogProduct>(logn1, mode, pts, var, &out);
   return out;
 }
 
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool forced) {
-  const KernelLaunch kl = colp_kernel_info(logn1, mode, pts, forced);
+                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, int var) {
+  const KernelLaunch kl = colp_kernel_info(logn1, mode, pts, var);
   if (!kl.func) return;
   const long long* nb = nullptr;
   const float2* s = static_cast<const float2*>(src);
@@ -862,9 +906,9 @@ void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const 
     (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
 }
 
-KernelLaunch col_step_kernel(int logn1, int pts, bool forced) {
+KernelLaunch col_step_kernel(int logn1, int pts, int var) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<ColTable, kMinLog>(logn1, &out, pts, forced);
+  dispatch_info<ColTable, kMinLog>(logn1, &out, pts, var);
   return out;
 }
 

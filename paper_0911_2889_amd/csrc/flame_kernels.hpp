@@ -16,9 +16,9 @@ struct KernelLaunch {
 };
 
 // The step kernels for a transform length (arguments: fls, n, nbase, src / in, out).
-// forced: the column kernel variant that adds each flame's bound forcing
-// spectrum (it steps flames without one unforced).
-KernelLaunch col_step_kernel(int logn1, int pts, bool forced = false);
+// var (StepVar): the column kernel's integrator stage and whether it reads
+// the flames' forcing spectra (flames without one are stepped unforced).
+KernelLaunch col_step_kernel(int logn1, int pts, int var = VAR_EULER);
 KernelLaunch row_step_kernel(int logn2, int pts);
 void launch_set_step(hipStream_t st, long long* counter, long long value);
 
@@ -26,18 +26,18 @@ void launch_set_step(hipStream_t st, long long* counter, long long value);
 // (fl points at their consecutive FlameDev entries in device memory). src,
 // if not null, replaces the state read by COL_FIRST and COL_SYNTH.
 // With ev_start/ev_stop (step mode only) the events mark the kernel's start and end;
-// forced selects the step variant that adds the forcing.
+// var selects the step variant (StepVar).
 void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                 const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
-                hipEvent_t ev_stop = nullptr, bool forced = false);
+                hipEvent_t ev_stop = nullptr, int var = VAR_EULER);
 
 // Column kernel of the step on the product grid (3 N1/4 rows; N1 >= 128),
 // mode COL_STEP or COL_FIRST; colp_kernel_info gives its function and shape
 // (func null for an unsupported size).
-KernelLaunch colp_kernel_info(int logn1, int mode, int pts, bool forced = false);
+KernelLaunch colp_kernel_info(int logn1, int mode, int pts, int var = VAR_EULER);
 void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                  const void* src = nullptr, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
-                 hipEvent_t ev_stop = nullptr, bool forced = false);
+                 hipEvent_t ev_stop = nullptr, int var = VAR_EULER);
 
 // Adjoint kernels (adjoint_kernels.hip); see the modes in flame_dev.hpp.
 void launch_adj_col(int logn1, int mode, int tiles, hipStream_t st, const FlameDev* fl, long long n,

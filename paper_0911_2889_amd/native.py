@@ -38,7 +38,7 @@ class FlameDesc(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("axis_scale", ctypes.c_double * 2),
         ("r0_law", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -106,13 +106,15 @@ def check(rc):
     return rc
 
 
-def make_desc(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25, axis_scale=None, r0_law=0):
+def make_desc(n1, n2, gamma=0.8, theta_pi=1.0, t0=200.0, dt=0.25, axis_scale=None, r0_law=0, integrator=0):
+    """integrator: 0 integrating-factor Euler, 1 integrating-factor Heun (or "euler" / "rk2")."""
     d = FlameDesc()
     d.n1, d.n2 = int(n1), int(n2)
     d.gamma, d.theta_pi, d.t0, d.dt = float(gamma), float(theta_pi), float(t0), float(dt)
     sc = (0.0, 0.0) if axis_scale is None else (float(axis_scale[0]), float(axis_scale[1]))
     d.axis_scale[0], d.axis_scale[1] = sc
-    d.r0_law, d.reserved = int(r0_law), 0
+    d.r0_law = int(r0_law)
+    d.integrator = {"euler": 0, "rk2": 1}.get(integrator, integrator) if isinstance(integrator, str) else int(integrator)
     return d
 
 

@@ -20,8 +20,9 @@ class FlameEnsemble:
 
     descs: list of dicts with keys n1, n2 and optionally gamma, theta_pi, t0,
     dt, axis_scale, r0_law (1: the reference radius comes from a table given
-    with set_r0_table). The plan is bound to the current torch stream of
-    `device`.
+    with set_r0_table), integrator (0 or "euler": integrating-factor Euler;
+    1 or "rk2": integrating-factor Heun). The plan is bound to the current
+    torch stream of `device`.
     """
 
     def __init__(self, descs, device="cuda", ws_fill=None):

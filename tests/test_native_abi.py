@@ -54,6 +54,8 @@ def test_state_and_workspace_sizes(native):
     (dict(n1=64, n2=128, axis_scale=(1.0, 0.0)), -1),
     (dict(n1=64, n2=128, r0_law=2), -1),
     (dict(n1=64, n2=128, r0_law=-1), -1),
+    (dict(n1=64, n2=128, integrator=2), -1),
+    (dict(n1=64, n2=128, integrator=-1), -1),
 ])
 def test_bad_descriptors_are_rejected(native, kw, code):
     d = native.make_desc(**kw)
