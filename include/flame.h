@@ -182,7 +182,9 @@ int flame_set_r0_table(flame_plan plan, int32_t flame, const double* table, int6
  * Im f~_0 have no effect; entries outside the box are ignored. The buffer is
  * read by every later step until replaced or flame_destroy: for a forcing
  * that varies in time, rewrite it (stream-ordered) between calls of
- * flame_step, which then uses one forcing for all of its nsteps steps. The
+ * flame_step, which then uses one forcing for all of its nsteps steps (with
+ * integrator 1, for both of Heun's stages, i.e. also as f~(t_{n+1}); a
+ * forcing that varies within a step is then taken to first order only). The
  * adjoint and gradient calls do not depend on it. A grid-size group steps
  * with a column-kernel variant that reads the forcing while any of its
  * flames has one bound (members without one are stepped unforced by it);
