@@ -154,3 +154,35 @@ def test_full_size_heun_steps_match_oracle(flame):
     got = sim.spectrum().cpu().numpy()
     assert rel_l2(got, half) > 1e-3
     assert rel_l2(got, ref) < 1e-5
+
+
+@pytest.mark.parametrize("n1,n2", [(64, 128), (128, 256)])
+def test_dt_convergence_orders_on_the_gpu(flame, n1, n2):
+    """dt-convergence study of the GPU stepper over t in [5, 7] (amplitude 0.1,
+    so the quadratic term matters) against DOP853 on the oracle's right-hand
+    side of Eq. (1): the error falls by about 2 per halving of dt for Euler
+    and by about 4 for Heun (observed orders 1 and 2)."""
+    from scipy.integrate import solve_ivp
+
+    w = synth.Workload("conv", n1, n2, 1, 0.2, "disc", 0.1, -1.0, 11, max_norm=24, t0=5.0)
+    half = synth.workload_spectrum(w)
+    t0, T = 5.0, 2.0
+    full0 = oracle.run(oracle.half_to_full(half.astype(np.complex128), n1, n2), oracle.Params(n1, n2, t0=t0), 0)
+    mask = oracle.box_mask(n1, n2)
+    pp = oracle.Params(n1, n2, t0=t0, dt=1.0)
+    sol = solve_ivp(lambda t, y: (oracle.rhs(y.reshape(n1, n2), pp, t) * mask).ravel(), (t0, t0 + T),
+                    (full0 * mask).ravel(), method="DOP853", rtol=1e-12, atol=1e-16)
+    ref = oracle.full_to_half(sol.y[:, -1].reshape(n1, n2), n1, n2)
+    errs = {}
+    for integ in (0, 1):
+        errs[integ] = []
+        for ns in (10, 20, 40, 80):
+            sim = flame.FlameSim(n1, n2, t0=t0, dt=T / ns, integrator=integ)
+            sim.set_spectrum(half)
+            sim.step(ns)
+            errs[integ].append(rel_l2(sim.spectrum().cpu().numpy(), ref))
+    r_euler = [a / b for a, b in zip(errs[0], errs[0][1:])]
+    r_heun = [a / b for a, b in zip(errs[1], errs[1][1:])]
+    assert all(1.8 < r < 2.6 for r in r_euler), (errs, r_euler)
+    assert all(3.0 < r < 4.6 for r in r_heun) and r_heun[-1] > 3.6, (errs, r_heun)
+    assert errs[1][-1] < 0.1 * errs[0][-1]
