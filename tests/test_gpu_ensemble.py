@@ -103,11 +103,14 @@ def test_full_ensemble_256_flames():
     assert all(ens.diagnostics(f)["finite"] for f in range(0, 256, 17))
 
 
-def test_autotune_keeps_the_state_and_agrees_with_the_oracle():
+@pytest.mark.parametrize("graph_steps", [0, 6])
+def test_autotune_keeps_the_state_and_agrees_with_the_oracle(graph_steps):
+    """With and without graph replays set on the plan."""
     from paper_0911_2889_amd import FlameEnsemble
     members = [synth.Workload(f"a{i}", n1, n2, 20, 0.25, "disc", 1e-3, -1.0, 3000 + i, max_norm=12)
                for i, (n1, n2) in enumerate([(64, 128), (64, 128), (256, 512), (128, 64)])]
     ens = FlameEnsemble(member_descs(members))
+    ens.set_graph_steps(graph_steps)
     halves = [synth.workload_spectrum(w) for w in members]
     for f, h in enumerate(halves):
         ens.set_spectrum(h, flame=f, n=0)
