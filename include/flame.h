@@ -29,7 +29,8 @@
  *    queue device work do not synchronise.
  *  - A plan is not thread-safe; use one plan per stream.
  *
- * Supported grids: N1 and N2 powers of two with 16 <= N_i <= 4096.
+ * Supported grids: N1 and N2 powers of two with 16 <= N_i <= 8192 (flame_init
+ * also checks that every kernel of the grid fits the device's LDS per workgroup).
  *
  * State layout (internal to the stepper but documented for checkpointing):
  * complex64 S[m][s], m = k2 in [0, N2/4), s in [0, N1/2) with k1 = s - N1/4;
@@ -62,7 +63,7 @@ typedef struct flame_plan_s* flame_plan;
 /* Problem description of one flame (Section 2: gamma = 0.8, t0 = 200 in the
  * paper's runs; theta_pi is the segment integer; dt is the fixed step). */
 typedef struct {
-  int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 4096] */
+  int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 8192] */
   double gamma;           /* density contrast 1 - rho_b/rho_u, >= 0 */
   double theta_pi;        /* segment integer theta_pi, > 0 */
   double t0;              /* time of step index 0, > 0 */
@@ -85,7 +86,10 @@ int flame_workspace_bytes(const flame_desc* descs, int32_t n_flames, size_t* byt
  * and ws (dev, ws_bytes >= flame_workspace_bytes) stay bound to the plan until
  * flame_destroy. Builds twiddle tables on the host (double precision, rounded
  * once to float) and copies them into ws on the stream. The states are not
- * initialised: call flame_set_spectrum or flame_set_state next. */
+ * initialised: call flame_set_spectrum or flame_set_state next. Fails with
+ * FLAME_ERR_UNSUPPORTED_SIZE if a kernel of some flame's grid needs more LDS
+ * per workgroup than the device offers (the 8192-point transforms use up to
+ * 104 KB). */
 int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, void* ws, size_t ws_bytes,
                void* hip_stream, flame_plan* out);
 

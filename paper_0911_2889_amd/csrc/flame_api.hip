@@ -59,7 +59,7 @@ int check_desc(const flame_desc* d, Sizes* s) {
   const int l1 = ilog2_exact(d->n1), l2 = ilog2_exact(d->n2);
   if (l1 < 0 || l2 < 0) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must be powers of two", d->n1, d->n2);
   if (l1 < flame::kMinLog || l1 > flame::kMaxLog || l2 < flame::kMinLog || l2 > flame::kMaxLog)
-    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must lie in [16, 4096]", d->n1, d->n2);
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must lie in [16, 8192]", d->n1, d->n2);
   if (!(std::isfinite(d->gamma) && d->gamma >= 0.0)) return fail(FLAME_ERR_INVALID_ARG, "gamma must be finite and >= 0");
   if (!(std::isfinite(d->theta_pi) && d->theta_pi > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "theta_pi must be > 0");
   if (!(std::isfinite(d->t0) && d->t0 > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "t0 must be > 0");
@@ -485,6 +485,22 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e, "hipGetDevice");
+  }
+  // every kernel of every flame must fit the device's LDS per workgroup
+  int max_lds = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  for (int f = 0; f < n_flames; ++f) {
+    const Sizes& s = p->layout.sizes[f];
+    const int need = flame::lds_bytes_needed(s.logn1, s.logn2);
+    if (need > max_lds) {
+      delete p;
+      return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d needs %d bytes of LDS per workgroup, the device has %d",
+                  descs[f].n1, descs[f].n2, need, max_lds);
+    }
   }
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->nfl = n_flames;

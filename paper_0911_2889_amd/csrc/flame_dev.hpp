@@ -11,6 +11,18 @@
 
 namespace flame {
 
+// Minimum waves per SIMD the row and column kernels are compiled for (a
+// register budget of 512 / waves VGPRs).
+#ifndef ROW_WAVES_PER_EU
+#define ROW_WAVES_PER_EU 3
+#endif
+#ifndef COL_WAVES_PER_EU
+#define COL_WAVES_PER_EU 2
+#endif
+#ifndef ADJ_ROW_WAVES_PER_EU
+#define ADJ_ROW_WAVES_PER_EU 2
+#endif
+
 // Per-flame pointers and constants read by every kernel (one entry per flame
 // in a device array; blockIdx.y selects the flame inside a launch).
 struct FlameDev {
@@ -112,6 +124,9 @@ struct ColCfgQ {
 };
 
 // Row kernel: B = max(1, 16*256/N2) row pairs per workgroup, interleaved.
+// WPE: the minimum waves per SIMD it is compiled for; at N2 = 8192 with 16
+// points per thread a workgroup is 8 waves (2 per SIMD), which may then use
+// the whole register budget instead of spilling.
 template <int LOGN2, int PTS = ff::kPts>
 struct RowCfg {
   static constexpr int G16 = ff::Shape<LOGN2>::G;
@@ -119,6 +134,7 @@ struct RowCfg {
   static constexpr int B = G16 >= 256 ? 1 : 256 / G16;
   static constexpr int THREADS = B * G;
   static constexpr int LDS_BYTES = ff::Shape<LOGN2>::LDS * B * 8;
+  static constexpr int WPE = THREADS >= 512 && PTS == 16 ? 2 : ROW_WAVES_PER_EU;
 };
 
 constexpr int col_tile(int logn1) { return col_tile_for((1 << logn1) / ff::kPts); }
@@ -161,20 +177,8 @@ constexpr int kTwCacheMinNs = FLAME_TW_CACHE_MIN_NS;
 constexpr bool kPrune = FLAME_PRUNE != 0;
 
 
-// Minimum waves per SIMD the row and column kernels are compiled for (a
-// register budget of 512 / waves VGPRs).
-#ifndef ROW_WAVES_PER_EU
-#define ROW_WAVES_PER_EU 3
-#endif
-#ifndef COL_WAVES_PER_EU
-#define COL_WAVES_PER_EU 2
-#endif
-#ifndef ADJ_ROW_WAVES_PER_EU
-#define ADJ_ROW_WAVES_PER_EU 2
-#endif
-
 constexpr int kMinLog = 4;
-constexpr int kMaxLog = 12;
+constexpr int kMaxLog = 13;
 constexpr int kDiagThreads = 256;
 
 }  // namespace flame

@@ -187,7 +187,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
 }
 
 template <int LOGN2, int MODE, int PTS = ff::kPts>
-__global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(ROW_WAVES_PER_EU)))
+__global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(RowCfg<LOGN2, PTS>::WPE)))
     row_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase,
                const float* __restrict__ phys_in, float* __restrict__ phys_out) {
   if (nbase) n += *nbase;
@@ -904,6 +904,38 @@ void launch_colp(int logn1, int mode, int tiles, int nfl, hipStream_t st, const 
     (void)hipExtLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st, ev_start, ev_stop, 0);
   else
     (void)hipLaunchKernel(kl.func, dim3(tiles, nfl), dim3(kl.threads), args, kl.lds, st);
+}
+
+namespace {
+
+template <int L>
+int col_lds(int logn1) {
+  if constexpr (L <= kMaxLog) {
+    if (logn1 != L) return col_lds<L + 1>(logn1);
+    int b = ColCfg<L, 16>::LDS_BYTES > ColCfg<L, 8>::LDS_BYTES ? ColCfg<L, 16>::LDS_BYTES : ColCfg<L, 8>::LDS_BYTES;
+    if constexpr (L >= kMinLogProduct) {
+      if (ColCfgP<L, 16>::LDS_BYTES > b) b = ColCfgP<L, 16>::LDS_BYTES;
+      if (ColCfgQ<L>::LDS_BYTES > b) b = ColCfgQ<L>::LDS_BYTES;
+    }
+    return b;
+  }
+  return 0;
+}
+
+template <int L>
+int row_lds(int logn2) {
+  if constexpr (L <= kMaxLog) {
+    if (logn2 != L) return row_lds<L + 1>(logn2);
+    return RowCfg<L, 16>::LDS_BYTES > RowCfg<L, 8>::LDS_BYTES ? RowCfg<L, 16>::LDS_BYTES : RowCfg<L, 8>::LDS_BYTES;
+  }
+  return 0;
+}
+
+}  // namespace
+
+int lds_bytes_needed(int logn1, int logn2) {
+  const int c = col_lds<kMinLog>(logn1), r = row_lds<kMinLog>(logn2);
+  return c > r ? c : r;
 }
 
 KernelLaunch col_step_kernel(int logn1, int pts, int var) {

@@ -21,6 +21,9 @@ struct KernelLaunch {
 KernelLaunch col_step_kernel(int logn1, int pts, int var = VAR_EULER);
 KernelLaunch row_step_kernel(int logn2, int pts);
 void launch_set_step(hipStream_t st, long long* counter, long long value);
+// Largest dynamic LDS (bytes per workgroup) any kernel of an N1 x N2 flame
+// asks for (row, column, product-grid and adjoint kernels, every variant).
+int lds_bytes_needed(int logn1, int logn2);
 
 // Column kernel over `tiles` tiles of T columns for `nfl` flames of one size
 // (fl points at their consecutive FlameDev entries in device memory). src,

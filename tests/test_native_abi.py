@@ -41,12 +41,15 @@ def test_state_and_workspace_sizes(native):
     # five N1 x N2/4 complex intermediates dominate (three for the step, two for the adjoint)
     assert 5 * 2048 * 1024 * 8 <= ws < 5 * 2048 * 1024 * 8 + (1 << 20)
     assert native.workspace_bytes([d, native.make_desc(64, 128)]) > ws
+    # the largest supported grid
+    assert native.state_bytes(native.make_desc(8192, 8192)) == 8192 * 8192
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(n1=100, n2=128), -4),
     (dict(n1=8, n2=128), -4),
-    (dict(n1=64, n2=8192), -4),
+    (dict(n1=64, n2=16384), -4),
+    (dict(n1=8, n2=8192), -4),
     (dict(n1=64, n2=128, dt=0.0), -1),
     (dict(n1=64, n2=128, t0=-1.0), -1),
     (dict(n1=64, n2=128, gamma=float("nan")), -1),
