@@ -957,6 +957,10 @@ int flame_get_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t* enable
   return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
 }
 
+// A configuration replaces the default only if it runs in at most this
+// fraction of the default's time.
+constexpr float kAutotuneMargin = 0.98f;
+
 int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
@@ -998,6 +1002,9 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
         for (int r : {16, 8}) cfgs.push_back(Cfg{true, c, r});
     float best = 1e30f;
     Cfg best_cfg{gr.product, gr.col_pts, gr.row_pts};
+    // the default: 16 points per thread, product grid where it exists
+    const Cfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts};
+    float default_ms = 1e30f;
     auto select = [&](const Cfg& cf) -> int {
       gr.col_pts = cf.c;
       gr.row_pts = cf.r;
@@ -1038,7 +1045,11 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
         best = ms;
         best_cfg = cf;
       }
+      if (cf.product == default_cfg.product && cf.c == default_cfg.c && cf.r == default_cfg.r) default_ms = ms;
     }
+    // keep the default unless another choice is clearly faster: choices
+    // within timing noise of each other would otherwise flip between runs
+    if (best > kAutotuneMargin * default_ms) best_cfg = default_cfg;
     rc = select(best_cfg);
     if (rc) {
       (void)hipEventDestroy(ev0);
