@@ -339,3 +339,42 @@ def test_tabulated_reference_radius_matches_oracle(flame, n1, n2, product):
     ref = oracle.full_to_half(oracle.step_adjoint(sf, lf, p, 5), n1, n2)
     sim.states[0].copy_(lo)
     assert rel_l2(sim.spectrum().cpu().numpy(), ref) < 1e-5
+
+
+def test_degenerate_cases(flame):
+    """gamma = 0 (no instability: every small mode decays), a step of 0
+    steps, a very long time step, and a state holding only the mean mode
+    (E_0 = 1 and the quadratic term vanishes, so it must not change)."""
+    n1, n2 = 64, 128
+    # gamma = 0 against the oracle, and every mode's magnitude decays
+    w = small_workload(n1, n2, seed=21, amp=1e-4, t0=5.0, dt=0.2)
+    half = synth.workload_spectrum(w)
+    sim = flame.FlameSim(n1, n2, gamma=0.0, t0=w.t0, dt=w.dt)
+    sim.set_spectrum(half)
+    sim.step(10)
+    got = sim.spectrum().cpu().numpy()
+    p = oracle.Params(n1, n2, gamma=0.0, t0=w.t0, dt=w.dt)
+    assert rel_l2(got, oracle_trajectory(half, p, [10])[10]) < 1e-5
+    nz = np.abs(half) > 0
+    assert np.all(np.abs(got[nz]) < np.abs(half[nz]))
+    # zero steps change nothing, not even the step index
+    before = sim.spectrum().cpu().numpy()
+    sim.step(0)
+    assert sim.step_index == 10 and np.array_equal(sim.spectrum().cpu().numpy(), before)
+    # a long step (dt = 50 at t0 = 200): high modes are damped to zero, no overflow
+    w2 = small_workload(n1, n2, seed=22, amp=1e-2, t0=200.0, dt=50.0)
+    half2 = synth.workload_spectrum(w2)
+    sim2 = make_sim(flame, w2)
+    sim2.set_spectrum(half2)
+    sim2.step(3)
+    got2 = sim2.spectrum().cpu().numpy()
+    assert np.all(np.isfinite(got2))
+    assert rel_l2(got2, oracle_trajectory(half2, oracle_params(w2), [3])[3]) < 1e-5
+    # only the mean mode: unchanged bit for bit, everything else stays zero
+    k1max = (half.shape[0] - 1) // 2
+    mean_only = np.zeros_like(half)
+    mean_only[k1max, 0] = np.complex64(0.37)
+    sim3 = make_sim(flame, w)
+    sim3.set_spectrum(mean_only)
+    sim3.step(7)
+    assert np.array_equal(sim3.spectrum().cpu().numpy(), mean_only)
