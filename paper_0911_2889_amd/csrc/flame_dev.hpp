@@ -29,7 +29,7 @@ struct FlameDev {
   float2* S;           // state, [M][H1]
   float2* Wp;          // column transforms of (i kappa1 - kappa2) Phi~ and ...
   float2* Wm;          // ... the conj of those of (i kappa1 + kappa2) Phi~, interleaved
-                       // [j1/2][m][Wp, Wm][j1%2] (Wm = Wp + 2; index with w_index)
+                       // [j1/4][m][j1%4], Wp and Wm in the two halves of W (index with w_index)
   float2* Q;           // row transforms of |grad Phi|^2 (and scratch), tiled [m/TQ][j1][m%TQ]
   float2* A1;          // adjoint scratch, same layout: row transform of w1 = m g1
   float2* A2;          // adjoint scratch, same layout: i kappa2 x row transform of w2 = m g2

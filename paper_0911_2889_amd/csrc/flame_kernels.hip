@@ -16,7 +16,7 @@
 //    k1 Psi and k2 Psi; the inverse column transform of the product.)
 // The global transposes of Section 3 are the layouts of Wp/Wm and Q in HBM:
 // each kernel reads long contiguous runs and writes pieces of at least 64
-// bytes (2 rows x 4 columns of Q; 2 rows x 2 columns of Wp and Wm).
+// bytes (2 rows x 4 columns of Q; 4 rows x 2 columns of Wp, and of Wm).
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -220,17 +220,17 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
     }();
     // both rows' inputs come in one 16-byte load per register (w_index layout)
     float2 vr[2][PTS];
-    const int pbase = pair * mcols;
+    const int pbase4 = (pair >> 1) * mcols, poff = (pair & 1) << 1;
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
       const int idx = t + G * i;
       float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
       if (live) {
         if (i < LOW) {
-          ld_pair(Wp + ((pbase + idx) << 2), a, b);
+          ld_pair(Wp + (((pbase4 + idx) << 2) + poff), a, b);
         } else if (i >= HIGH) {
           const int mm = N2 - idx;
-          if (mm < mcols) ld_pair(Wm + ((pbase + mm) << 2), a, b);
+          if (mm < mcols) ld_pair(Wm + (((pbase4 + mm) << 2) + poff), a, b);
         }
       }
       vr[0][i] = a;

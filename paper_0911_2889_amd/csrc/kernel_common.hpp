@@ -170,13 +170,14 @@ __device__ __forceinline__ float2 forcing_at(const FlameDev& f, int m, int k1) {
   return ld((const gf2*)f.F + (size_t)m * f.h1 + (f.n1 >> 2) + k1);
 }
 
-// Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm = f.Wp + 2:
-// [j1/2][m][Wp, Wm][j1%2], so that the spectra of a row pair are one
-// contiguous run (the row kernel reads both rows of Wp or Wm with one 16-byte
-// load per lane) and the column kernel writes its two columns of a row pair,
-// Wp and Wm, as one 64-byte piece.
+// Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm (Wp and Wm
+// fill the two halves of the W buffer): [j1/4][m][j1%4], so that the two rows
+// of a row pair are adjacent (the row kernel reads both with one 16-byte load
+// per lane) and a column workgroup of T columns writes four rows of them as
+// one 32 T-byte piece of Wp (64 bytes at T = 2), and one of Wm, each complete
+// when it is stored.
 __device__ __forceinline__ int w_index(int j1, int m, int mcols) {
-  return (((j1 >> 1) * mcols + m) << 2) + (j1 & 1);
+  return (((j1 >> 2) * mcols + m) << 2) + (j1 & 3);
 }
 
 using v4f = float __attribute__((ext_vector_type(4)));
