@@ -339,7 +339,8 @@ def ensemble_leg(steps, graph_steps):
     nbytes = None  # set after autotuning, which picks each group's grid
     for f, h in enumerate(halves):
         ens.set_spectrum(h, flame=f)
-    ens.autotune(steps=10)  # points per thread per grid group
+    ens.set_graph_steps(graph_steps)
+    ens.autotune(steps=10)  # per grid group, then jointly for the groups' concurrent graph branches
     grids = ((128, 256), (256, 512), (512, 1024))
     tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) + ["product" if ens.product_grid(n1, n2) else "n1"]
              for n1, n2 in grids}

@@ -250,7 +250,12 @@ int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* ena
  * the product grid where n1 >= 128), else the default, so that choices within
  * timing noise of each other do not change from run to run. The
  * configurations are (col_pts, row_pts) in {16, 8}^2 on the N1-row grid
- * and, for n1 >= 128, on the product grid. The states
+ * and, for n1 >= 128, on the product grid. When graphs are in use
+ * (flame_set_graph_steps > 0) and the plan has several groups, whose chains
+ * run concurrently in a replay, the choices are then refined jointly:
+ * coordinate descent over the groups, each trial running `steps` steps of
+ * every group at once on streams of their own, a change kept only if it runs
+ * in at most 98 % of the best time so far. The states
  * and the step index are saved in the workspace and restored afterwards, so
  * the call does not change the simulation; it synchronises the stream.
  * *n_configs_tried (nullable) receives the number of timed configurations. */

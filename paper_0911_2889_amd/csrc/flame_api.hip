@@ -350,19 +350,21 @@ int apply_rows(flame_plan p, int gi) {
   return FLAME_OK;
 }
 
-void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
-  flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups(), gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                    nullptr, gr.row_pts, e0, e1);
+// The step's kernels of one group, on the plan's stream unless `st` is given.
+void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
+                     hipStream_t st = nullptr) {
+  flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups(), gr.count, st ? st : p->stream, p->ddev + gr.first, n,
+                    nullptr, nullptr, gr.row_pts, e0, e1);
 }
 
 void launch_step_col(flame_plan p, const Group& gr, long long n, int pass, hipEvent_t e0 = nullptr,
-                     hipEvent_t e1 = nullptr) {
+                     hipEvent_t e1 = nullptr, hipStream_t st = nullptr) {
   if (gr.product)
-    flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                       gr.col_pts, e0, e1, gr.col_var(pass));
+    flame::launch_colp(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, st ? st : p->stream, p->ddev + gr.first, n,
+                       nullptr, gr.col_pts, e0, e1, gr.col_var(pass));
   else
-    flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, p->stream, p->ddev + gr.first, n, nullptr,
-                      gr.col_pts, e0, e1, gr.col_var(pass));
+    flame::launch_col(gr.logn1, flame::COL_STEP, gr.tiles, gr.count, st ? st : p->stream, p->ddev + gr.first, n,
+                      nullptr, gr.col_pts, e0, e1, gr.col_var(pass));
 }
 
 void drop_graph(flame_plan p) {
@@ -961,6 +963,121 @@ int flame_get_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t* enable
 // fraction of the default's time.
 constexpr float kAutotuneMargin = 0.98f;
 
+struct TuneCfg {
+  bool product;
+  int c, r;
+  bool operator==(const TuneCfg& o) const { return product == o.product && c == o.c && r == o.r; }
+};
+
+static std::vector<TuneCfg> tune_cfgs(const Group& gr) {
+  std::vector<TuneCfg> cfgs;
+  for (int c : {16, 8})
+    for (int r : {16, 8}) cfgs.push_back(TuneCfg{false, c, r});
+  if (gr.logn1 >= flame::kMinLogProduct)
+    for (int c : {16, 8})
+      for (int r : {16, 8}) cfgs.push_back(TuneCfg{true, c, r});
+  return cfgs;
+}
+
+static int tune_select(flame_plan p, size_t gi, const TuneCfg& cf) {
+  Group& gr = p->groups[gi];
+  gr.col_pts = cf.c;
+  gr.row_pts = cf.r;
+  if (gr.product != cf.product) {
+    gr.product = cf.product;
+    return apply_rows(p, (int)gi);
+  }
+  return FLAME_OK;
+}
+
+// Joint refinement for plans of several groups that step in graphs: in a
+// replay the groups' chains run concurrently, so a group's fastest choice
+// alone need not be the fastest beside the others. Each trial runs `steps`
+// steps of every group at once, each group's chain on a stream of its own
+// (forked from and joined back to the plan's stream, as a replay's branches
+// are), and coordinate descent over the groups keeps a change only if the
+// trial's time falls below kAutotuneMargin of the best so far.
+static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev0, hipEvent_t ev1) {
+  const size_t ng = p->groups.size();
+  std::vector<hipStream_t> st(ng, nullptr);
+  std::vector<hipEvent_t> done(ng, nullptr);
+  hipEvent_t fork = nullptr;
+  int rc = FLAME_OK;
+  hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (size_t gi = 0; e == hipSuccess && gi < ng; ++gi) {
+    e = hipStreamCreateWithFlags(&st[gi], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done[gi], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) rc = hip_fail(e, "autotune streams");
+  auto trial = [&](float* ms) -> int {
+    for (int f = 0; f < p->nfl; ++f)
+      if (!p->w_valid[f]) {
+        const int r = rebuild_w(p, f);
+        if (r) return r;
+      }
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // the first repetition warms up
+      hipError_t e2 = hipEventRecord(ev0, p->stream);
+      if (e2 == hipSuccess) e2 = hipEventRecord(fork, p->stream);
+      for (size_t gi = 0; e2 == hipSuccess && gi < ng; ++gi) {
+        e2 = hipStreamWaitEvent(st[gi], fork, 0);
+        const Group& gr = p->groups[gi];
+        for (int s = 0; e2 == hipSuccess && s < steps; ++s)
+          for (int pass = 0; pass < gr.passes(); ++pass) {
+            launch_step_row(p, gr, n0, nullptr, nullptr, st[gi]);
+            launch_step_col(p, gr, n0, pass, nullptr, nullptr, st[gi]);
+          }
+        if (e2 == hipSuccess) e2 = hipEventRecord(done[gi], st[gi]);
+        if (e2 == hipSuccess) e2 = hipStreamWaitEvent(p->stream, done[gi], 0);
+      }
+      if (e2 == hipSuccess) e2 = hipEventRecord(ev1, p->stream);
+      if (e2 == hipSuccess) e2 = hipEventSynchronize(ev1);
+      float t = 0.f;
+      if (e2 == hipSuccess) e2 = hipEventElapsedTime(&t, ev0, ev1);
+      if (e2 != hipSuccess) return hip_fail(e2, "autotune joint timing");
+      if (rep > 0) best = std::min(best, t);
+    }
+    *ms = best;
+    return last_launch("autotune joint launch");
+  };
+  float best_all = 0.f;
+  if (rc == FLAME_OK) rc = trial(&best_all);
+  for (int round = 0; rc == FLAME_OK && round < 2; ++round) {
+    bool improved = false;
+    for (size_t gi = 0; rc == FLAME_OK && gi < ng; ++gi) {
+      const Group& gr = p->groups[gi];
+      const TuneCfg cur{gr.product, gr.col_pts, gr.row_pts};
+      TuneCfg keep = cur;
+      for (const TuneCfg& cf : tune_cfgs(gr)) {
+        if (cf == cur) continue;
+        rc = tune_select(p, gi, cf);
+        float t = 0.f;
+        if (rc == FLAME_OK) rc = trial(&t);
+        if (rc) break;
+        if (t < kAutotuneMargin * best_all) {
+          best_all = t;
+          keep = cf;
+          improved = true;
+        }
+      }
+      if (rc == FLAME_OK) rc = tune_select(p, gi, keep);
+    }
+    if (!improved) break;
+  }
+  // every stream has drained: ev1 was synchronised after the last trial
+  if (rc == FLAME_OK) {
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "autotune joint sync");
+  }
+  for (size_t gi = 0; gi < ng; ++gi) {
+    if (st[gi]) (void)hipStreamSynchronize(st[gi]);
+    if (done[gi]) (void)hipEventDestroy(done[gi]);
+    if (st[gi]) (void)hipStreamDestroy(st[gi]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  return rc;
+}
+
 int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
@@ -1068,8 +1185,13 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
       return rc;
     }
   }
+  if (saved_graph > 0 && p->groups.size() > 1) rc = autotune_jointly(p, steps, n0, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
+  if (rc) {
+    p->graph_steps = saved_graph;
+    return rc;
+  }
   for (int f = 0; f < p->nfl; ++f) {
     const size_t bytes = (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2);
     e = hipMemcpyAsync(p->hdev[f].S, p->hdev[f].A1, bytes, hipMemcpyDeviceToDevice, p->stream);
