@@ -268,10 +268,13 @@ int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
  * no edges between them, so a mixed ensemble runs its groups concurrently.
  * flame_step(n) launches floor(n / steps) graphs and the remainder directly.
  * The graph is built on first use and replayed; the step index is read from
- * the workspace, set by a one-thread kernel before each replay. */
+ * the workspace, set by a one-thread kernel before each replay. Calls that
+ * discard the graph (a new graph length, points per thread, grid or forcing
+ * group) first wait for the plan's stream. */
 int flame_set_graph_steps(flame_plan plan, int32_t steps);
 
-/* Release the plan's host metadata (device buffers stay the caller's). */
+/* Release the plan's host metadata (device buffers stay the caller's), after
+ * waiting for the plan's stream. */
 int flame_destroy(flame_plan plan);
 
 /* Text of the last error raised on the calling thread ("" if none). */

@@ -367,7 +367,11 @@ void launch_step_col(flame_plan p, const Group& gr, long long n, int pass, hipEv
                       nullptr, gr.col_pts, e0, e1, gr.col_var(pass));
 }
 
+// Destroy the step graph. A replay may still run on the plan's stream (or
+// the runtime may still hold it), so the stream is drained first.
 void drop_graph(flame_plan p) {
+  if (!p->graph_exec && !p->graph) return;
+  (void)hipStreamSynchronize(p->stream);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->graph_exec = nullptr;
@@ -1241,6 +1245,11 @@ int flame_timing_end(flame_plan p, double* ms4, int64_t* counts4) {
 
 int flame_destroy(flame_plan p) {
   if (!p) return fail(FLAME_ERR_INVALID_ARG, "null plan");
+  {
+    // the plan's graph and events may still be in use by queued work
+    DeviceGuard g(p->device);
+    (void)hipStreamSynchronize(p->stream);
+  }
   delete p;
   return FLAME_OK;
 }
