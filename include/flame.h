@@ -256,8 +256,9 @@ int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* ena
  * coordinate descent over the groups, each trial running `steps` steps of
  * every group at once on streams of their own, a change kept only if it runs
  * in at most 98 % of the best time so far. The states
- * and the step index are saved in the workspace and restored afterwards, so
- * the call does not change the simulation; it synchronises the stream.
+ * and the step index are saved in the workspace and restored afterwards,
+ * also when a trial fails, so the call does not change the simulation; it
+ * synchronises the stream.
  * *n_configs_tried (nullable) receives the number of timed configurations. */
 int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
 

@@ -1082,6 +1082,53 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
   return rc;
 }
 
+// Each group alone: time every configuration of tune_cfgs in two rounds
+// (keeping each one's faster time: in the first round the early
+// configurations run on a GPU that is still raising its clocks), then select
+// the fastest unless the default (16 points per thread, product grid where it
+// exists) is within kAutotuneMargin of it, so that choices within timing noise
+// of each other do not flip between runs.
+static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipEvent_t ev0, hipEvent_t ev1,
+                          int* tried) {
+  const Group& gr = p->groups[gi];
+  const std::vector<TuneCfg> cfgs = tune_cfgs(gr);
+  const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts};
+  std::vector<float> t_best(cfgs.size(), 1e30f);
+  for (int round = 0; round < 2; ++round) {
+    for (size_t ci = 0; ci < cfgs.size(); ++ci) {
+      int rc = tune_select(p, gi, cfgs[ci]);
+      for (int f = gr.first; rc == FLAME_OK && f < gr.first + gr.count; ++f)
+        if (!p->w_valid[f]) rc = rebuild_w(p, f);
+      if (rc) return rc;
+      // one untimed step, then `steps` timed steps of this group alone
+      hipError_t e = hipSuccess;
+      for (int s = 0; s <= steps; ++s) {
+        if (s == 1) e = hipEventRecord(ev0, p->stream);
+        for (int pass = 0; pass < gr.passes(); ++pass) {
+          launch_step_row(p, gr, n0);
+          launch_step_col(p, gr, n0, pass);
+        }
+      }
+      if (e == hipSuccess) e = hipEventRecord(ev1, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e != hipSuccess) return hip_fail(e, "autotune timing");
+      rc = last_launch("autotune launch");
+      if (rc) return rc;
+      if (round == 0) ++*tried;
+      t_best[ci] = std::min(t_best[ci], ms);
+    }
+  }
+  size_t best = 0, dflt = 0;
+  for (size_t ci = 0; ci < cfgs.size(); ++ci) {
+    if (t_best[ci] < t_best[best]) best = ci;
+    if (cfgs[ci] == default_cfg) dflt = ci;
+  }
+  if (t_best[best] > kAutotuneMargin * t_best[dflt]) best = dflt;
+  return tune_select(p, gi, cfgs[best]);
+}
+
 int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
@@ -1089,123 +1136,45 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   rc = check_r0(p, 0, p->nfl, p->n, p->n, true);  // every timed step runs at the current index
   if (rc) return rc;
   DeviceGuard g(p->device);
-  // save every state in its flame's adjoint scratch (each at least 2x the state)
-  hipError_t e;
-  for (int f = 0; f < p->nfl; ++f) {
-    const size_t bytes = (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2);
-    e = hipMemcpyAsync(p->hdev[f].A1, p->hdev[f].S, bytes, hipMemcpyDeviceToDevice, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "autotune save");
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipError_t e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  if (e != hipSuccess) {
+    if (ev0) (void)hipEventDestroy(ev0);
+    return hip_fail(e, "autotune events");
   }
-  for (int f = 0; f < p->nfl; ++f)
-    if (!p->w_valid[f]) {
-      rc = rebuild_w(p, f);
-      if (rc) return rc;
-    }
+  // save every state in its flame's adjoint scratch (each at least 2x the state)
+  auto state_bytes = [&](int f) { return (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2); };
+  for (int f = 0; e == hipSuccess && f < p->nfl; ++f)
+    e = hipMemcpyAsync(p->hdev[f].A1, p->hdev[f].S, state_bytes(f), hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    return hip_fail(e, "autotune save");
+  }
   const long long n0 = p->n;
   const int saved_graph = p->graph_steps;
   drop_graph(p);
   p->graph_steps = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-    return fail(FLAME_ERR_HIP, "autotune: hipEventCreate failed");
   int tried = 0;
-  struct Cfg {
-    bool product;
-    int c, r;
-  };
-  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-    Group& gr = p->groups[gi];
-    std::vector<Cfg> cfgs;
-    for (int c : {16, 8})
-      for (int r : {16, 8}) cfgs.push_back(Cfg{false, c, r});
-    if (gr.logn1 >= flame::kMinLogProduct)
-      for (int c : {16, 8})
-        for (int r : {16, 8}) cfgs.push_back(Cfg{true, c, r});
-    float best = 1e30f;
-    Cfg best_cfg{gr.product, gr.col_pts, gr.row_pts};
-    // the default: 16 points per thread, product grid where it exists
-    const Cfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts};
-    float default_ms = 1e30f;
-    auto select = [&](const Cfg& cf) -> int {
-      gr.col_pts = cf.c;
-      gr.row_pts = cf.r;
-      if (gr.product != cf.product) {
-        gr.product = cf.product;
-        return apply_rows(p, (int)gi);
-      }
-      return FLAME_OK;
-    };
-    // two rounds over the configurations, keeping each one's faster time: in
-    // the first round the early configurations run on a GPU that is still
-    // raising its clocks
-    std::vector<float> t_best(cfgs.size(), 1e30f);
-    for (int round = 0; round < 2; ++round) {
-      for (size_t ci = 0; ci < cfgs.size(); ++ci) {
-        const Cfg& cf = cfgs[ci];
-        rc = select(cf);
-        for (int f = gr.first; rc == FLAME_OK && f < gr.first + gr.count; ++f)
-          if (!p->w_valid[f]) rc = rebuild_w(p, f);
-        if (rc) {
-          (void)hipEventDestroy(ev0);
-          (void)hipEventDestroy(ev1);
-          return rc;
-        }
-        // one untimed step, then `steps` timed steps of this group alone
-        for (int s = 0; s <= steps; ++s) {
-          if (s == 1) (void)hipEventRecord(ev0, p->stream);
-          for (int pass = 0; pass < gr.passes(); ++pass) {
-            launch_step_row(p, gr, n0);
-            launch_step_col(p, gr, n0, pass);
-          }
-        }
-        (void)hipEventRecord(ev1, p->stream);
-        e = hipEventSynchronize(ev1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-        if (e != hipSuccess) {
-          (void)hipEventDestroy(ev0);
-          (void)hipEventDestroy(ev1);
-          return hip_fail(e, "autotune timing");
-        }
-        if (round == 0) ++tried;
-        t_best[ci] = std::min(t_best[ci], ms);
-      }
-    }
-    for (size_t ci = 0; ci < cfgs.size(); ++ci) {
-      const Cfg& cf = cfgs[ci];
-      if (t_best[ci] < best) {
-        best = t_best[ci];
-        best_cfg = cf;
-      }
-      if (cf.product == default_cfg.product && cf.c == default_cfg.c && cf.r == default_cfg.r) default_ms = t_best[ci];
-    }
-    // keep the default unless another choice is clearly faster: choices
-    // within timing noise of each other would otherwise flip between runs
-    if (best > kAutotuneMargin * default_ms) best_cfg = default_cfg;
-    rc = select(best_cfg);
-    if (rc) {
-      (void)hipEventDestroy(ev0);
-      (void)hipEventDestroy(ev1);
-      return rc;
-    }
-  }
-  if (saved_graph > 0 && p->groups.size() > 1) rc = autotune_jointly(p, steps, n0, ev0, ev1);
+  for (int f = 0; rc == FLAME_OK && f < p->nfl; ++f)
+    if (!p->w_valid[f]) rc = rebuild_w(p, f);
+  for (size_t gi = 0; rc == FLAME_OK && gi < p->groups.size(); ++gi)
+    rc = autotune_alone(p, gi, steps, n0, ev0, ev1, &tried);
+  if (rc == FLAME_OK && saved_graph > 0 && p->groups.size() > 1) rc = autotune_jointly(p, steps, n0, ev0, ev1);
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
-  if (rc) {
-    p->graph_steps = saved_graph;
-    return rc;
-  }
+  // restore every state and the step index, after a failed trial too
   for (int f = 0; f < p->nfl; ++f) {
-    const size_t bytes = (size_t)(p->descs[f].n2 / 4) * (p->descs[f].n1 / 2) * sizeof(float2);
-    e = hipMemcpyAsync(p->hdev[f].S, p->hdev[f].A1, bytes, hipMemcpyDeviceToDevice, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "autotune restore");
+    e = hipMemcpyAsync(p->hdev[f].S, p->hdev[f].A1, state_bytes(f), hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess && rc == FLAME_OK) rc = hip_fail(e, "autotune restore");
     p->w_valid[f] = 0;
   }
   p->n = n0;
   p->graph_steps = saved_graph;
+  if (rc) return rc;
   if (n_configs_tried) *n_configs_tried = tried;
-  return last_launch("autotune launch");
+  return FLAME_OK;
 }
 
 int flame_set_graph_steps(flame_plan p, int32_t steps) {
