@@ -50,10 +50,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, pts, rows):
+def measured_traffic(kernel, workload, pts, rows, streaming=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources and lists the same variant of the
-    kernel (points per thread, product-grid rows); else None."""
+    kernel (points per thread, product-grid rows, store kind); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -62,7 +62,7 @@ def measured_traffic(kernel, workload, pts, rows):
     if rec.get("source_digest") != source_digest():
         return None
     for v in rec.get("variants", []):
-        if v.get("points_per_thread") == pts and v.get("rows") == rows:
+        if v.get("points_per_thread") == pts and v.get("rows") == rows and v.get("streaming", False) == streaming:
             return v.get("hbm_bytes_per_launch")
     return None
 
@@ -250,8 +250,8 @@ def heun_leg(w, half, steps, graph_steps, diag_every, euler_ms):
     return {
         "integrator": "integrating-factor Heun (2 row + 2 column kernels per step)",
         "steps": steps, "graph_steps": graph_steps, "points_per_thread": {"col": pts[0], "row": pts[1]},
-        "product_rows": rows, "ms_per_step": ms, "point_steps_per_s": w.points / (ms * 1e-3),
-        "over_euler": ms / euler_ms, "step_bytes": step_bytes,
+        "product_rows": rows, "streaming_stores": sim.streaming_stores(w.n1, w.n2), "ms_per_step": ms,
+        "point_steps_per_s": w.points / (ms * 1e-3), "over_euler": ms / euler_ms, "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms_per_launch": {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")},
     }
@@ -343,7 +343,7 @@ def ensemble_leg(steps, graph_steps):
     ens.autotune(steps=10)  # per grid group, then jointly for the groups' concurrent graph branches
     grids = ((128, 256), (256, 512), (512, 1024))
     tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) + ["product" if ens.product_grid(n1, n2) else "n1"]
-             for n1, n2 in grids}
+             + ["streaming" if ens.streaming_stores(n1, n2) else "plain"] for n1, n2 in grids}
     nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2, 3 * w.n1 // 4 if ens.product_grid(w.n1, w.n2) else w.n1).values())
                  for w in members)
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
@@ -382,6 +382,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch every step directly (no hipGraph replays)")
     ap.add_argument("--grid", choices=("product", "n1"),
                     help="form the quadratic term on 3*N1/4 rows or on N1 rows (default: autotuned)")
+    ap.add_argument("--stores", choices=("plain", "streaming"),
+                    help="store kind of the step's intermediates Q and W (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-flame ensemble leg (0 skips it)")
     ap.add_argument("--forcing-steps", type=int, default=200,
@@ -440,15 +442,18 @@ def main():
 
     # points per thread of the step kernels chosen by the library's autotuner
     sim.set_spectrum(half)
-    if args.pts or args.grid:
+    if args.pts or args.grid or args.stores:
         if args.grid:
             sim.set_product_grid(w.n1, w.n2, args.grid == "product")
         if args.pts:
             sim.set_points_per_thread(w.n1, w.n2, *args.pts)
+        if args.stores:
+            sim.set_streaming_stores(w.n1, w.n2, args.stores == "streaming")
     else:
         sim.autotune(steps=20)
     pts = sim.points_per_thread(w.n1, w.n2)
     rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
+    streaming = sim.streaming_stores(w.n1, w.n2)
 
     # steps between diagnostics run as one hipGraph replay
     graph_steps = 0 if args.no_graph else args.diag_every
@@ -485,7 +490,7 @@ def main():
     per_launch = {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")}
     dom = max(per_launch, key=per_launch.get)
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1], rows)
+    traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1], rows, streaming)
     result = {
         "metric": "flame point-steps/s fwd & adjoint, FP32 vs FP64 oracle at 1e-5; % HBM roofline",
         "value": w.points * args.steps / (ms * 1e-3),
@@ -502,7 +507,7 @@ def main():
         "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
                    "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}",
                    "points_per_thread": {"col": pts[0], "row": pts[1]}, "product_rows": rows,
-                   "graph_steps": graph_steps},
+                   "streaming_stores": streaming, "graph_steps": graph_steps},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom}_kernel",

@@ -242,15 +242,30 @@ int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t
 int flame_set_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);
 int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* enabled);
 
+/* Store kind of the step's intermediates for the flames of grid n1 x n2:
+ * enable = 1 makes the row kernel write Q, and the column kernel write Wp and
+ * Wm, with non-temporal stores (the lines are not kept in L2 for reuse); 0,
+ * the default, uses plain stores. The arithmetic and the results are the same
+ * either way, bit for bit. Non-temporal stores shorten the kernel that writes
+ * and lengthen the one that reads next, which then misses in the caches more
+ * often; which way the step gains depends on the grid and on what runs beside
+ * it, so flame_autotune measures both. The state, the diagnostics and the
+ * adjoint use plain stores. Errors: FLAME_ERR_INVALID_ARG if no flame of the
+ * plan has that grid (or a null output pointer). Setting discards the step
+ * graph (it is rebuilt at the next graph step). */
+int flame_set_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);
+int flame_get_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t* enabled);
+
 /* Choose the step kernels of each grid group by timing. For every group of
  * equal grids, each configuration runs one untimed and `steps` timed steps of
  * that group (HIP events on the plan's stream), twice in two rounds over all
  * configurations (the faster time counts), and the fastest is kept if
  * it runs in at most 98 % of the default's time (16 points per thread, on
- * the product grid where n1 >= 128), else the default, so that choices within
- * timing noise of each other do not change from run to run. The
- * configurations are (col_pts, row_pts) in {16, 8}^2 on the N1-row grid
- * and, for n1 >= 128, on the product grid. When graphs are in use
+ * the product grid where n1 >= 128, plain stores), else the default, so that
+ * choices within timing noise of each other do not change from run to run.
+ * The configurations are (col_pts, row_pts) in {16, 8}^2 on the N1-row grid
+ * and, for n1 >= 128, on the product grid, each with plain and with
+ * non-temporal stores (flame_set_streaming_stores). When graphs are in use
  * (flame_set_graph_steps > 0) and the plan has several groups, whose chains
  * run concurrently in a replay, the choices are then refined jointly:
  * coordinate descent over the groups, each trial running `steps` steps of

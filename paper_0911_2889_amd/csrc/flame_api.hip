@@ -157,13 +157,15 @@ struct Group {
   int logn1, logn2, first, count, tiles, rpairs;
   int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
   bool product = false;                        // step on the 3N1/4-row product grid
+  bool streaming = false;                      // non-temporal stores of Q and W in the step
   bool forced = false;                         // some flame of the group has a forcing bound
   int integrator = 0;                          // 0: IF-Euler (one pass per step); 1: IF-Heun (two passes)
   int passes() const { return integrator == 1 ? 2 : 1; }
   // the column kernel's variant in pass 0 or 1 of a step
   int col_var(int pass) const {
-    if (integrator == 1) return pass == 0 ? flame::VAR_HEUN_P : flame::VAR_HEUN_C;
-    return forced ? flame::VAR_EULER_F : flame::VAR_EULER;
+    const int nt = streaming ? flame::VAR_NT : 0;
+    if (integrator == 1) return (pass == 0 ? flame::VAR_HEUN_P : flame::VAR_HEUN_C) | nt;
+    return (forced ? flame::VAR_EULER_F : flame::VAR_EULER) | nt;
   }
   int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
   int rgroups() const { return (rows() / 2 + rpairs - 1) / rpairs; }
@@ -354,7 +356,7 @@ int apply_rows(flame_plan p, int gi) {
 void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                      hipStream_t st = nullptr) {
   flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups(), gr.count, st ? st : p->stream, p->ddev + gr.first, n,
-                    nullptr, nullptr, gr.row_pts, e0, e1);
+                    nullptr, nullptr, gr.row_pts, e0, e1, gr.streaming);
 }
 
 void launch_step_col(flame_plan p, const Group& gr, long long n, int pass, hipEvent_t e0 = nullptr,
@@ -390,7 +392,7 @@ int build_graph(flame_plan p) {
   // one pass of group gi at step offset s: row node, then column node, chained after the group's last node
   auto add_pass = [&](size_t gi, int s, int pass) -> int {
     const Group& gr = p->groups[gi];
-    const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts);
+    const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts, gr.streaming);
     const flame::KernelLaunch ck =
         gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts, gr.col_var(pass))
                    : flame::col_step_kernel(gr.logn1, gr.col_pts, gr.col_var(pass));
@@ -963,6 +965,35 @@ int flame_get_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t* enable
   return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
 }
 
+int flame_set_streaming_stores(flame_plan p, int32_t n1, int32_t n2, int32_t enable) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  bool found = false;
+  for (Group& gr : p->groups) {
+    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
+      gr.streaming = enable != 0;
+      found = true;
+    }
+  }
+  if (!found) return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+  DeviceGuard g(p->device);
+  drop_graph(p);
+  return FLAME_OK;
+}
+
+int flame_get_streaming_stores(flame_plan p, int32_t n1, int32_t n2, int32_t* enabled) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!enabled) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  for (const Group& gr : p->groups) {
+    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
+      *enabled = gr.streaming ? 1 : 0;
+      return FLAME_OK;
+    }
+  }
+  return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
+}
+
 // A configuration replaces the default only if it runs in at most this
 // fraction of the default's time.
 constexpr float kAutotuneMargin = 0.98f;
@@ -970,16 +1001,19 @@ constexpr float kAutotuneMargin = 0.98f;
 struct TuneCfg {
   bool product;
   int c, r;
-  bool operator==(const TuneCfg& o) const { return product == o.product && c == o.c && r == o.r; }
+  bool nt;
+  bool operator==(const TuneCfg& o) const { return product == o.product && c == o.c && r == o.r && nt == o.nt; }
 };
 
 static std::vector<TuneCfg> tune_cfgs(const Group& gr) {
   std::vector<TuneCfg> cfgs;
-  for (int c : {16, 8})
-    for (int r : {16, 8}) cfgs.push_back(TuneCfg{false, c, r});
-  if (gr.logn1 >= flame::kMinLogProduct)
+  for (bool nt : {false, true}) {
     for (int c : {16, 8})
-      for (int r : {16, 8}) cfgs.push_back(TuneCfg{true, c, r});
+      for (int r : {16, 8}) cfgs.push_back(TuneCfg{false, c, r, nt});
+    if (gr.logn1 >= flame::kMinLogProduct)
+      for (int c : {16, 8})
+        for (int r : {16, 8}) cfgs.push_back(TuneCfg{true, c, r, nt});
+  }
   return cfgs;
 }
 
@@ -987,6 +1021,7 @@ static int tune_select(flame_plan p, size_t gi, const TuneCfg& cf) {
   Group& gr = p->groups[gi];
   gr.col_pts = cf.c;
   gr.row_pts = cf.r;
+  gr.streaming = cf.nt;
   if (gr.product != cf.product) {
     gr.product = cf.product;
     return apply_rows(p, (int)gi);
@@ -1050,7 +1085,7 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
     bool improved = false;
     for (size_t gi = 0; rc == FLAME_OK && gi < ng; ++gi) {
       const Group& gr = p->groups[gi];
-      const TuneCfg cur{gr.product, gr.col_pts, gr.row_pts};
+      const TuneCfg cur{gr.product, gr.col_pts, gr.row_pts, gr.streaming};
       TuneCfg keep = cur;
       for (const TuneCfg& cf : tune_cfgs(gr)) {
         if (cf == cur) continue;
@@ -1086,13 +1121,13 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
 // (keeping each one's faster time: in the first round the early
 // configurations run on a GPU that is still raising its clocks), then select
 // the fastest unless the default (16 points per thread, product grid where it
-// exists) is within kAutotuneMargin of it, so that choices within timing noise
-// of each other do not flip between runs.
+// exists, plain stores) is within kAutotuneMargin of it, so that choices
+// within timing noise of each other do not flip between runs.
 static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipEvent_t ev0, hipEvent_t ev1,
                           int* tried) {
   const Group& gr = p->groups[gi];
   const std::vector<TuneCfg> cfgs = tune_cfgs(gr);
-  const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts};
+  const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts, false};
   std::vector<float> t_best(cfgs.size(), 1e30f);
   for (int round = 0; round < 2; ++round) {
     for (size_t ci = 0; ci < cfgs.size(); ++ci) {

@@ -148,6 +148,9 @@ enum ColMode : int { COL_STEP = 0, COL_FIRST = 1, COL_PROJECT = 2, COL_SYNTH = 3
 //   VAR_HEUN_P: predictor Phi* = E (Phi~^n + dt (f~ - c_n N(Phi~^n))) -> S2;
 //   VAR_HEUN_C: corrector Phi~^{n+1} = (Phi* + E Phi~^n + dt (f~ - c_{n+1} N(Phi*))) / 2 -> S.
 enum StepVar : int { VAR_EULER = 0, VAR_EULER_F = 1, VAR_HEUN_P = 2, VAR_HEUN_C = 3 };
+// Or-ed into a StepVar: the column kernel writes W with non-temporal stores
+// (the row kernel's Q stores take the same choice through its NT argument).
+constexpr int VAR_NT = 4;
 enum RowMode : int { ROW_STEP = 0, ROW_FORWARD = 1, ROW_SYNTH = 2, ROW_DIAG = 3 };
 // Adjoint column kernel: ADJ_A forms mu = E lambda and the column transforms
 // of mu and of the state's packed gradient; ADJ_C / SEED_C form the

@@ -30,9 +30,11 @@
 
 namespace flame {
 
-template <int LOGN1, int MODE, int PTS = ff::kPts, int VAR = VAR_EULER>
+template <int LOGN1, int MODE, int PTS = ff::kPts, int SV = VAR_EULER>
 __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  constexpr int VAR = SV & ~VAR_NT;
+  constexpr bool NT = MODE == COL_STEP && (SV & VAR_NT) != 0;
   if (nbase) n += *nbase;  // graph replays read the step index from device memory
   using S = ff::Shape<LOGN1, PTS>;
   constexpr int G = S::G, T = ColCfg<LOGN1, PTS>::T, N1 = S::N;
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < PTS; ++i) st(Wpc + w_index(t + G * i, m, f.m), v[i]);
+      for (int i = 0; i < PTS; ++i) st_nt<NT>(Wpc + w_index(t + G * i, m, f.m), v[i]);
     }
     // Z- column for k2 = -m: conj(IFFT_k1((i kappa1 + kappa2) Phi~))
 #pragma unroll
@@ -181,12 +183,12 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
-      for (int i = 0; i < PTS; ++i) st(Wmc + w_index(t + G * i, m, f.m), ff::cconj(v[i]));
+      for (int i = 0; i < PTS; ++i) st_nt<NT>(Wmc + w_index(t + G * i, m, f.m), ff::cconj(v[i]));
     }
   }
 }
 
-template <int LOGN2, int MODE, int PTS = ff::kPts>
+template <int LOGN2, int MODE, int PTS = ff::kPts, bool NT = false>
 __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(RowCfg<LOGN2, PTS>::WPE)))
     row_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase,
                const float* __restrict__ phys_in, float* __restrict__ phys_out) {
@@ -319,8 +321,8 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       const float2 ym = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
       const float2 qa = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
       const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
-      st(Q + tiled(ja, k, n1, ts), qa);
-      st(Q + tiled(jb, k, n1, ts), qb);
+      st_nt<NT>(Q + tiled(ja, k, n1, ts), qa);
+      st_nt<NT>(Q + tiled(jb, k, n1, ts), qb);
     }
   }
 }
@@ -333,10 +335,12 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
 // {4, 5} except position 4*N6, which is k1 = -(K1 + 1)) go through LDS back
 // to the natural map t + G*i (the k2 = 0 column symmetrised on the way), the
 // state is stored from that map, and the two inverse transforms start there.
-template <int LOGN1, int MODE, int PTS = 16, int VAR = VAR_EULER>
+template <int LOGN1, int MODE, int PTS = 16, int SV = VAR_EULER>
 __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     colp_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  constexpr int VAR = SV & ~VAR_NT;
+  constexpr bool NT = MODE == COL_STEP && (SV & VAR_NT) != 0;
   static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
   if (nbase) n += *nbase;
   using Cfg = ColCfgP<LOGN1, PTS>;
@@ -470,9 +474,9 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
           for (int r = 0; r < 6; ++r) {
             const int j1 = j + r * N6;
             if (pass == 0)
-              st(Wpc + w_index(j1, m, f.m), o[it * 6 + r]);
+              st_nt<NT>(Wpc + w_index(j1, m, f.m), o[it * 6 + r]);
             else
-              st(Wmc + w_index(j1, m, f.m), ff::cconj(o[it * 6 + r]));
+              st_nt<NT>(Wmc + w_index(j1, m, f.m), ff::cconj(o[it * 6 + r]));
           }
         }
       }
@@ -484,9 +488,11 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
 // per thread over 2G threads, then the Wp and Wm inverse transforms side by
 // side, 16 points per thread, G threads each. Same results as colp_kernel up
 // to rounding. Every barrier is reached by every thread.
-template <int LOGN1, int MODE, int VAR = VAR_EULER>
+template <int LOGN1, int MODE, int SV = VAR_EULER>
 __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdgpu_waves_per_eu(3)))
     colq_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
+  constexpr int VAR = SV & ~VAR_NT;
+  constexpr bool NT = MODE == COL_STEP && (SV & VAR_NT) != 0;
   static_assert(MODE == COL_STEP || MODE == COL_FIRST, "step modes only");
   if (nbase) n += *nbase;
   using Cfg = ColCfgQ<LOGN1>;
@@ -617,7 +623,7 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
       if (j < N6) {
 #pragma unroll
         for (int r = 0; r < 6; ++r)
-          st(dst + w_index(j + r * N6, m, f.m), make_float2(o[it * 6 + r].x, cs * o[it * 6 + r].y));
+          st_nt<NT>(dst + w_index(j + r * N6, m, f.m), make_float2(o[it * 6 + r].x, cs * o[it * 6 + r].y));
       }
     }
   }
@@ -757,6 +763,10 @@ struct ColTable {
       case VAR_EULER_F: return step_kernel_v<VAR_EULER_F>(pts);
       case VAR_HEUN_P: return step_kernel_v<VAR_HEUN_P>(pts);
       case VAR_HEUN_C: return step_kernel_v<VAR_HEUN_C>(pts);
+      case VAR_NT | VAR_EULER: return step_kernel_v<VAR_NT | VAR_EULER>(pts);
+      case VAR_NT | VAR_EULER_F: return step_kernel_v<VAR_NT | VAR_EULER_F>(pts);
+      case VAR_NT | VAR_HEUN_P: return step_kernel_v<VAR_NT | VAR_HEUN_P>(pts);
+      case VAR_NT | VAR_HEUN_C: return step_kernel_v<VAR_NT | VAR_HEUN_C>(pts);
       default: return step_kernel_v<VAR_EULER>(pts);
     }
   }
@@ -781,13 +791,15 @@ struct RowTable {
       default: hipLaunchKernelGGL((row_kernel<LOGN, ROW_DIAG>), grid, dim3(th), lds, st, fl, n, nb, in, out); break;
     }
   }
-  static KernelLaunch step_kernel(int pts) {
+  template <bool NT>
+  static KernelLaunch step_kernel_nt(int pts) {
     if (pts == 8)
-      return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8>), RowCfg<LOGN, 8>::THREADS,
+      return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8, NT>), RowCfg<LOGN, 8>::THREADS,
                           RowCfg<LOGN, 8>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP>), RowCfg<LOGN>::THREADS,
-                        RowCfg<LOGN>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, ff::kPts, NT>),
+                        RowCfg<LOGN>::THREADS, RowCfg<LOGN>::LDS_BYTES};
   }
+  static KernelLaunch step_kernel(int pts, bool nt) { return nt ? step_kernel_nt<true>(pts) : step_kernel_nt<false>(pts); }
 };
 
 template <int LOGN>
@@ -816,6 +828,10 @@ struct ColPTable {
       case VAR_EULER_F: return pick<VAR_EULER_F>(mode, pts);
       case VAR_HEUN_P: return pick<VAR_HEUN_P>(mode, pts);
       case VAR_HEUN_C: return pick<VAR_HEUN_C>(mode, pts);
+      case VAR_NT | VAR_EULER: return pick<VAR_NT | VAR_EULER>(mode, pts);
+      case VAR_NT | VAR_EULER_F: return pick<VAR_NT | VAR_EULER_F>(mode, pts);
+      case VAR_NT | VAR_HEUN_P: return pick<VAR_NT | VAR_HEUN_P>(mode, pts);
+      case VAR_NT | VAR_HEUN_C: return pick<VAR_NT | VAR_HEUN_C>(mode, pts);
       default: return pick<VAR_EULER>(mode, pts);
     }
   }
@@ -873,9 +889,9 @@ void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const F
 }
 
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
-                const float* in, float* out, int pts, hipEvent_t ev_start, hipEvent_t ev_stop) {
-  if (mode == ROW_STEP && (pts != ff::kPts || ev_start || ev_stop)) {
-    const KernelLaunch kl = row_step_kernel(logn2, pts);
+                const float* in, float* out, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt) {
+  if (mode == ROW_STEP && (pts != ff::kPts || nt || ev_start || ev_stop)) {
+    const KernelLaunch kl = row_step_kernel(logn2, pts, nt);
     const long long* nb = nullptr;
     void* args[] = {&fl, &n, &nb, &in, &out};
     if (ev_start || ev_stop)
@@ -944,9 +960,9 @@ KernelLaunch col_step_kernel(int logn1, int pts, int var) {
   return out;
 }
 
-KernelLaunch row_step_kernel(int logn2, int pts) {
+KernelLaunch row_step_kernel(int logn2, int pts, bool nt) {
   KernelLaunch out{nullptr, 0, 0};
-  dispatch_info<RowTable, kMinLog>(logn2, &out, pts);
+  dispatch_info<RowTable, kMinLog>(logn2, &out, pts, nt);
   return out;
 }
 

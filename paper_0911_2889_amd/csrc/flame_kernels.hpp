@@ -17,9 +17,10 @@ struct KernelLaunch {
 
 // The step kernels for a transform length (arguments: fls, n, nbase, src / in, out).
 // var (StepVar): the column kernel's integrator stage and whether it reads
-// the flames' forcing spectra (flames without one are stepped unforced).
+// the flames' forcing spectra (flames without one are stepped unforced), or-ed
+// with VAR_NT for non-temporal W stores; nt: non-temporal Q stores.
 KernelLaunch col_step_kernel(int logn1, int pts, int var = VAR_EULER);
-KernelLaunch row_step_kernel(int logn2, int pts);
+KernelLaunch row_step_kernel(int logn2, int pts, bool nt = false);
 void launch_set_step(hipStream_t st, long long* counter, long long value);
 // Largest dynamic LDS (bytes per workgroup) any kernel of an N1 x N2 flame
 // asks for (row, column, product-grid and adjoint kernels, every variant).
@@ -53,7 +54,7 @@ void launch_adjp_col(int logn1, int mode, int tiles, hipStream_t st, const Flame
 // Row kernel over `groups` groups of B row pairs for `nfl` flames of one size.
 void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const FlameDev* fl, long long n,
                 const float* in, float* out, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
-                hipEvent_t ev_stop = nullptr);
+                hipEvent_t ev_stop = nullptr, bool nt = false);
 
 void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half);
 void launch_get_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, void* half);

@@ -54,6 +54,17 @@ __device__ __forceinline__ void st(gf2* p, float2 a) {
   v.y = a.y;
   *p = v;
 }
+// Store that is non-temporal if NT (the line is not kept in L2 for reuse).
+template <bool NT>
+__device__ __forceinline__ void st_nt(gf2* p, float2 a) {
+  v2f v;
+  v.x = a.x;
+  v.y = a.y;
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 // Twiddle source of a kernel: cached in registers for the kernel's lifetime
 // (each kernel runs two or three transforms of one length), or read from the

@@ -23,7 +23,8 @@ EXPORTS = (
     "flame_step_index", "flame_step", "flame_diagnostics", "flame_adjoint_step", "flame_area_gradient",
     "flame_synthesize", "flame_timing_begin", "flame_timing_end", "flame_set_graph_steps",
     "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
-    "flame_get_product_grid", "flame_set_r0_table", "flame_set_forcing", "flame_autotune", "flame_destroy",
+    "flame_get_product_grid", "flame_set_streaming_stores", "flame_get_streaming_stores", "flame_set_r0_table",
+    "flame_set_forcing", "flame_autotune", "flame_destroy",
     "flame_last_error",
 )
 
@@ -85,6 +86,8 @@ def load():
         "flame_set_r0_table": [P, i32, ctypes.c_void_p, ctypes.c_int64],
         "flame_set_forcing": [P, i32, ctypes.c_void_p],
         "flame_get_product_grid": [P, i32, i32, ctypes.POINTER(i32)],
+        "flame_set_streaming_stores": [P, i32, i32, i32],
+        "flame_get_streaming_stores": [P, i32, i32, ctypes.POINTER(i32)],
         "flame_timing_begin": [P],
         "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "flame_destroy": [P],

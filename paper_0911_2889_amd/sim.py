@@ -208,9 +208,20 @@ class FlameEnsemble:
         native.check(self.lib.flame_get_product_grid(self.plan, int(n1), int(n2), ctypes.byref(v)))
         return bool(v.value)
 
+    def set_streaming_stores(self, n1, n2, enable):
+        """Write the step's intermediates Q and W of the flames of grid n1 x n2 with
+        non-temporal stores (True) or plain ones (False); the results are identical."""
+        native.check(self.lib.flame_set_streaming_stores(self.plan, int(n1), int(n2), int(bool(enable))))
+
+    def streaming_stores(self, n1, n2):
+        v = ctypes.c_int32()
+        native.check(self.lib.flame_get_streaming_stores(self.plan, int(n1), int(n2), ctypes.byref(v)))
+        return bool(v.value)
+
     def autotune(self, steps=20):
-        """Time every points-per-thread choice per grid group and keep the fastest;
-        the simulation state is unchanged. Returns the number of timed configurations."""
+        """Time every grid, points-per-thread and store-kind choice per grid group and
+        keep the fastest; the simulation state is unchanged. Returns the number of
+        timed configurations."""
         tried = ctypes.c_int32()
         native.check(self.lib.flame_autotune(self.plan, int(steps), ctypes.byref(tried)))
         return tried.value

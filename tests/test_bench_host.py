@@ -46,11 +46,14 @@ def test_power_law_fit_recovers_exponent_and_origin():
 def test_traffic_lookup_needs_digest_and_variant(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     rec = {"kernel": "col_kernel", "workload": "w", "source_digest": bench.source_digest(),
-           "variants": [{"points_per_thread": 16, "rows": 1536, "hbm_bytes_per_launch": 1.5e7}]}
+           "variants": [{"points_per_thread": 16, "rows": 1536, "hbm_bytes_per_launch": 1.5e7},
+                        {"points_per_thread": 16, "rows": 1536, "streaming": True, "hbm_bytes_per_launch": 1.6e7}]}
     (tmp_path / "profiles" / "col_kernel_w_traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_digest", lambda: rec["source_digest"])
     assert bench.measured_traffic("col", "w", 16, 1536) == 1.5e7
+    assert bench.measured_traffic("col", "w", 16, 1536, streaming=True) == 1.6e7
+    assert bench.measured_traffic("col", "w", 8, 1536, streaming=True) is None
     assert bench.measured_traffic("col", "w", 8, 1536) is None
     assert bench.measured_traffic("col", "w", 16, 2048) is None
     assert bench.measured_traffic("row", "w", 16, 1536) is None

@@ -117,8 +117,9 @@ def test_autotune_keeps_the_state_and_agrees_with_the_oracle(graph_steps):
     ens.step(5)
     before = [ens.spectrum(f).cpu().numpy() for f in range(len(members))]
     # per group: four points-per-thread choices on N1 rows, and four more on
-    # the product grid where n1 >= 128 (256x512 and 128x64)
-    assert ens.autotune(steps=4) == 4 + 8 + 8
+    # the product grid where n1 >= 128 (256x512 and 128x64), each with plain
+    # and with non-temporal stores
+    assert ens.autotune(steps=4) == 8 + 16 + 16
     assert ens.step_index == 5
     for f in range(len(members)):
         assert np.array_equal(ens.spectrum(f).cpu().numpy(), before[f])
