@@ -62,9 +62,12 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   float2 sv[KEEP];
 
   if constexpr (MODE == COL_STEP || MODE == COL_PROJECT) {
+    // The loads carry no condition, so that no branch between them makes one
+    // wait for another: a column past the grid reads its padded slots of Q and
+    // column 0 of the state (its results are never stored).
+    const int ms = live ? m : 0;
 #pragma unroll
-    for (int i = 0; i < PTS; ++i)
-      v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = ld(Qc + (t + G * i) * TQ);
     // the old state is loaded before the transform so its latency is hidden
     // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
     constexpr bool FORCED = MODE == COL_STEP && VAR != VAR_EULER;
@@ -73,9 +76,9 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int kk = 0; kk < KEEP; ++kk) {
       const int i = kept_reg<PTS>(kk);
       const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
-      old[kk] = (MODE == COL_STEP && live) ? ld(Sc + k1) : make_float2(0.f, 0.f);
-      frc[kk] = (FORCED && live) ? forcing_at(f, m, k1) : make_float2(0.f, 0.f);
-      prd[kk] = (MODE == COL_STEP && VAR == VAR_HEUN_C && live) ? ld(Pc + k1) : make_float2(0.f, 0.f);
+      old[kk] = MODE == COL_STEP ? ld(Sc + (size_t)(ms - m) * f.h1 + k1) : make_float2(0.f, 0.f);
+      frc[kk] = FORCED ? forcing_at(f, ms, k1) : make_float2(0.f, 0.f);
+      prd[kk] = MODE == COL_STEP && VAR == VAR_HEUN_C ? ld(Pc + (size_t)(ms - m) * f.h1 + k1) : make_float2(0.f, 0.f);
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
@@ -220,24 +223,30 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       const double r = r0_at(f, n);
       return (float)(1.0 / (r * r));
     }();
-    // both rows' inputs come in one 16-byte load per register (w_index layout)
+    // both rows' inputs come in one 16-byte load per register (w_index layout).
+    // The loads carry no condition, so that no branch between them makes one
+    // wait for another: a pair past the grid reads pair 0 (its results are
+    // never stored), and the one position past the box (k2 = -N2/4, at t = 0)
+    // is read in bounds and zeroed.
     float2 vr[2][PTS];
-    const int pbase4 = (pair >> 1) * mcols, poff = (pair & 1) << 1;
+    const int pl = live ? pair : 0;
+    const int pbase4 = (pl >> 1) * mcols, poff = (pl & 1) << 1;
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
       const int idx = t + G * i;
       float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
-      if (live) {
-        if (i < LOW) {
-          ld_pair(Wp + (((pbase4 + idx) << 2) + poff), a, b);
-        } else if (i >= HIGH) {
-          const int mm = N2 - idx;
-          if (mm < mcols) ld_pair(Wm + (((pbase4 + mm) << 2) + poff), a, b);
-        }
+      if (i < LOW) {
+        ld_pair(Wp + (((pbase4 + idx) << 2) + poff), a, b);
+      } else if (i >= HIGH) {
+        const int mm = N2 - idx;  // < mcols except at i = HIGH, t = 0
+        ld_pair(Wm + (((pbase4 + (i > HIGH || t > 0 ? mm : 0)) << 2) + poff), a, b);
       }
       vr[0][i] = a;
       vr[1][i] = b;
     }
+    // zeroed once every load is issued (a select, not a branch that would wait on the load)
+    vr[0][HIGH] = t > 0 ? vr[0][HIGH] : make_float2(0.f, 0.f);
+    vr[1][HIGH] = t > 0 ? vr[1][HIGH] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       fft<LOGN2, true, kPrune>(vr[half], t, my, B, tw2);
@@ -367,9 +376,16 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
 
   float2 sv[PTS];  // spectrum at natural positions t + G*i, zero outside the box
   if constexpr (MODE == COL_STEP) {
+    // The loads carry no condition, so that no branch between them makes one
+    // wait for another. A column past the grid reads its padded slots of Q
+    // and column 0 of the state (its results are never stored); a slot that
+    // holds no kept mode reads k1 = 0, and its value is not used.
+    const int ms = live ? m : 0;
+    gf2* const Sl = Sc + (size_t)(ms - m) * f.h1;
+    gf2* const Pl = Pc + (size_t)(ms - m) * f.h1;
     float2 v[PTS];
 #pragma unroll
-    for (int i = 0; i < PTS; ++i) v[i] = live ? ld(Qc + (t + G * i) * TQ) : make_float2(0.f, 0.f);
+    for (int i = 0; i < PTS; ++i) v[i] = ld(Qc + (t + G * i) * TQ);
     // the old state in the radix-6 output map, loaded before the transform
     constexpr int KR[4] = {0, 1, 4, 5};
     // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
@@ -381,10 +397,10 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int pos = j + KR[q] * N6;
-        const bool ok = live && j < N6 && kept_at(pos);
-        old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
-        frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
-        prd[it][q] = VAR == VAR_HEUN_C && ok ? ld(Pc + k1_of(pos)) : make_float2(0.f, 0.f);
+        const int k1 = j < N6 && kept_at(pos) ? k1_of(pos) : 0;
+        old[it][q] = ld(Sl + k1);
+        frc[it][q] = FORCED ? forcing_at(f, ms, k1) : make_float2(0.f, 0.f);
+        prd[it][q] = VAR == VAR_HEUN_C ? ld(Pl + k1) : make_float2(0.f, 0.f);
       }
     }
     float2 o[IT * 6];
@@ -520,10 +536,16 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
   float2 sv[16];  // spectrum at natural positions t16 + G16*i
   if constexpr (MODE == COL_STEP) {
     {
+      // unconditional loads, as in colp_kernel: a column past the grid reads
+      // its padded slots of Q and column 0 of the state; a slot that holds no
+      // kept mode reads k1 = 0, and its value is not used
+      const int ms = live ? m : 0;
+      gf2* const Sl = Sc + (size_t)(ms - m) * f.h1;
+      gf2* const Pl = Pc + (size_t)(ms - m) * f.h1;
       const auto twf = KernelTw6<LOGP, 8>::make(f.tw6_8, t8);
       float2 v[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = live ? ld(Qc + (t8 + G8 * i) * TQ) : make_float2(0.f, 0.f);
+      for (int i = 0; i < 8; ++i) v[i] = ld(Qc + (t8 + G8 * i) * TQ);
       constexpr int KR[4] = {0, 1, 4, 5};
       // frc: the forcing (not in VAR_EULER); prd: Heun's predictor (VAR_HEUN_C)
       constexpr bool FORCED = VAR != VAR_EULER;
@@ -534,10 +556,10 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int pos = j + KR[q] * N6;
-          const bool ok = live && j < N6 && kept_at(pos);
-          old[it][q] = ok ? ld(Sc + k1_of(pos)) : make_float2(0.f, 0.f);
-          frc[it][q] = FORCED && ok ? forcing_at(f, m, k1_of(pos)) : make_float2(0.f, 0.f);
-          prd[it][q] = VAR == VAR_HEUN_C && ok ? ld(Pc + k1_of(pos)) : make_float2(0.f, 0.f);
+          const int k1 = j < N6 && kept_at(pos) ? k1_of(pos) : 0;
+          old[it][q] = ld(Sl + k1);
+          frc[it][q] = FORCED ? forcing_at(f, ms, k1) : make_float2(0.f, 0.f);
+          prd[it][q] = VAR == VAR_HEUN_C ? ld(Pl + k1) : make_float2(0.f, 0.f);
         }
       }
       float2 o[ITF * 6];
