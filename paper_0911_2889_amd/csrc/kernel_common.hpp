@@ -175,10 +175,14 @@ __device__ __forceinline__ float growth_factor(float kk2, const StepScalars& sc,
 // f~_k of Eq. (1) for stored column m and wavenumber k1, read from the bound
 // forcing spectrum (state layout), or zero when none is bound. The update
 // takes dt f~ inside the propagator, like the quadratic term:
-// E (Phi~ + dt (f~ - c N)). m must be a stored column.
+// E (Phi~ + dt (f~ - c N)). m must be a stored column. The load is issued
+// either way (from the state, which has the same layout, when no forcing is
+// bound) and the value selected afterwards: a branch around it would make
+// the compiler wait for every load issued before it.
 __device__ __forceinline__ float2 forcing_at(const FlameDev& f, int m, int k1) {
-  if (!f.F) return make_float2(0.f, 0.f);
-  return ld((const gf2*)f.F + (size_t)m * f.h1 + (f.n1 >> 2) + k1);
+  const float2* base = f.F ? f.F : f.S;
+  const float2 v = ld((const gf2*)base + (size_t)m * f.h1 + (f.n1 >> 2) + k1);
+  return f.F ? v : make_float2(0.f, 0.f);
 }
 
 // Offset of element (j1, m) of Wp from f.Wp, and of Wm from f.Wm (Wp and Wm
