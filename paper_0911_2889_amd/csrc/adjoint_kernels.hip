@@ -62,6 +62,10 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   constexpr int TQ = ColCfg<LOGN1>::TQ, QS = ColCfg<LOGN1>::QS;
   const size_t tile_base = ((((size_t)m >> QS) * N1) << QS) + (m & (TQ - 1));  // column m of Q, A1, A2
   const size_t col = (size_t)m * f.h1 + N1 / 4;  // element k1 of column m at col + k1
+  // loads carry no condition (a branch around a load makes the compiler wait
+  // for every load issued before it): a column past the grid reads column 0
+  // of the spectra and its padded slots of A1 and A2, and is never stored
+  const size_t coll = (size_t)(live ? m : 0) * f.h1 + N1 / 4;
   const auto tw1 = KernelTw<LOGN1>::make(f.tw1, t);
   const float kap2 = f.s2 * (float)m;
 
@@ -72,7 +76,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
-      lam[kk] = live ? ld(glob(const_cast<float2*>(lam_in)) + col + k1) : make_float2(0.f, 0.f);
+      lam[kk] = ld(glob(const_cast<float2*>(lam_in)) + coll + k1);
     }
   }
 
@@ -83,7 +87,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int kk = 0; kk < 8; ++kk) {
       const int i = kept_reg<ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
-      sv[kk] = live ? ld(glob(const_cast<float2*>(state)) + col + k1) : make_float2(0.f, 0.f);
+      sv[kk] = ld(glob(const_cast<float2*>(state)) + coll + k1);
     }
     // M = column synthesis of mu = E lambda  -> Q
 #pragma unroll
@@ -126,7 +130,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int pass = 0; pass < 2; ++pass) {
       gf2* srcp = glob(pass == 0 ? f.A1 : f.A2) + tile_base;
 #pragma unroll
-      for (int i = 0; i < ff::kPts; ++i) v[i] = live ? ld(srcp + (t + G * i) * TQ) : make_float2(0.f, 0.f);
+      for (int i = 0; i < ff::kPts; ++i) v[i] = ld(srcp + (t + G * i) * TQ);
       fft<LOGN1, false>(v, t, my, T, tw1);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg<ff::kPts>(kk)];
@@ -206,6 +210,9 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
   float2* my = lds + c;
   const size_t tile_base = ((((size_t)m >> QS) * M1) << QS) + (m & (TQ - 1));  // column m of Q, A1, A2
   const size_t col = (size_t)m * f.h1 + N1 / 4;  // element k1 of column m at col + k1
+  // loads carry no condition, as in adj_col_kernel; a slot that holds no kept
+  // mode reads k1 = 0 and its value is replaced or unused
+  const size_t coll = (size_t)(live ? m : 0) * f.h1 + N1 / 4;
   const auto tw = KernelTw6<LOGP, 16>::make(f.tw6, t);
   const float kap2 = f.s2 * (float)m;
   const StepScalars sc = step_scalars(f, n, M1);
@@ -218,10 +225,17 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int pos = t + G * i;
-      const bool ok = live && kept_at(pos);
-      const float2 lam = ok ? ld(lin + col + k1_of(pos)) : make_float2(0.f, 0.f);
-      sv[i] = ok ? ld(glob(const_cast<float2*>(state)) + col + k1_of(pos)) : make_float2(0.f, 0.f);
-      v[i] = ok ? ff::cscale(lam, efactor(f, sc, k1_of(pos), kap2)) : make_float2(0.f, 0.f);  // mu = E lambda
+      const int k1 = kept_at(pos) ? k1_of(pos) : 0;
+      v[i] = ld(lin + coll + k1);
+      sv[i] = ld(glob(const_cast<float2*>(state)) + coll + k1);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {  // mu = E lambda, zero outside the box (selects, after every load)
+      const int pos = t + G * i;
+      const bool kept = kept_at(pos);
+      const float e = efactor(f, sc, kept ? k1_of(pos) : 0, kap2);
+      v[i] = kept ? ff::cscale(v[i], e) : make_float2(0.f, 0.f);
+      sv[i] = kept ? sv[i] : make_float2(0.f, 0.f);
     }
     float2 o[IT * 6];
     fft6<LOGP, true, 16>(v, o, t, my, T, tw);  // M = column synthesis of mu -> Q
@@ -268,7 +282,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int pos = j + KR[q] * N6;
-        lam[it][q] = live && j < N6 && kept_at(pos) ? ld(lin + col + k1_of(pos)) : make_float2(0.f, 0.f);
+        lam[it][q] = ld(lin + coll + (j < N6 && kept_at(pos) ? k1_of(pos) : 0));
       }
     }
     // forward column transforms of the row transforms of w1 and i kappa2 w2
@@ -276,10 +290,10 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
     {
       float2 v[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = live ? ld(glob(f.A1) + tile_base + (size_t)(t + G * i) * TQ) : make_float2(0.f, 0.f);
+      for (int i = 0; i < 16; ++i) v[i] = ld(glob(f.A1) + tile_base + (size_t)(t + G * i) * TQ);
       fft6<LOGP, false, 16>(v, ou, t, my, T, tw);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = live ? ld(glob(f.A2) + tile_base + (size_t)(t + G * i) * TQ) : make_float2(0.f, 0.f);
+      for (int i = 0; i < 16; ++i) v[i] = ld(glob(f.A2) + tile_base + (size_t)(t + G * i) * TQ);
       fft6<LOGP, false, 16>(v, ow, t, my, T, tw);
     }
 #pragma unroll
@@ -340,6 +354,9 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
   const int n1 = MODE == ROW_ADJ ? f.rows : f.n1, ts = f.tshift, mcols = f.m;
   const bool live = pair < n1 / 2;
   const int ja = 2 * pair, jb = 2 * pair + 1;
+  // rows the loads read: a pair past the grid reads pair 0 (never stored), so
+  // that no load sits behind a branch
+  const int jal = live ? ja : 0, jbl = live ? jb : 1;
   float2* my = lds + p;
   const auto tw2 = KernelTw<LOGN2>::make(f.tw2, t);
   gf2* const Wp = glob(f.Wp);
@@ -360,20 +377,18 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
     for (int i = 0; i < ff::kPts; ++i) {
       const int idx = t + G * i;
       float2 val = make_float2(0.f, 0.f);
-      if (live) {
-        if (i < 4) {
-          const float2 a = ld(Q + tiled(ja, idx, n1, ts)), b = ld(Q + tiled(jb, idx, n1, ts));
-          val = make_float2(a.x - b.y, a.y + b.x);
-        } else if (i >= 12) {
-          const int mm = N2 - idx;
-          if (mm < mcols) {
-            const float2 a = ld(Q + tiled(ja, mm, n1, ts)), b = ld(Q + tiled(jb, mm, n1, ts));
-            val = make_float2(a.x + b.y, -a.y + b.x);
-          }
-        }
+      if (i < 4) {
+        const float2 a = ld(Q + tiled(jal, idx, n1, ts)), b = ld(Q + tiled(jbl, idx, n1, ts));
+        val = make_float2(a.x - b.y, a.y + b.x);
+      } else if (i >= 12) {
+        const int mm = N2 - idx;  // < mcols except at i = 12, t = 0
+        const int mc = i > 12 || t > 0 ? mm : 0;
+        const float2 a = ld(Q + tiled(jal, mc, n1, ts)), b = ld(Q + tiled(jbl, mc, n1, ts));
+        val = make_float2(a.x + b.y, -a.y + b.x);
       }
       y[i] = val;
     }
+    y[12] = t > 0 ? y[12] : make_float2(0.f, 0.f);  // a select once every load is issued
     fft<LOGN2, true, kPrune>(y, t, my, B, tw2);
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) {
@@ -384,22 +399,21 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
 
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
-    const int row = half ? jb : ja;
+    const int row = half ? jbl : jal;
     float2 v[ff::kPts];
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) {
       const int idx = t + G * i;
       float2 val = make_float2(0.f, 0.f);
-      if (live) {
-        if (i < 4) {
-          val = ld(Wp + w_index(row, idx, mcols));
-        } else if (i >= 12) {
-          const int mm = N2 - idx;
-          if (mm < mcols) val = ld(Wm + w_index(row, mm, mcols));
-        }
+      if (i < 4) {
+        val = ld(Wp + w_index(row, idx, mcols));
+      } else if (i >= 12) {
+        const int mm = N2 - idx;  // < mcols except at i = 12, t = 0
+        val = ld(Wm + w_index(row, i > 12 || t > 0 ? mm : 0, mcols));
       }
       v[i] = val;
     }
+    v[12] = t > 0 ? v[12] : make_float2(0.f, 0.f);  // a select once every load is issued
     fft<LOGN2, true, kPrune>(v, t, my, B, tw2);  // z = g1 + i g2 on the row
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) {
