@@ -66,6 +66,8 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     // wait for another: a column past the grid reads its padded slots of Q and
     // column 0 of the state (its results are never stored).
     const int ms = live ? m : 0;
+    gf2* const Sl = glob(f.S) + (size_t)ms * f.h1 + N1 / 4;
+    gf2* const Pl = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)ms * f.h1 + N1 / 4;
 #pragma unroll
     for (int i = 0; i < PTS; ++i) v[i] = ld(Qc + (t + G * i) * TQ);
     // the old state is loaded before the transform so its latency is hidden
@@ -76,9 +78,9 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int kk = 0; kk < KEEP; ++kk) {
       const int i = kept_reg<PTS>(kk);
       const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
-      old[kk] = MODE == COL_STEP ? ld(Sc + (size_t)(ms - m) * f.h1 + k1) : make_float2(0.f, 0.f);
+      old[kk] = MODE == COL_STEP ? ld(Sl + k1) : make_float2(0.f, 0.f);
       frc[kk] = FORCED ? forcing_at(f, ms, k1) : make_float2(0.f, 0.f);
-      prd[kk] = MODE == COL_STEP && VAR == VAR_HEUN_C ? ld(Pc + (size_t)(ms - m) * f.h1 + k1) : make_float2(0.f, 0.f);
+      prd[kk] = MODE == COL_STEP && VAR == VAR_HEUN_C ? ld(Pl + k1) : make_float2(0.f, 0.f);
     }
     fft<LOGN1, false>(v, t, my, T, tw1);
     StepScalars sc{};
@@ -381,8 +383,8 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     // and column 0 of the state (its results are never stored); a slot that
     // holds no kept mode reads k1 = 0, and its value is not used.
     const int ms = live ? m : 0;
-    gf2* const Sl = Sc + (size_t)(ms - m) * f.h1;
-    gf2* const Pl = Pc + (size_t)(ms - m) * f.h1;
+    gf2* const Sl = glob(f.S) + (size_t)ms * f.h1 + N1 / 4;
+    gf2* const Pl = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)ms * f.h1 + N1 / 4;
     float2 v[PTS];
 #pragma unroll
     for (int i = 0; i < PTS; ++i) v[i] = ld(Qc + (t + G * i) * TQ);
@@ -540,8 +542,8 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
       // its padded slots of Q and column 0 of the state; a slot that holds no
       // kept mode reads k1 = 0, and its value is not used
       const int ms = live ? m : 0;
-      gf2* const Sl = Sc + (size_t)(ms - m) * f.h1;
-      gf2* const Pl = Pc + (size_t)(ms - m) * f.h1;
+      gf2* const Sl = glob(f.S) + (size_t)ms * f.h1 + N1 / 4;
+      gf2* const Pl = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)ms * f.h1 + N1 / 4;
       const auto twf = KernelTw6<LOGP, 8>::make(f.tw6_8, t8);
       float2 v[8];
 #pragma unroll
