@@ -99,3 +99,21 @@ def test_streaming_is_set_per_grid_in_an_ensemble(flame):
         ens.set_streaming_stores(128, 128, True)
     with pytest.raises(flame.native.FlameError):
         ens.streaming_stores(512, 512)
+
+
+def test_switching_the_store_kind_between_graph_replays(flame):
+    """The setting discards the step graph; the next replay is rebuilt with the
+    other kernels and continues the same trajectory bit for bit."""
+    n1, n2 = 256, 512
+    w = workload(n1, n2, seed=123)
+    half = synth.workload_spectrum(w)
+    ref = run(flame, w, half, 20, False, graph_steps=5)
+    sim = flame.FlameSim(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
+    sim.set_graph_steps(5)
+    sim.set_spectrum(half)
+    for k, streaming in enumerate((False, True, False, True)):
+        sim.set_streaming_stores(n1, n2, streaming)
+        sim.step(5)
+        assert sim.step_index == 5 * (k + 1)
+    torch.cuda.synchronize()
+    assert np.array_equal(sim.spectrum().cpu().numpy(), ref)
