@@ -340,7 +340,9 @@ def ensemble_leg(steps, graph_steps):
     for f, h in enumerate(halves):
         ens.set_spectrum(h, flame=f)
     ens.set_graph_steps(graph_steps)
-    ens.autotune(steps=10)  # per grid group, then jointly for the groups' concurrent graph branches
+    # per grid group, then jointly for the groups' concurrent graph branches; with 10 timed
+    # steps per trial the choices followed timing noise and the replayed step was ~3 % slower
+    ens.autotune(steps=30)
     grids = ((128, 256), (256, 512), (512, 1024))
     tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) + ["product" if ens.product_grid(n1, n2) else "n1"]
              + ["streaming" if ens.streaming_stores(n1, n2) else "plain"] for n1, n2 in grids}
