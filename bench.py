@@ -209,7 +209,7 @@ def heun_leg(w, half, steps, graph_steps, diag_every, euler_ms):
 
     sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt, integrator=1)
     sim.set_spectrum(half)
-    sim.autotune(steps=10)
+    sim.autotune(steps=20)
     pts = sim.points_per_thread(w.n1, w.n2)
     rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
     diag = torch.zeros(4, dtype=torch.float64, device=sim.device)
