@@ -369,6 +369,26 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
     return (float)(1.0 / (r * r));
   }();
 
+  // both rows' packed-gradient spectra, loaded before m's transform so that
+  // their latency is hidden behind it
+  float2 wv[2][ff::kPts];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int row = half ? jbl : jal;
+#pragma unroll
+    for (int i = 0; i < ff::kPts; ++i) {
+      const int idx = t + G * i;
+      float2 val = make_float2(0.f, 0.f);
+      if (i < 4) {
+        val = ld(Wp + w_index(row, idx, mcols));
+      } else if (i >= 12) {
+        const int mm = N2 - idx;  // < mcols except at i = 12, t = 0
+        val = ld(Wm + w_index(row, i > 12 || t > 0 ? mm : 0, mcols));
+      }
+      wv[half][i] = val;
+    }
+  }
+
   float ma[ff::kPts], mb[ff::kPts];
   if constexpr (MODE == ROW_ADJ) {
     // m for both rows: Y = X_a + i X_b, X(k2) = M(k2), X(-k2) = conj(M(k2))
@@ -399,21 +419,11 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
 
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
-    const int row = half ? jbl : jal;
+    const int row = half ? jb : ja;  // the row this half stores (live pairs only)
     float2 v[ff::kPts];
 #pragma unroll
-    for (int i = 0; i < ff::kPts; ++i) {
-      const int idx = t + G * i;
-      float2 val = make_float2(0.f, 0.f);
-      if (i < 4) {
-        val = ld(Wp + w_index(row, idx, mcols));
-      } else if (i >= 12) {
-        const int mm = N2 - idx;  // < mcols except at i = 12, t = 0
-        val = ld(Wm + w_index(row, i > 12 || t > 0 ? mm : 0, mcols));
-      }
-      v[i] = val;
-    }
-    v[12] = t > 0 ? v[12] : make_float2(0.f, 0.f);  // a select once every load is issued
+    for (int i = 0; i < ff::kPts; ++i) v[i] = wv[half][i];
+    v[12] = t > 0 ? v[12] : make_float2(0.f, 0.f);  // the position past the box
     fft<LOGN2, true, kPrune>(v, t, my, B, tw2);  // z = g1 + i g2 on the row
 #pragma unroll
     for (int i = 0; i < ff::kPts; ++i) {
