@@ -1,7 +1,7 @@
 """Integral diagnostics of the flame state in FP64 (oracle; test infrastructure only).
 
-Section 3 (averages paragraph) says the code computes "a variety of averages"
-without listing them; Section 2 plots the averaged flame velocity <Phi_t>.
+Section 3 (averages paragraph) mentions averages of the solution without
+listing them; Section 2 plots the averaged flame velocity <Phi_t>.
 The readings used here:
 
 * mean radius  r_bar = r0(t) + Re Phi~_0  (r = r0 + Phi, Section 2);

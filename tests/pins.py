@@ -315,13 +315,21 @@ def pin_area_gradient_fd(n1=16, n2=24, seed=6, t0=2.0, amp=0.6):
     return worst
 
 
-def pin_trajectory_gradient_fd(n1=16, n2=24, seed=7, t0=3.0, dt=0.2, nsteps=10, amp=0.5):
+def pin_trajectory_gradient_fd(n1=16, n2=24, seed=7, t0=3.0, dt=0.2, nsteps=10, amp=0.5, n_start=0,
+                               checkpoint_every=None):
     """Gradient of J(Phi^T) with respect to a projected physical initial field
-    against central differences along random grid directions."""
+    against central differences along random grid directions.
+
+    The trajectory starts at step index n_start (time t0 + n_start dt) and
+    ends at n_start + nsteps; with checkpoint_every the gradient goes through
+    the branch that keeps only every checkpoint_every-th state and recomputes
+    each segment. The differences of J are formed from the forward run alone
+    (``run`` and the grid mean of sqrt(1 + x) - 1), so a wrong step index in
+    the recomputation or in the adjoint steps shows up as a mismatch."""
     rng = np.random.default_rng(seed)
     p = oracle.Params(n1, n2, t0=t0, dt=dt)
     phi0 = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, amp), n1, n2))
-    _, lam = oracle.trajectory_gradient(phi0, p, nsteps)
+    _, lam = oracle.trajectory_gradient(phi0, p, nsteps, n_start=n_start, checkpoint_every=checkpoint_every)
     grad_grid = oracle.synthesize(lam).real
     worst = 0.0
     for _ in range(4):
@@ -330,11 +338,55 @@ def pin_trajectory_gradient_fd(n1=16, n2=24, seed=7, t0=3.0, dt=0.2, nsteps=10, 
         eps = 1e-5
 
         def J(x):
-            return oracle.area_excess(oracle.run(x, p, nsteps), p, nsteps)
+            return area_mean(oracle.run(x, p, nsteps, n_start), p, n_start + nsteps)
 
         fd = (J(phi0 + eps * vp) - J(phi0 - eps * vp)) / (2 * eps)
         worst = max(worst, abs(fd - float((grad_grid * v).sum())) / abs(fd))
     return worst
+
+
+def area_mean(full, p, n):
+    """Grid mean of sqrt(1 + x) - 1, x = |grad Phi|^2 / r0(t_n)^2, written out
+    here from the gradient's definition (spectral derivative, then synthesis)
+    and evaluated the plain way; used as the functional of the finite
+    differences, so that they do not rely on the oracle's own J."""
+    k1, k2 = p.kappa()
+    g1 = np.fft.ifft2(1j * k1 * full).real * full.size
+    g2 = np.fft.ifft2(1j * k2 * full).real * full.size
+    rr = p.r0(p.time(n))
+    x = (g1 * g1 + g2 * g2) / (rr * rr)
+    return float((np.sqrt(1.0 + x) - 1.0).mean())
+
+
+def pin_checkpointed_gradient_identical(n1=16, n2=24, seed=9, t0=3.0, dt=0.2, nsteps=7, n_start=4, amp=0.5):
+    """The checkpointed gradient recomputes the same states in the same order
+    as the full-storage one, so every checkpoint spacing must give the same
+    value and coefficients bit for bit (returns the number of spacings that
+    differ, 0 when all agree)."""
+    rng = np.random.default_rng(seed)
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    phi0 = oracle.symmetrise(dict_to_full(random_hermitian(n1, n2, rng, amp), n1, n2))
+    ref_v, ref_l = oracle.trajectory_gradient(phi0, p, nsteps, n_start=n_start)
+    bad = 0
+    for every in (1, 2, 3, nsteps - 1, nsteps, nsteps + 5):
+        v, lam = oracle.trajectory_gradient(phi0, p, nsteps, n_start=n_start, checkpoint_every=every)
+        if not (v == ref_v and np.array_equal(lam, ref_l)):
+            bad += 1
+    return bad
+
+
+def pin_area_excess_series(n1=32, n2=64, k=(2, 3), a=0.5, psi=0.4, n=3):
+    """oracle.area_excess (the J of the adjoint module) against the exact
+    series for a single cosine, and against diagnostics()[2]."""
+    p = oracle.Params(n1, n2, t0=3.0, dt=0.1)
+    coef = {k: 0.5 * a * np.exp(1j * psi), (-k[0], -k[1]): 0.5 * a * np.exp(-1j * psi)}
+    full = dict_to_full(coef, n1, n2)
+    r = 3.0 + n * 0.1
+    b = a * a * (k[0] ** 2 + k[1] ** 2) / (r * r)
+    j = oracle.area_excess(full, p, n)
+    e_series = abs(j - area_series(b)) / area_series(b)
+    e_diag = abs(j - oracle.diagnostics(full, p, n)[2]) / abs(j)
+    return max(e_series, e_diag)
 
 
 def pin_convolution_direct_anisotropic():

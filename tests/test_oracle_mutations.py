@@ -28,7 +28,15 @@ THRESHOLDS = {
     "pin_adjoint_dot_product": 1e-10,
     "pin_trajectory_gradient_fd": 1e-5,
     "pin_forcing_geometric_series": 1e-12,
+    "pin_area_excess_series": 1e-12,
 }
+
+# pins that take arguments: (label, callable, threshold)
+CALL_PINS = [
+    ("pin_trajectory_gradient_fd_checkpointed",
+     lambda: pins.pin_trajectory_gradient_fd(n_start=5, checkpoint_every=3), 1e-6),
+    ("pin_checkpointed_gradient_identical", pins.pin_checkpointed_gradient_identical, 0),
+]
 
 
 def failing_pins():
@@ -37,6 +45,14 @@ def failing_pins():
         try:
             v = getattr(pins, name)()
         except Exception:  # a crash also counts as caught
+            bad.append(name)
+            continue
+        if not np.isfinite(v) or v > tol:
+            bad.append(name)
+    for name, fn, tol in CALL_PINS:
+        try:
+            v = fn()
+        except Exception:
             bad.append(name)
             continue
         if not np.isfinite(v) or v > tol:
@@ -222,12 +238,65 @@ def _heun_propagator_on_corrector(monkeypatch):
     monkeypatch.setattr(om, "step", step)
 
 
+def _checkpoint_recompute_off_by_one(monkeypatch):
+    # each recomputed segment state advanced with the step index one too far
+    def traj(full0, p, nsteps, n_start=0, checkpoint_every=None):
+        every = nsteps if not checkpoint_every else int(checkpoint_every)
+        checkpoints, cur, n = [], om.run(full0, p, 0, n_start), 0
+        while n < nsteps:
+            checkpoints.append((n, cur))
+            k = min(every, nsteps - n)
+            for i in range(k):
+                cur = om.step(cur, p, n_start + n + i)
+            n += k
+        value = oadj.area_excess(cur, p, n_start + nsteps)
+        lam = oadj.area_gradient(cur, p, n_start + nsteps)
+        for n0, saved in reversed(checkpoints):
+            k = min(every, nsteps - n0)
+            states = [saved]
+            for i in range(1, k):
+                states.append(om.step(states[-1], p, n_start + n0 + i))
+            for i in reversed(range(k)):
+                lam = oadj.step_adjoint(states[i], lam, p, n_start + n0 + i)
+        return value, lam
+    monkeypatch.setattr(oracle, "trajectory_gradient", traj)
+    monkeypatch.setattr(oadj, "trajectory_gradient", traj)
+
+
+def _adjoint_steps_from_zero_index(monkeypatch):
+    # the adjoint steps of a trajectory that starts at n_start taken at 0 .. nsteps-1
+    orig = oadj.trajectory_gradient
+
+    def traj(full0, p, nsteps, n_start=0, checkpoint_every=None):
+        saved = oadj.step_adjoint
+
+        def adj(state_n, lam_next, pp, n):
+            return saved(state_n, lam_next, pp, n - n_start)
+        monkeypatch.setattr(oadj, "step_adjoint", adj)
+        try:
+            return orig(full0, p, nsteps, n_start, checkpoint_every)
+        finally:
+            monkeypatch.setattr(oadj, "step_adjoint", saved)
+    monkeypatch.setattr(oracle, "trajectory_gradient", traj)
+
+
+def _area_excess_plain_mean_of_x(monkeypatch):
+    # J taken as half the mean of x (the small-slope limit) in the adjoint module
+    def area(full, p, n):
+        rr = p.r0(p.time(n))
+        g1, g2 = odiag.gradient_fields(full, p)
+        return float(((g1 * g1 + g2 * g2) / (rr * rr)).mean() / 2)
+    monkeypatch.setattr(oracle, "area_excess", area)
+    monkeypatch.setattr(oadj, "area_excess", area)
+
+
 MUTATIONS = [
     _flip_nonlinear_sign, _drop_instability_term, _euler_radius_integral, _missing_half_in_c,
     _transposed_kappa, _cross_term_dropped, _aliased_grid, _nonlinear_at_new_time,
     _velocity_without_half, _area_without_sqrt, _adjoint_missing_factor_two,
     _adjoint_without_decay, _forcing_outside_integrating_factor, _heun_corrector_at_old_time,
-    _heun_propagator_on_corrector,
+    _heun_propagator_on_corrector, _checkpoint_recompute_off_by_one, _adjoint_steps_from_zero_index,
+    _area_excess_plain_mean_of_x,
 ]
 
 

@@ -146,6 +146,22 @@ def test_trajectory_gradient_matches_finite_differences():
     assert pins.pin_trajectory_gradient_fd() < 1e-6
 
 
+@pytest.mark.parametrize("every", [1, 3, 10])
+def test_checkpointed_trajectory_gradient_matches_finite_differences(every):
+    # the checkpoint branch (recomputed segments) from a nonzero step index
+    assert pins.pin_trajectory_gradient_fd(n_start=5, checkpoint_every=every) < 1e-6
+
+
+def test_checkpointed_gradient_is_bitwise_the_full_storage_one():
+    assert pins.pin_checkpointed_gradient_identical() == 0
+    assert pins.pin_checkpointed_gradient_identical(n1=13, n2=20, seed=11, nsteps=5, n_start=0) == 0
+
+
+def test_area_excess_matches_series_and_diagnostics():
+    assert pins.pin_area_excess_series() < 1e-12
+    assert pins.pin_area_excess_series(k=(0, 5), a=0.3, n=0) < 1e-12
+
+
 def test_gradient_is_band_limited():
     rng = np.random.default_rng(3)
     n1, n2 = 16, 24
