@@ -293,6 +293,33 @@ int flame_set_graph_steps(flame_plan plan, int32_t steps);
  * waiting for the plan's stream. */
 int flame_destroy(flame_plan plan);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory
+ * or build a plan (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Advances one flame described by `desc`
+ * (host) by nsteps >= 0 integrating-factor Euler steps of Eq. (1), with
+ * the kernel sequence flame_step runs on a fresh plan in its default
+ * configuration (product grid for n1 >= 128, 16 points per thread, plain
+ * stores, direct launches): the column transforms of the state, then a row
+ * and a column kernel per step. `state` (dev, flame_state_bytes, 16-byte
+ * aligned, the state layout above) holds the state at step index n
+ * (time t0 + n dt) and is updated in place; the work is queued on
+ * hip_stream (a hipStream_t, 0 for the null stream) of the current device.
+ * Only r0_law = 0 and integrator = 0 are accepted (FLAME_ERR_INVALID_ARG
+ * otherwise).
+ *
+ * The workspace (the intermediates W and Q, the twiddle tables, the flame
+ * descriptor) is a static device array of FLAME_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends; the call
+ * allocates nothing. A grid whose workspace exceeds it (2048 x 4096 fits)
+ * fails with FLAME_ERR_WORKSPACE_TOO_SMALL before anything is queued. Every
+ * call on one GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (other streams or host threads) race, while calls
+ * queued in order on one stream do not. Nothing in the array needs to start
+ * at zero: each call writes every location that a kernel reads for a stored
+ * result. */
+#define FLAME_NOALLOC_SCRATCH_BYTES (48u * 1024u * 1024u)
+int flame_step_noalloc(const flame_desc* desc, void* state, int64_t n, int32_t nsteps, void* hip_stream);
+
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* flame_last_error(void);
 

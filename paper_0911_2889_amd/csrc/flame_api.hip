@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -437,11 +438,195 @@ int build_graph(flame_plan p) {
   return FLAME_OK;
 }
 
+// ------------------------------------------------------------------------
+// Workspace of flame_step_noalloc: a static device array (one copy per GPU,
+// held until the process ends). Host code never passes the array's name to
+// a kernel or copy: its device address comes from hipGetSymbolAddress, once
+// per device, and is kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)FLAME_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FLAME_ERR_INVALID_ARG, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(FLAME_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FLAME_OK;
+}
+
+// One twiddle table: passes q = 1 .. npass-1 of a Stockham plan hold
+// exp(-2 pi i r k / (ns_q R_q)) at off_q + (r - 1) ns_q + k, 0 < r < R_q,
+// k < ns_q (the layout of ff::build_twiddles and, with the radix-6 pass as
+// its last pass, of ff::build_twiddles6). Built on the device in double
+// precision and rounded once, like the host tables of flame_init.
+struct TwSpec {
+  float2* out;
+  int npass;
+  int ns[6], radix[6], off[6];
+  int count;
+};
+constexpr int kMaxTwTables = 4;
+struct TwSpecs {
+  TwSpec t[kMaxTwTables];
+  int ntab;
+};
+
+__global__ void noalloc_setup_kernel(flame::FlameDev fd, flame::FlameDev* dst, TwSpecs specs) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *dst = fd;
+  for (int ti = 0; ti < specs.ntab; ++ti) {
+    const TwSpec& s = specs.t[ti];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s.count; i += gridDim.x * blockDim.x) {
+      int q = 1;
+      while (q + 1 < s.npass && i >= s.off[q + 1]) ++q;
+      const int rel = i - s.off[q];
+      const int ns = s.ns[q], r = s.radix[q];
+      const int m = rel / ns + 1, k = rel % ns;
+      const long long e = (long long)k * m % (long long)(ns * r);
+      const double ang = -2.0 * M_PI * double(e) / (double(ns) * double(r));
+      s.out[i] = make_float2((float)cos(ang), (float)sin(ang));
+    }
+  }
+}
+
+TwSpec tw_spec_pow2(float2* out, int logn, int pts) {
+  const ff::PassPlan p = ff::make_pass_plan(logn, pts);
+  TwSpec s{};
+  s.out = out;
+  s.npass = p.npass;
+  for (int q = 0; q < p.npass; ++q) {
+    s.ns[q] = p.ns[q];
+    s.radix[q] = p.radix[q];
+    s.off[q] = p.tw_off[q];
+  }
+  s.count = p.tw_size;
+  return s;
+}
+
+// Shape6 of length 6 * 2^logp: the power-of-two passes, then the radix-6 pass.
+TwSpec tw_spec_six(float2* out, int logp, int pts) {
+  TwSpec s = tw_spec_pow2(out, logp, pts);
+  const int q = s.npass;
+  s.ns[q] = 1 << logp;
+  s.radix[q] = 6;
+  s.off[q] = s.count;
+  s.npass = q + 1;
+  s.count += 5 * (1 << logp);
+  return s;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* flame_last_error(void) { return g_last_error.c_str(); }
+
+int flame_step_noalloc(const flame_desc* desc, void* state, int64_t n, int32_t nsteps, void* hip_stream) {
+  Sizes s{};
+  int rc = check_desc(desc, &s);
+  if (rc) return rc;
+  if (!state) return fail(FLAME_ERR_INVALID_ARG, "null state pointer");
+  if (reinterpret_cast<uintptr_t>(state) % 16) return fail(FLAME_ERR_INVALID_ARG, "state must be 16-byte aligned");
+  if (desc->r0_law != 0) return fail(FLAME_ERR_INVALID_ARG, "flame_step_noalloc takes r0(t) = t only (r0_law = 0)");
+  if (desc->integrator != 0)
+    return fail(FLAME_ERR_INVALID_ARG, "flame_step_noalloc takes integrating-factor Euler only (integrator = 0)");
+  if (nsteps < 0) return fail(FLAME_ERR_INVALID_ARG, "nsteps must be >= 0");
+  // the default configuration of flame_init: the product grid for n1 >= 128,
+  // 16 points per thread, plain stores, direct launches
+  const bool product = s.logn1 >= flame::kMinLogProduct;
+  const int rows = product ? 3 * desc->n1 / 4 : desc->n1;
+  const size_t cols = (size_t)std::max(s.tiles * s.tcol, (desc->n2 / 4 + s.tq - 1) / s.tq * s.tq);
+  const size_t wq = cols * (size_t)rows;  // elements of Q, and of each of Wp and Wm
+  TwSpecs specs{};
+  size_t off = align_up(sizeof(flame::FlameDev));
+  size_t tw_off[kMaxTwTables] = {};
+  auto add_table = [&](const TwSpec& t) {
+    tw_off[specs.ntab] = off;
+    specs.t[specs.ntab++] = t;
+    off = align_up(off + (size_t)std::max(t.count, 1) * sizeof(float2));
+  };
+  // pointers are filled in once the scratch address is known
+  if (product) add_table(tw_spec_six(nullptr, s.logn1 - 3, ff::kPts));
+  else add_table(tw_spec_pow2(nullptr, s.logn1, ff::kPts));
+  add_table(tw_spec_pow2(nullptr, s.logn2, ff::kPts));
+  const size_t off_w = off;
+  off = align_up(off + 2 * wq * sizeof(float2));
+  const size_t off_q = off;
+  off = align_up(off + wq * sizeof(float2));
+  if (off > kScratchBytes)
+    return fail(FLAME_ERR_WORKSPACE_TOO_SMALL,
+                "grid %d x %d needs %zu bytes of scratch; the static scratch of flame_step_noalloc holds %zu",
+                desc->n1, desc->n2, off, kScratchBytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int max_lds = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  const int need_lds = flame::lds_bytes_needed(s.logn1, s.logn2);
+  if (need_lds > max_lds)
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d needs %d bytes of LDS per workgroup, the device has %d",
+                desc->n1, desc->n2, need_lds, max_lds);
+  void* base_v = nullptr;
+  rc = scratch_address(dev, &base_v);
+  if (rc) return rc;
+  char* base = static_cast<char*>(base_v);
+  for (int i = 0; i < specs.ntab; ++i) specs.t[i].out = reinterpret_cast<float2*>(base + tw_off[i]);
+  flame::FlameDev fd;
+  std::memset(&fd, 0, sizeof fd);
+  fd.S = static_cast<float2*>(state);
+  fd.Wp = reinterpret_cast<float2*>(base + off_w);
+  fd.Wm = fd.Wp + wq;
+  fd.Q = reinterpret_cast<float2*>(base + off_q);
+  const float2* tw_col = specs.t[0].out;
+  const float2* tw_row = specs.t[1].out;
+  fd.tw1 = product ? nullptr : tw_col;
+  fd.tw6 = product ? tw_col : nullptr;
+  fd.tw2 = tw_row;
+  fd.n1 = desc->n1;
+  fd.n2 = desc->n2;
+  fd.m = desc->n2 / 4;
+  fd.h1 = desc->n1 / 2;
+  fd.tshift = ilog2_exact(s.tq);
+  fd.rows = rows;
+  const bool lit = desc->axis_scale[0] == 0.0;
+  fd.s1 = (float)(lit ? desc->theta_pi : desc->axis_scale[0]);
+  fd.s2 = (float)(lit ? desc->theta_pi : desc->axis_scale[1]);
+  fd.gamma = (float)desc->gamma;
+  fd.t0 = desc->t0;
+  fd.dt = desc->dt;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  flame::FlameDev* dfl = reinterpret_cast<flame::FlameDev*>(base);
+  // the flame table and the twiddles; every other scratch location a kernel
+  // reads for a stored result is written earlier in this call
+  hipLaunchKernelGGL(noalloc_setup_kernel, dim3(32), dim3(256), 0, st, fd, dfl, specs);
+  rc = last_launch("flame_step_noalloc setup launch");
+  if (rc) return rc;
+  // W from the state, then the steps (the kernel sequence of flame_step)
+  if (product)
+    flame::launch_colp(s.logn1, flame::COL_FIRST, s.tiles, 1, st, dfl, n, nullptr, ff::kPts);
+  else
+    flame::launch_col(s.logn1, flame::COL_FIRST, s.tiles, 1, st, dfl, n);
+  const int rgroups = (rows / 2 + s.rpairs - 1) / s.rpairs;
+  for (int i = 0; i < nsteps; ++i) {
+    flame::launch_row(s.logn2, flame::ROW_STEP, rgroups, 1, st, dfl, n + i, nullptr, nullptr, ff::kPts);
+    if (product)
+      flame::launch_colp(s.logn1, flame::COL_STEP, s.tiles, 1, st, dfl, n + i, nullptr, ff::kPts);
+    else
+      flame::launch_col(s.logn1, flame::COL_STEP, s.tiles, 1, st, dfl, n + i, nullptr, ff::kPts);
+  }
+  return last_launch("flame_step_noalloc launch");
+}
+
 
 int flame_state_bytes(const flame_desc* desc, size_t* bytes) {
   if (!bytes) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");

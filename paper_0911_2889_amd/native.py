@@ -24,7 +24,7 @@ EXPORTS = (
     "flame_synthesize", "flame_timing_begin", "flame_timing_end", "flame_set_graph_steps",
     "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
     "flame_get_product_grid", "flame_set_streaming_stores", "flame_get_streaming_stores", "flame_set_r0_table",
-    "flame_set_forcing", "flame_autotune", "flame_destroy",
+    "flame_set_forcing", "flame_autotune", "flame_destroy", "flame_step_noalloc",
     "flame_last_error",
 )
 
@@ -91,6 +91,7 @@ def load():
         "flame_timing_begin": [P],
         "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "flame_destroy": [P],
+        "flame_step_noalloc": [desc_p, P, i64, i32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -82,6 +82,30 @@ def test_null_and_empty_arguments(native):
     assert lib.flame_init(d, 1, None, None, 0, None, ctypes.byref(plan)) == -1
 
 
+def test_noalloc_host_checks_run_before_any_device_call(native):
+    """flame_step_noalloc validates its arguments and the scratch size on the
+    host before it touches a device (these calls return without a GPU)."""
+    lib = native.load()
+    st = ctypes.c_void_p(256)  # never dereferenced: every call below fails its checks first
+    cases = [
+        (native.make_desc(4096, 4096), 1, native.FLAME_ERR_WORKSPACE_TOO_SMALL),
+        (native.make_desc(8192, 8192), 1, native.FLAME_ERR_WORKSPACE_TOO_SMALL),
+        (native.make_desc(64, 128, integrator=1), 1, native.FLAME_ERR_INVALID_ARG),
+        (native.make_desc(64, 128, r0_law=1), 1, native.FLAME_ERR_INVALID_ARG),
+        (native.make_desc(64, 128), -1, native.FLAME_ERR_INVALID_ARG),
+        (native.make_desc(100, 128), 1, native.FLAME_ERR_UNSUPPORTED_SIZE),
+    ]
+    for d, nsteps, code in cases:
+        assert lib.flame_step_noalloc(ctypes.byref(d), st, 0, nsteps, None) == code
+        assert lib.flame_last_error().decode()
+    assert lib.flame_step_noalloc(ctypes.byref(native.make_desc(64, 128)), None, 0, 1, None) == \
+        native.FLAME_ERR_INVALID_ARG
+    assert lib.flame_step_noalloc(ctypes.byref(native.make_desc(64, 128)), ctypes.c_void_p(8), 0, 1, None) == \
+        native.FLAME_ERR_INVALID_ARG
+    assert "scratch" in (lib.flame_step_noalloc(ctypes.byref(native.make_desc(4096, 4096)), st, 0, 1, None) and
+                         lib.flame_last_error().decode())
+
+
 def test_fft_engine_on_host_matches_numpy(tmp_path):
     """Drive the device FFT engine's passes thread by thread on the CPU."""
     exe = tmp_path / "fft_engine_check"
