@@ -220,8 +220,15 @@ int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
 /* Points per thread of the step kernels for the flames of grid n1 x n2: each
  * length-N transform is owned by N/pts threads holding pts points, with
  * radix-pts passes (col_pts for the column kernel, row_pts for the row
- * kernel; 8 or 16, default 16). Results agree to rounding, not bit for bit;
- * the choice trades registers per thread for waves per transform. */
+ * kernel; 8 or 16, default 16). pts = 12 selects the 12-point plan (a
+ * radix-12 pass, then radix 4 and 2) for transforms of 3/4 of the grid on
+ * N/16 threads: col_pts = 12 runs the column transforms of the product grid
+ * (it needs flame_set_product_grid enabled, FLAME_ERR_INVALID_ARG
+ * otherwise), row_pts = 12 forms the quadratic term on 3 N2/4 phi points
+ * instead of N2 (n2 >= 64, FLAME_ERR_UNSUPPORTED_SIZE otherwise); for a
+ * product of two box-limited fields that grid is also alias-free, as the
+ * theta product grid is. Results agree to rounding, not bit for bit; the
+ * choice trades registers per thread for waves per transform. */
 int flame_set_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t col_pts, int32_t row_pts);
 int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t* col_pts, int32_t* row_pts);
 
@@ -238,7 +245,8 @@ int flame_get_points_per_thread(flame_plan plan, int32_t n1, int32_t n2, int32_t
  * threads with 8 points each and whose Wp and Wm transforms run side by
  * side). Diagnostics,
  * state I/O, synthesis and the adjoint always use the N1 x N2 grid. Default:
- * enabled for n1 >= 128. Changing it synchronises the stream. */
+ * enabled for n1 >= 128. Disabling it while col_pts = 12 fails with
+ * FLAME_ERR_INVALID_ARG. Changing it synchronises the stream. */
 int flame_set_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t enable);
 int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* enabled);
 
@@ -263,9 +271,10 @@ int flame_get_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t*
  * it runs in at most 98 % of the default's time (16 points per thread, on
  * the product grid where n1 >= 128, plain stores), else the default, so that
  * choices within timing noise of each other do not change from run to run.
- * The configurations are (col_pts, row_pts) in {16, 8}^2 on the N1-row grid
- * and, for n1 >= 128, on the product grid, each with plain and with
- * non-temporal stores (flame_set_streaming_stores). When graphs are in use
+ * The configurations are (col_pts, row_pts) in {16, 8} x {16, 8, 12} on the
+ * N1-row grid and, for n1 >= 128, {16, 8, 12}^2 on the product grid (row_pts
+ * 12 only where n2 >= 64), each with plain and with non-temporal stores
+ * (flame_set_streaming_stores). When graphs are in use
  * (flame_set_graph_steps > 0) and the plan has several groups, whose chains
  * run concurrently in a replay, the choices are then refined jointly:
  * coordinate descent over the groups, each trial running `steps` steps of

@@ -74,18 +74,18 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
   if constexpr (MODE != SEED_C) {
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg<ff::kPts>(kk);
+      const int i = kept_reg<LOGN1, ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       lam[kk] = ld(glob(const_cast<float2*>(lam_in)) + coll + k1);
     }
   }
 
   if constexpr (MODE == ADJ_A) {
-    const StepScalars sc = step_scalars(f, n, f.n1);
+    const StepScalars sc = step_scalars(f, n, f.n1, f.n2);
     float2 sv[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg<ff::kPts>(kk);
+      const int i = kept_reg<LOGN1, ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       sv[kk] = ld(glob(const_cast<float2*>(state)) + coll + k1);
     }
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg<ff::kPts>(kk);
+      const int i = kept_reg<LOGN1, ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       v[i] = ff::cscale(lam[kk], efactor(f, sc, k1, kap2));
     }
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       for (int i = 0; i < ff::kPts; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
-        const int i = kept_reg<ff::kPts>(kk);
+        const int i = kept_reg<LOGN1, ff::kPts>(kk);
         const float kap1 = f.s1 * (float)(t + G * i - (i >= 12 ? N1 : 0));
         v[i] = make_float2(-kap1 * sv[kk].y + sgn * kap2 * sv[kk].x, kap1 * sv[kk].x + sgn * kap2 * sv[kk].y);
       }
@@ -133,15 +133,15 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       for (int i = 0; i < ff::kPts; ++i) v[i] = ld(srcp + (t + G * i) * TQ);
       fft<LOGN1, false>(v, t, my, T, tw1);
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg<ff::kPts>(kk)];
+      for (int kk = 0; kk < 8; ++kk) (pass == 0 ? u : w)[kk] = v[kept_reg<LOGN1, ff::kPts>(kk)];
     }
     float2 out[8];
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     StepScalars sc{};
-    if constexpr (MODE == ADJ_C) sc = step_scalars(f, n, f.n1);
+    if constexpr (MODE == ADJ_C) sc = step_scalars(f, n, f.n1, f.n2);
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const int i = kept_reg<ff::kPts>(kk);
+      const int i = kept_reg<LOGN1, ff::kPts>(kk);
       const int k1 = t + G * i - (i >= 12 ? N1 : 0);
       const float kap1 = f.s1 * (float)k1;
       // raw divergence i kappa1 U1 + V2 (sums without the 1/P factors)
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
       if (c == 0) {
 #pragma unroll
         for (int kk = 4; kk < 8; ++kk) {
-          const int k1 = t + G * kept_reg<ff::kPts>(kk) - N1;
+          const int k1 = t + G * kept_reg<LOGN1, ff::kPts>(kk) - N1;
           if (k1 > -N1 / 4) out[kk] = ff::cconj(lds[-k1]);
         }
         if (t == 0) out[0].y = 0.f;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(ColCfg<LOGN1>::THREADS) __attribute__((amdgpu_
     if (live) {
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
-        const int i = kept_reg<ff::kPts>(kk);
+        const int i = kept_reg<LOGN1, ff::kPts>(kk);
         const int k1 = t + G * i - (i >= 12 ? N1 : 0);
         st(glob(lam_out) + col + k1, out[kk]);
       }
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, 16>::THREADS))
   const size_t coll = (size_t)(live ? m : 0) * f.h1 + N1 / 4;
   const auto tw = KernelTw6<LOGP, 16>::make(f.tw6, t);
   const float kap2 = f.s2 * (float)m;
-  const StepScalars sc = step_scalars(f, n, M1);
+  const StepScalars sc = step_scalars(f, n, M1, f.n2);
   auto k1_of = [](int p) { return p < M1 / 2 ? p : p - M1; };
   auto kept_at = [](int p) { return p < 2 * N6 || p > 4 * N6; };
   gf2* const lin = glob(const_cast<float2*>(lam_in));

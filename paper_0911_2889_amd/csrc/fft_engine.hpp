@@ -34,11 +34,13 @@ namespace ff {
 
 constexpr int kPts = 16;  // default points per thread
 
+constexpr int kMaxPass = 8;
+
 struct PassPlan {
   int logn, n, g, npass;
-  int radix[5];
-  int ns[5];
-  int tw_off[5];
+  int radix[kMaxPass];
+  int ns[kMaxPass];
+  int tw_off[kMaxPass];
   int tw_size;
 };
 
@@ -61,10 +63,32 @@ constexpr PassPlan make_pass_plan(int logn, int pts = kPts) {
     if (q > 0) off += ns * (p.radix[q] - 1);
     ns *= p.radix[q];
   }
-  for (int q = p.npass; q < 5; ++q) {
+  for (int q = p.npass; q < kMaxPass; ++q) {
     p.radix[q] = 1;
     p.ns[q] = ns;
     p.tw_off[q] = off;
+  }
+  p.tw_size = off;
+  return p;
+}
+
+// Length 12 * 2^e with 12 points per thread: a radix-12 pass, then radix-4
+// passes, and a radix-2 pass last when e is odd (every radix divides 12, so
+// each thread runs 12/R butterflies of a pass on its own registers).
+constexpr PassPlan make_plan12(int e) {
+  PassPlan p{};
+  p.logn = -1;  // not a power of two
+  p.n = 12 << e;
+  p.g = 1 << e;
+  p.npass = 1 + e / 2 + (e & 1);
+  int ns = 1, off = 0;
+  for (int q = 0; q < kMaxPass; ++q) {
+    const int r = q == 0 ? 12 : (q < p.npass ? (q <= e / 2 ? 4 : 2) : 1);
+    p.radix[q] = r;
+    p.ns[q] = ns;
+    p.tw_off[q] = off;
+    if (q > 0 && q < p.npass) off += ns * (r - 1);
+    ns *= r;
   }
   p.tw_size = off;
   return p;
@@ -116,6 +140,36 @@ struct Shape6 {
   static_assert(LOGP >= 4 && LOGP <= 10, "power-of-two part must be 16..1024");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
+
+// Transform of N = 12 * 2^E points with 12 points per thread (make_plan12):
+// G = 2^E threads, thread t holding x[t + G*i], i < 12, like Shape. With
+// N = 3 * 2^q the length-N transform of a product grid (3/4 of a power of
+// two) runs on G = N/12 threads, which makes waves per CU a multiple of four
+// where 16 points per thread would not.
+template <int E>
+struct Shape12 {
+  static constexpr int PTS = 12;
+  static constexpr PassPlan plan = make_plan12(E);
+  static constexpr int N = 12 << E;
+  static constexpr int G = 1 << E;
+  static constexpr int NPASS = plan.npass;
+  static constexpr int NBF = NPASS;
+  static constexpr int LDS = N + N / 16;
+  static constexpr int radix(int p) { return plan.radix[p]; }
+  static constexpr int ns(int p) { return plan.ns[p]; }
+  static constexpr int tw_off(int p) { return plan.tw_off[p]; }
+  static_assert(E >= 2 && E <= 9, "length 48..6144");
+};
+
+// k mod ns for k >= 0 (ns a compile-time constant, not always a power of two)
+template <int NS>
+__host__ __device__ __forceinline__ constexpr int mod_ns(int k) {
+  if constexpr ((NS & (NS - 1)) == 0) {
+    return k & (NS - 1);
+  } else {
+    return (int)((unsigned)k % (unsigned)NS);
+  }
+}
 
 // ---------------------------------------------------------------- complex
 
@@ -319,6 +373,64 @@ __host__ __device__ __forceinline__ void dft6(float2* x) {
   x[5] = b2;
 }
 
+// length-12 DFT as 4 x 3: r = 3 a + b, m = c + 4 d. Length-4 transforms over
+// a for each b, the inner roots w12^(b c), then length-3 transforms over b:
+// X[c + 4 d] = sum_b w3^(b d) w12^(b c) sum_a x[3 a + b] w4^(a c).
+// ZMID: the caller guarantees x[4..7] == 0 (a spectrum kept in the first and
+// last third), which drops the terms that vanish.
+template <bool INV, bool ZMID = false>
+__host__ __device__ __forceinline__ void dft12(float2* x) {
+  constexpr float h = 0.86602540378443864676f;  // sqrt(3)/2 = cos(pi/6)
+  float2 y[3][4];
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    float2 a0 = x[b], a1 = x[3 + b], a2 = x[6 + b], a3 = x[9 + b];
+    if constexpr (ZMID) {
+      // zero inputs: x[4] (a=1,b=1), x[5] (a=1,b=2), x[6] (a=2,b=0), x[7] (a=2,b=1)
+      if (b == 0) {  // a2 == 0
+        const float2 s13 = cadd(a1, a3), d13 = mul_q<INV>(csub(a1, a3));
+        y[b][0] = cadd(a0, s13);
+        y[b][2] = csub(a0, s13);
+        y[b][1] = cadd(a0, d13);
+        y[b][3] = csub(a0, d13);
+      } else if (b == 1) {  // a1 == a2 == 0
+        const float2 qa3 = mul_q<INV>(a3);
+        y[b][0] = cadd(a0, a3);
+        y[b][1] = csub(a0, qa3);
+        y[b][2] = csub(a0, a3);
+        y[b][3] = cadd(a0, qa3);
+      } else {  // a1 == 0
+        const float2 s02 = cadd(a0, a2), d02 = csub(a0, a2), qa3 = mul_q<INV>(a3);
+        y[b][0] = cadd(s02, a3);
+        y[b][2] = csub(s02, a3);
+        y[b][1] = csub(d02, qa3);
+        y[b][3] = cadd(d02, qa3);
+      }
+    } else {
+      dft4<INV>(a0, a1, a2, a3);
+      y[b][0] = a0;
+      y[b][1] = a1;
+      y[b][2] = a2;
+      y[b][3] = a3;
+    }
+  }
+  // inner roots: w12^1 = (h, -+1/2), w12^2 = (1/2, -+h), w12^3 = -+i, w12^4 = (-1/2, -+h), w12^6 = -1
+  y[1][1] = mul_root<INV>(y[1][1], h, 0.5f);
+  y[1][2] = mul_root<INV>(y[1][2], 0.5f, h);
+  y[1][3] = mul_q<INV>(y[1][3]);
+  y[2][1] = mul_root<INV>(y[2][1], 0.5f, h);
+  y[2][2] = mul_root<INV>(y[2][2], -0.5f, h);
+  y[2][3] = make_float2(-y[2][3].x, -y[2][3].y);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float2 p = y[0][c], q = y[1][c], r = y[2][c];
+    dft3<INV>(p, q, r);
+    x[c] = p;
+    x[c + 4] = q;
+    x[c + 8] = r;
+  }
+}
+
 template <int R, bool INV>
 __host__ __device__ __forceinline__ void dft(float2* x) {
   if constexpr (R == 2) {
@@ -327,6 +439,8 @@ __host__ __device__ __forceinline__ void dft(float2* x) {
     dft4<INV>(x[0], x[1], x[2], x[3]);
   } else if constexpr (R == 8) {
     dft8<INV>(x);
+  } else if constexpr (R == 12) {
+    dft12<INV>(x);
   } else {
     static_assert(R == 16, "radix");
     dft16<INV>(x);
@@ -343,7 +457,7 @@ struct GlobalTwS {
   template <int P>
   __host__ __device__ __forceinline__ float2 get(int b, int r) const {
     constexpr int NS = S::ns(P);
-    const int k = (t + b * S::G) & (NS - 1);
+    const int k = mod_ns<NS>(t + b * S::G);
     return tw[S::tw_off(P) + (r - 1) * NS + k];
   }
   // radix-6 pass of a Shape6 transform: round `it`, butterfly j = t + G*it
@@ -405,7 +519,7 @@ struct RegTwS {
         constexpr int R = S::radix(P), NS = S::ns(P), NB = PTS / R;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const int k = (t + b * S::G) & (NS - 1);
+          const int k = mod_ns<NS>(t + b * S::G);
 #pragma unroll
           for (int r = 1; r < R; ++r) w[offset(P) + b * (R - 1) + (r - 1)] = fetch(S::tw_off(P) + (r - 1) * NS + k);
         }
@@ -420,7 +534,7 @@ struct RegTwS {
       return w[offset(P) + b * (S::radix(P) - 1) + (r - 1)];
     } else {
       constexpr int NS = S::ns(P);
-      return fetch(S::tw_off(P) + (r - 1) * NS + ((t + b * S::G) & (NS - 1)));
+      return fetch(S::tw_off(P) + (r - 1) * NS + mod_ns<NS>(t + b * S::G));
     }
   }
 
@@ -440,7 +554,8 @@ struct FftS {
   // into LDS, or, in the last pass (Ns * R = N), back into the same registers.
   // OUTER: the caller guarantees v[PTS/4 .. 3PTS/4 - 1] == 0 on entry to
   // pass 0 (inputs confined to the first and last quarter), which prunes the
-  // first butterfly.
+  // first butterfly; with 12 points per thread, v[4 .. 7] == 0 (inputs
+  // confined to the first and last third).
   template <int P, class TW, bool OUTER = false>
   static __host__ __device__ __forceinline__ void butterflies(float2 (&v)[PTS], int t, float2* lds, int stride,
                                                               const TW& tw) {
@@ -452,7 +567,7 @@ struct FftS {
 #pragma unroll
       for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
       const int j = t + b * S::G;
-      const int k = j & (NS - 1);
+      const int k = mod_ns<NS>(j);
       if constexpr (P > 0) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -465,6 +580,8 @@ struct FftS {
         dft16_outer<INV>(x);
       } else if constexpr (OUTER && P == 0 && R == 8 && PTS == 8) {
         dft8_outer<INV>(x);
+      } else if constexpr (OUTER && P == 0 && R == 12 && PTS == 12) {
+        dft12<INV, true>(x);
       } else {
         dft<R, INV>(x);
       }
@@ -522,6 +639,20 @@ struct FftS {
 };
 template <int LOGN, bool INV, int PTS = kPts>
 using Fft = FftS<Shape<LOGN, PTS>, INV>;
+
+// Host: fill the twiddle table of a pass plan (tw_size entries).
+inline void build_twiddles_plan(const PassPlan& p, float2* out) {
+  for (int q = 1; q < p.npass; ++q) {
+    const int ns = p.ns[q], r = p.radix[q];
+    const double span = double(ns) * double(r);
+    for (int m = 1; m < r; ++m)
+      for (int k = 0; k < ns; ++k) {
+        const long long e = (long long)k * m % (long long)(ns * r);
+        const double ang = -2.0 * M_PI * double(e) / span;
+        out[p.tw_off[q] + (m - 1) * ns + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+      }
+  }
+}
 
 // Host: fill the twiddle table of a length 2^logn transform with pts points
 // per thread (tw_size entries of that pass plan).

@@ -98,6 +98,7 @@ struct Layout {
   size_t off_tw8[flame::kMaxLog + 1];  // twiddles, 8 points per thread
   size_t off_tw6[flame::kMaxLog + 1];  // twiddles of the length-3N1/4 transform (product grid)
   size_t off_tw6_8[flame::kMaxLog + 1];
+  size_t off_tw12[flame::kMaxLog + 1];  // length 3*2^l/4 in the 12-point plan (product grids)
   size_t off_dev;
   size_t off_dev_full;  // device flame table whose W is the adjoint scratch (physical-grid W for diagnostics)
   size_t off_counter;  // step index read by graph replays
@@ -108,12 +109,14 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   if (!descs || nfl <= 0) return fail(FLAME_ERR_INVALID_ARG, "need at least one flame descriptor");
   L->sizes.resize(nfl);
   size_t off = 0;
-  bool need_tw[flame::kMaxLog + 1] = {}, need_tw6[flame::kMaxLog + 1] = {};
+  bool need_tw[flame::kMaxLog + 1] = {}, need_tw6[flame::kMaxLog + 1] = {}, need_tw12[flame::kMaxLog + 1] = {};
   for (int f = 0; f < nfl; ++f) {
     int rc = check_desc(&descs[f], &L->sizes[f]);
     if (rc) return rc;
     need_tw[L->sizes[f].logn1] = need_tw[L->sizes[f].logn2] = true;
     need_tw6[L->sizes[f].logn1] = L->sizes[f].logn1 >= flame::kMinLogProduct;
+    if (L->sizes[f].logn1 >= flame::kMinLogProduct) need_tw12[L->sizes[f].logn1] = true;
+    if (L->sizes[f].logn2 >= flame::kMinLogRow12) need_tw12[L->sizes[f].logn2] = true;
   }
   for (int f = 0; f < nfl; ++f) {
     const Sizes& s = L->sizes[f];
@@ -143,6 +146,8 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
     if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3, 16) * sizeof(float2));
     L->off_tw6_8[l] = off;
     if (need_tw6[l]) off = align_up(off + (size_t)ff::twiddles6_size(l - 3, 8) * sizeof(float2));
+    L->off_tw12[l] = off;
+    if (need_tw12[l]) off = align_up(off + (size_t)std::max(1, ff::make_plan12(l - 4).tw_size) * sizeof(float2));
   }
   L->off_dev = off;
   off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
@@ -169,6 +174,8 @@ struct Group {
     return (forced ? flame::VAR_EULER_F : flame::VAR_EULER) | nt;
   }
   int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
+  // phi points of the quadratic term's grid: the 12-point row kernel forms it on 3 N2/4
+  int cols() const { return row_pts == 12 ? 3 * (1 << logn2) / 4 : (1 << logn2); }
   int rgroups() const { return (rows() / 2 + rpairs - 1) / rpairs; }
 };
 
@@ -201,6 +208,7 @@ struct flame_plan_s {
   std::vector<std::vector<float2>> tw_host8;  // 8 points per thread
   std::vector<std::vector<float2>> tw_host6;  // length-3N1/4 transforms (16 and 8 points per thread)
   std::vector<std::vector<float2>> tw_host6_8;
+  std::vector<std::vector<float2>> tw_host12;  // length 3*2^l/4, 12 points per thread
   flame::FlameDev* ddev = nullptr;
   flame::FlameDev* ddev_full = nullptr;       // same flames, W in the adjoint scratch
   std::vector<flame::FlameDev> hdev_full;
@@ -344,6 +352,7 @@ int apply_rows(flame_plan p, int gi) {
   const Group& gr = p->groups[gi];
   for (int f = gr.first; f < gr.first + gr.count; ++f) {
     p->hdev[f].rows = gr.rows();
+    p->hdev[f].cols = gr.cols();
     p->w_valid[f] = 0;
   }
   hipError_t e = hipMemcpyAsync(p->ddev + gr.first, p->hdev.data() + gr.first, sizeof(flame::FlameDev) * gr.count,
@@ -598,6 +607,7 @@ int flame_step_noalloc(const flame_desc* desc, void* state, int64_t n, int32_t n
   fd.h1 = desc->n1 / 2;
   fd.tshift = ilog2_exact(s.tq);
   fd.rows = rows;
+  fd.cols = desc->n2;
   const bool lit = desc->axis_scale[0] == 0.0;
   fd.s1 = (float)(lit ? desc->theta_pi : desc->axis_scale[0]);
   fd.s2 = (float)(lit ? desc->theta_pi : desc->axis_scale[1]);
@@ -626,7 +636,6 @@ int flame_step_noalloc(const flame_desc* desc, void* state, int64_t n, int32_t n
   }
   return last_launch("flame_step_noalloc launch");
 }
-
 
 int flame_state_bytes(const flame_desc* desc, size_t* bytes) {
   if (!bytes) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
@@ -739,6 +748,23 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
       }
     }
   }
+  p->tw_host12.resize(flame::kMaxLog + 1);
+  for (int l = flame::kMinLogRow12; l <= flame::kMaxLog; ++l) {
+    bool used = false;
+    for (const Sizes& s : L.sizes)
+      used |= (s.logn1 == l && l >= flame::kMinLogProduct) || s.logn2 == l;
+    if (!used) continue;
+    const ff::PassPlan pp = ff::make_plan12(l - 4);
+    auto& host = p->tw_host12[l];
+    host.assign(std::max(1, pp.tw_size), make_float2(1.f, 0.f));
+    ff::build_twiddles_plan(pp, host.data());
+    e = hipMemcpyAsync(base + L.off_tw12[l], host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice,
+                       p->stream);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_fail(e, "twiddle upload");
+    }
+  }
   // device flame table, ordered so that flames of one grid size are contiguous
   p->hdev.resize(n_flames);
   for (int f = 0; f < n_flames; ++f) {
@@ -761,6 +787,8 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     const bool p6 = s.logn1 >= flame::kMinLogProduct;
     fd.tw6 = p6 ? reinterpret_cast<const float2*>(base + L.off_tw6[s.logn1]) : nullptr;
     fd.tw6_8 = p6 ? reinterpret_cast<const float2*>(base + L.off_tw6_8[s.logn1]) : nullptr;
+    fd.tw12a = p6 ? reinterpret_cast<const float2*>(base + L.off_tw12[s.logn1]) : nullptr;
+    fd.tw12b = s.logn2 >= flame::kMinLogRow12 ? reinterpret_cast<const float2*>(base + L.off_tw12[s.logn2]) : nullptr;
     fd.n1 = d.n1;
     fd.n2 = d.n2;
     fd.m = d.n2 / 4;
@@ -789,7 +817,10 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     }
     p->group_of[f] = (int)p->groups.size() - 1;
   }
-  for (int f = 0; f < n_flames; ++f) p->hdev[f].rows = p->groups[p->group_of[f]].rows();
+  for (int f = 0; f < n_flames; ++f) {
+    p->hdev[f].rows = p->groups[p->group_of[f]].rows();
+    p->hdev[f].cols = p->groups[p->group_of[f]].cols();
+  }
   // the physical-grid W of the diagnostics goes to the adjoint scratch A1..A2
   // (2 wq_elems, contiguous), so the step's W stays valid
   p->hdev_full = p->hdev;
@@ -797,6 +828,7 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
     p->hdev_full[f].Wp = p->hdev[f].A1;
     p->hdev_full[f].Wm = p->hdev[f].A1 + p->layout.sizes[f].wq_elems;
     p->hdev_full[f].rows = p->descs[f].n1;
+    p->hdev_full[f].cols = p->descs[f].n2;
   }
   p->ddev = reinterpret_cast<flame::FlameDev*>(base + L.off_dev);
   p->ddev_full = reinterpret_cast<flame::FlameDev*>(base + L.off_dev_full);
@@ -1085,18 +1117,31 @@ int flame_timing_begin(flame_plan p) {
 int flame_set_points_per_thread(flame_plan p, int32_t n1, int32_t n2, int32_t col_pts, int32_t row_pts) {
   int rc = check_plan(p);
   if (rc) return rc;
-  if ((col_pts != 8 && col_pts != 16) || (row_pts != 8 && row_pts != 16))
-    return fail(FLAME_ERR_INVALID_ARG, "points per thread must be 8 or 16");
+  auto valid = [](int v) { return v == 8 || v == 12 || v == 16; };
+  if (!valid(col_pts) || !valid(row_pts)) return fail(FLAME_ERR_INVALID_ARG, "points per thread must be 8, 12 or 16");
   bool found = false;
-  for (Group& gr : p->groups) {
-    if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
-      gr.col_pts = col_pts;
-      gr.row_pts = row_pts;
-      found = true;
-    }
+  for (const Group& gr : p->groups) {
+    if ((1 << gr.logn1) != n1 || (1 << gr.logn2) != n2) continue;
+    found = true;
+    if (col_pts == 12 && !gr.product)
+      return fail(FLAME_ERR_INVALID_ARG, "col_pts = 12 runs on the product grid: enable it first (n1 >= %d)",
+                  1 << flame::kMinLogProduct);
+    if (row_pts == 12 && gr.logn2 < flame::kMinLogRow12)
+      return fail(FLAME_ERR_UNSUPPORTED_SIZE, "row_pts = 12 needs n2 >= %d", 1 << flame::kMinLogRow12);
   }
   if (!found) return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
   DeviceGuard g(p->device);
+  for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+    Group& gr = p->groups[gi];
+    if ((1 << gr.logn1) != n1 || (1 << gr.logn2) != n2) continue;
+    const bool cols_change = (gr.row_pts == 12) != (row_pts == 12);
+    gr.col_pts = col_pts;
+    gr.row_pts = row_pts;
+    if (cols_change) {
+      rc = apply_rows(p, (int)gi);
+      if (rc) return rc;
+    }
+  }
   drop_graph(p);
   return FLAME_OK;
 }
@@ -1126,6 +1171,8 @@ int flame_set_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t enable)
     found = true;
     if (enable && gr.logn1 < flame::kMinLogProduct)
       return fail(FLAME_ERR_UNSUPPORTED_SIZE, "the product grid needs n1 >= %d", 1 << flame::kMinLogProduct);
+    if (!enable && gr.col_pts == 12)
+      return fail(FLAME_ERR_INVALID_ARG, "col_pts = 12 runs on the product grid: choose 8 or 16 points first");
     if (gr.product != (enable != 0)) {
       gr.product = enable != 0;
       rc = apply_rows(p, (int)gi);
@@ -1192,25 +1239,26 @@ struct TuneCfg {
 
 static std::vector<TuneCfg> tune_cfgs(const Group& gr) {
   std::vector<TuneCfg> cfgs;
+  std::vector<int> rows = {16, 8};
+  if (gr.logn2 >= flame::kMinLogRow12) rows.push_back(12);
   for (bool nt : {false, true}) {
     for (int c : {16, 8})
-      for (int r : {16, 8}) cfgs.push_back(TuneCfg{false, c, r, nt});
+      for (int r : rows) cfgs.push_back(TuneCfg{false, c, r, nt});
     if (gr.logn1 >= flame::kMinLogProduct)
-      for (int c : {16, 8})
-        for (int r : {16, 8}) cfgs.push_back(TuneCfg{true, c, r, nt});
+      for (int c : {16, 8, 12})
+        for (int r : rows) cfgs.push_back(TuneCfg{true, c, r, nt});
   }
   return cfgs;
 }
 
 static int tune_select(flame_plan p, size_t gi, const TuneCfg& cf) {
   Group& gr = p->groups[gi];
+  const bool grid_change = gr.product != cf.product || (gr.row_pts == 12) != (cf.r == 12);
   gr.col_pts = cf.c;
   gr.row_pts = cf.r;
   gr.streaming = cf.nt;
-  if (gr.product != cf.product) {
-    gr.product = cf.product;
-    return apply_rows(p, (int)gi);
-  }
+  gr.product = cf.product;
+  if (grid_change) return apply_rows(p, (int)gi);
   return FLAME_OK;
 }
 

@@ -39,6 +39,8 @@ struct FlameDev {
   const float2* tw2_8;
   const float2* tw6;   // twiddles of the length-3N1/4 transform (product grid), or null
   const float2* tw6_8; // the same for 8 points per thread
+  const float2* tw12a; // twiddles of the length-3N1/4 transform, 12 points per thread (Shape12), or null
+  const float2* tw12b; // the same for the length-3N2/4 transform
   double* part;        // per-workgroup partial sums of the diagnostics
   const double* r0tab; // reference-radius table {r0(t_n), I1_n, I2_n} (r0_law = 1), or null for r0 = t
   long long r0n;       // its entries
@@ -51,9 +53,28 @@ struct FlameDev {
   int rows;            // theta rows of the step's product grid: 3 N1/4, or N1
   float s1, s2;        // axis scales of kappa
   float gamma;
-  float pad2_;
+  int cols;            // phi points of the step's product grid: 3 N2/4, or N2
   double t0, dt;
 };
+
+// Register shape of a length-N transform with PTS points per thread: the
+// power-of-two plans (8 or 16 points), or, for PTS = 12, the length-3N/4
+// transform of a product grid in the 12-point plan (ff::Shape12), which also
+// uses N/16 threads. LOW, HIGH: registers i < LOW hold the spectral positions
+// k = t + G i >= 0 of the retained box, i >= HIGH the negative ones (k - L,
+// L the transform length); the registers between hold padding.
+template <int LOGN, int PTS>
+struct TfShape {
+  using S = ff::Shape<LOGN, PTS>;
+  static constexpr int LOW = PTS / 4, HIGH = 3 * PTS / 4;
+};
+template <int LOGN>
+struct TfShape<LOGN, 12> {
+  using S = ff::Shape12<LOGN - 4>;
+  static constexpr int LOW = 4, HIGH = 8;
+};
+template <int LOGN, int PTS>
+using TShape = typename TfShape<LOGN, PTS>::S;
 
 // Column kernel: T = max(1, 16*256/N1) columns per workgroup, interleaved
 // (thread tid works on column tid % T, FFT lane tid / T); the transform of
@@ -71,12 +92,12 @@ constexpr int q_tile_for(int g16) { return g16 >= 128 ? 2 * col_tile_for(g16) : 
 template <int LOGN1, int PTS = ff::kPts>
 struct ColCfg {
   static constexpr int G16 = ff::Shape<LOGN1>::G;
-  static constexpr int G = ff::Shape<LOGN1, PTS>::G;
+  static constexpr int G = TShape<LOGN1, PTS>::G;
   static constexpr int T = col_tile_for(G16);
   static constexpr int TQ = q_tile_for(G16);
   static constexpr int QS = ff::ilog2c(TQ);
   static constexpr int THREADS = T * G;
-  static constexpr int LDS_BYTES = ff::Shape<LOGN1>::LDS * T * 8;
+  static constexpr int LDS_BYTES = TShape<LOGN1, PTS>::LDS * T * 8;
 };
 
 // Product grid of the step: |grad Phi|^2 is formed on M1 = 3 N1/4 theta rows
@@ -87,6 +108,8 @@ struct ColCfg {
 // radix-PTS passes, then radix 6), with G = M1/PTS threads per column. Used
 // for N1 >= 128.
 constexpr int kMinLogProduct = 7;
+// The phi product grid (3 N2/4 points, 12 points per thread) needs N2 >= 64.
+constexpr int kMinLogRow12 = 6;
 
 template <int LOGN1, int PTS = 16>
 struct ColCfgP {
@@ -123,6 +146,16 @@ struct ColCfgQ {
   static_assert(THREADS % 64 == 0, "whole waves");
 };
 
+// The row kernel's 12-point plan keeps the twiddles of the passes with
+// Ns >= this in registers and reads the others from a copy in LDS (SplitTw).
+constexpr int kRow12MinNs = 192;
+// Table entries of the passes p >= 1 with Ns < min_ns (they come first in the table).
+constexpr int lds_twiddles(const ff::PassPlan& p, int min_ns) {
+  int q = 1;
+  while (q < p.npass && p.ns[q] < min_ns) ++q;
+  return p.tw_off[q] > 0 ? p.tw_off[q] : 1;
+}
+
 // Row kernel: B = max(1, 16*256/N2) row pairs per workgroup, interleaved.
 // WPE: the minimum waves per SIMD it is compiled for; at N2 = 8192 with 16
 // points per thread a workgroup is 8 waves (2 per SIMD), which may then use
@@ -130,11 +163,14 @@ struct ColCfgQ {
 template <int LOGN2, int PTS = ff::kPts>
 struct RowCfg {
   static constexpr int G16 = ff::Shape<LOGN2>::G;
-  static constexpr int G = ff::Shape<LOGN2, PTS>::G;
+  static constexpr int G = TShape<LOGN2, PTS>::G;
   static constexpr int B = G16 >= 256 ? 1 : 256 / G16;
   static constexpr int THREADS = B * G;
-  static constexpr int LDS_BYTES = ff::Shape<LOGN2>::LDS * B * 8;
-  static constexpr int WPE = THREADS >= 512 && PTS == 16 ? 2 : ROW_WAVES_PER_EU;
+  static constexpr int DATA_SLOTS = TShape<LOGN2, PTS>::LDS * B;  // transform exchange area
+  // with 12 points per thread, the small-Ns passes' twiddles follow in LDS (SplitTw)
+  static constexpr int TW_SLOTS = PTS == 12 ? lds_twiddles(TShape<LOGN2, PTS>::plan, kRow12MinNs) : 0;
+  static constexpr int LDS_BYTES = (DATA_SLOTS + TW_SLOTS) * 8;
+  static constexpr int WPE = THREADS >= 512 && PTS >= 12 ? 2 : ROW_WAVES_PER_EU;
 };
 
 constexpr int col_tile(int logn1) { return col_tile_for((1 << logn1) / ff::kPts); }

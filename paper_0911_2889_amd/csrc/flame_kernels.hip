@@ -30,15 +30,23 @@
 
 namespace flame {
 
+// PTS 16 or 8: the column transforms have length N1 (the grid's theta rows).
+// PTS 12: they have length L = 3 N1/4 (the product grid, N1 >= 128) in the
+// 12-point plan (ff::Shape12), on the same N1/16 threads per column as
+// PTS 16 on N1 rows; the kept modes sit in the first and last third of the
+// registers instead of the first and last quarter (TfShape). COL_STEP and
+// COL_FIRST only for PTS 12.
 template <int LOGN1, int MODE, int PTS = ff::kPts, int SV = VAR_EULER>
 __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     col_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase, const float2* src) {
   constexpr int VAR = SV & ~VAR_NT;
   constexpr bool NT = MODE == COL_STEP && (SV & VAR_NT) != 0;
+  static_assert(PTS != 12 || MODE == COL_STEP || MODE == COL_FIRST, "12 points per thread: step modes only");
   if (nbase) n += *nbase;  // graph replays read the step index from device memory
-  using S = ff::Shape<LOGN1, PTS>;
-  constexpr int G = S::G, T = ColCfg<LOGN1, PTS>::T, N1 = S::N;
-  constexpr int KEEP = PTS / 2, LOW = PTS / 4, HIGH = 3 * PTS / 4;
+  using TS = TfShape<LOGN1, PTS>;
+  using S = typename TS::S;
+  constexpr int G = S::G, T = ColCfg<LOGN1, PTS>::T, N1 = 1 << LOGN1, L = S::N;
+  constexpr int LOW = TS::LOW, HIGH = TS::HIGH, KEEP = LOW + PTS - HIGH;
   extern __shared__ float2 lds[];
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
@@ -48,7 +56,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   const bool live = m < f.m;
   float2* my = lds + c;
   constexpr int TQ = ColCfg<LOGN1, PTS>::TQ, QS = ColCfg<LOGN1, PTS>::QS;
-  gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * N1) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
+  gf2* const Qc = glob(f.Q) + ((((size_t)m >> QS) * L) << QS) + (m & (TQ - 1));  // column m: Qc[j1 * TQ]
   gf2* const Wpc = glob(f.Wp);  // element (j1, m) at w_index(j1, m, M)
   gf2* const Wmc = glob(f.Wm);
   // column m of the state: Sc[k1]; COL_FIRST and COL_SYNTH may read another
@@ -56,7 +64,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   gf2* const Sc = glob((MODE == COL_FIRST || MODE == COL_SYNTH) && src ? const_cast<float2*>(src) : f.S) +
                   (size_t)m * f.h1 + N1 / 4;
   gf2* const Pc = glob(VAR >= VAR_HEUN_P ? f.S2 : f.S) + (size_t)m * f.h1 + N1 / 4;  // Heun's predictor
-  const auto tw1 = KernelTw<LOGN1, PTS>::make(PTS == 8 ? f.tw1_8 : f.tw1, t);
+  const auto tw1 = AxisTw<LOGN1, PTS>::make(f.tw1, f.tw1_8, f.tw12a, t);
 
   float2 v[PTS];
   float2 sv[KEEP];
@@ -76,24 +84,24 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     float2 old[KEEP], frc[KEEP], prd[KEEP];
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
-      const int i = kept_reg<PTS>(kk);
-      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
+      const int i = kept_reg<LOGN1, PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? L : 0);
       old[kk] = MODE == COL_STEP ? ld(Sl + k1) : make_float2(0.f, 0.f);
       frc[kk] = FORCED ? forcing_at(f, ms, k1) : make_float2(0.f, 0.f);
       prd[kk] = MODE == COL_STEP && VAR == VAR_HEUN_C ? ld(Pl + k1) : make_float2(0.f, 0.f);
     }
-    fft<LOGN1, false>(v, t, my, T, tw1);
+    fft_s<S, false>(v, t, my, T, tw1);
     StepScalars sc{};
     float ac = 0.f;  // the corrector's dt c_{n+1} / P
-    if constexpr (MODE == COL_STEP) sc = step_scalars(f, n, f.n1);
-    if constexpr (MODE == COL_STEP && VAR == VAR_HEUN_C) ac = step_scalars(f, n + 1, f.n1).a;
+    if constexpr (MODE == COL_STEP) sc = step_scalars(f, n, L, f.cols);
+    if constexpr (MODE == COL_STEP && VAR == VAR_HEUN_C) ac = step_scalars(f, n + 1, L, f.cols).a;
     const float inv_p = 1.0f / ((float)f.n1 * (float)f.n2);
     const float kap2c = f.s2 * (float)m;
     const float dtf = (float)f.dt;
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
-      const int i = kept_reg<PTS>(kk);
-      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
+      const int i = kept_reg<LOGN1, PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? L : 0);
       const int s = k1 + N1 / 4;
       float2 val;
       if constexpr (MODE == COL_STEP) {
@@ -125,7 +133,7 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
       if (c == 0) {
 #pragma unroll
         for (int kk = LOW; kk < KEEP; ++kk) {
-          const int k1 = t + G * kept_reg<PTS>(kk) - N1;
+          const int k1 = t + G * kept_reg<LOGN1, PTS>(kk) - L;
           if (k1 > -N1 / 4) sv[kk] = ff::cconj(lds[-k1]);
         }
         if (t == 0) sv[0].y = 0.f;
@@ -136,16 +144,16 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
       gf2* const Dc = VAR == VAR_HEUN_P ? Pc : Sc;  // the predictor goes to S2
 #pragma unroll
       for (int kk = 0; kk < KEEP; ++kk) {
-        const int i = kept_reg<PTS>(kk);
-        const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
+        const int i = kept_reg<LOGN1, PTS>(kk);
+        const int k1 = t + G * i - (i >= HIGH ? L : 0);
         st(Dc + k1, sv[kk]);
       }
     }
   } else {
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
-      const int i = kept_reg<PTS>(kk);
-      const int k1 = t + G * i - (i >= HIGH ? N1 : 0);
+      const int i = kept_reg<LOGN1, PTS>(kk);
+      const int k1 = t + G * i - (i >= HIGH ? L : 0);
       sv[kk] = live ? ld(Sc + k1) : make_float2(0.f, 0.f);
     }
   }
@@ -154,8 +162,8 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
 #pragma unroll
     for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int kk = 0; kk < KEEP; ++kk) v[kept_reg<PTS>(kk)] = sv[kk];
-    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
+    for (int kk = 0; kk < KEEP; ++kk) v[kept_reg<LOGN1, PTS>(kk)] = sv[kk];
+    fft_s<S, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < PTS; ++i) st(Qc + (t + G * i) * TQ, v[i]);
@@ -167,11 +175,11 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
-      const int i = kept_reg<PTS>(kk);
-      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? N1 : 0));
+      const int i = kept_reg<LOGN1, PTS>(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? L : 0));
       v[i] = make_float2(-kap1 * sv[kk].y - kap2 * sv[kk].x, kap1 * sv[kk].x - kap2 * sv[kk].y);
     }
-    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
+    fft_s<S, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < PTS; ++i) st_nt<NT>(Wpc + w_index(t + G * i, m, f.m), v[i]);
@@ -181,11 +189,11 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
     for (int i = 0; i < PTS; ++i) v[i] = make_float2(0.f, 0.f);
 #pragma unroll
     for (int kk = 0; kk < KEEP; ++kk) {
-      const int i = kept_reg<PTS>(kk);
-      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? N1 : 0));
+      const int i = kept_reg<LOGN1, PTS>(kk);
+      const float kap1 = f.s1 * (float)(t + G * i - (i >= HIGH ? L : 0));
       v[i] = make_float2(-kap1 * sv[kk].y + kap2 * sv[kk].x, kap1 * sv[kk].x + kap2 * sv[kk].y);
     }
-    fft<LOGN1, true, kPrune>(v, t, my, T, tw1);
+    fft_s<S, true, kPrune>(v, t, my, T, tw1);
     if (live) {
 #pragma unroll
       for (int i = 0; i < PTS; ++i) st_nt<NT>(Wmc + w_index(t + G * i, m, f.m), ff::cconj(v[i]));
@@ -193,14 +201,19 @@ __global__ void __launch_bounds__((ColCfg<LOGN1, PTS>::THREADS)) __attribute__((
   }
 }
 
+// PTS 16 or 8: the row transforms have length N2. PTS 12 (ROW_STEP only):
+// the quadratic term is formed on L2 = 3 N2/4 phi points (the product grid
+// along phi, N2 >= 64), with the 12-point plan on N2/16 threads per row pair.
 template <int LOGN2, int MODE, int PTS = ff::kPts, bool NT = false>
 __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((amdgpu_waves_per_eu(RowCfg<LOGN2, PTS>::WPE)))
     row_kernel(const FlameDev* __restrict__ fls, long long n, const long long* nbase,
                const float* __restrict__ phys_in, float* __restrict__ phys_out) {
+  static_assert(PTS != 12 || MODE == ROW_STEP, "12 points per thread: the step only");
   if (nbase) n += *nbase;
-  using S = ff::Shape<LOGN2, PTS>;
-  constexpr int G = S::G, B = RowCfg<LOGN2, PTS>::B, N2 = S::N;
-  constexpr int LOW = PTS / 4, HIGH = 3 * PTS / 4;
+  using TS = TfShape<LOGN2, PTS>;
+  using S = typename TS::S;
+  constexpr int G = S::G, B = RowCfg<LOGN2, PTS>::B, N2 = 1 << LOGN2, L2 = S::N;
+  constexpr int LOW = TS::LOW, HIGH = TS::HIGH;
   extern __shared__ float2 lds[];
   const FlameDev f = fls[blockIdx.y];
   const int tid = threadIdx.x;
@@ -211,7 +224,18 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
   const bool live = pair < n1 / 2;
   const int ja = 2 * pair, jb = 2 * pair + 1;
   float2* my = lds + p;
-  const auto tw2 = KernelTw<LOGN2, PTS>::make(PTS == 8 ? f.tw2_8 : f.tw2, t);
+  // 12 points per thread: the small-Ns passes read their twiddles from LDS
+  using Tw12 = SplitTw<S, kRow12MinNs>;
+  float2* const lds_tw = lds + RowCfg<LOGN2, PTS>::DATA_SLOTS;
+  if constexpr (PTS == 12) Tw12::stage(lds_tw, f.tw12b, tid, RowCfg<LOGN2, PTS>::THREADS);
+  const auto tw2 = [&] {
+    if constexpr (PTS == 12) {
+      static_assert(Tw12::LDS_ENTRIES <= RowCfg<LOGN2, PTS>::TW_SLOTS, "LDS twiddle area");
+      return Tw12(f.tw12b, lds_tw, t);
+    } else {
+      return AxisTw<LOGN2, PTS>::make(f.tw2, f.tw2_8, f.tw12b, t);
+    }
+  }();
   gf2* const Wp = glob(f.Wp);
   gf2* const Wm = glob(f.Wm);
   gf2* const Q = glob(f.Q);
@@ -240,7 +264,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       if (i < LOW) {
         ld_pair(Wp + (((pbase4 + idx) << 2) + poff), a, b);
       } else if (i >= HIGH) {
-        const int mm = N2 - idx;  // < mcols except at i = HIGH, t = 0
+        const int mm = L2 - idx;  // < mcols except at i = HIGH, t = 0
         ld_pair(Wm + (((pbase4 + (i > HIGH || t > 0 ? mm : 0)) << 2) + poff), a, b);
       }
       vr[0][i] = a;
@@ -251,7 +275,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
     vr[1][HIGH] = t > 0 ? vr[1][HIGH] : make_float2(0.f, 0.f);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      fft<LOGN2, true, kPrune>(vr[half], t, my, B, tw2);
+      fft_s<S, true, kPrune>(vr[half], t, my, B, tw2);
 #pragma unroll
       for (int i = 0; i < PTS; ++i) {
         const float q = vr[half][i].x * vr[half][i].x + vr[half][i].y * vr[half][i].y;
@@ -306,7 +330,7 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
       }
       y[i] = val;
     }
-    fft<LOGN2, true, kPrune>(y, t, my, B, tw2);
+    fft_s<S, true, kPrune>(y, t, my, B, tw2);
     if (live) {
 #pragma unroll
       for (int i = 0; i < PTS; ++i) {
@@ -320,16 +344,16 @@ __global__ void __launch_bounds__((RowCfg<LOGN2, PTS>::THREADS)) __attribute__((
 
   // forward transform of the two packed real rows, then split:
   // Q_a(k) = (Y(k) + conj(Y(-k)))/2, Q_b(k) = (Y(k) - conj(Y(-k)))/(2i), k in [0, K2]
-  fft<LOGN2, false>(y, t, my, B, tw2);
+  fft_s<S, false>(y, t, my, B, tw2);
   __syncthreads();
-  ff::Fft<LOGN2, false, PTS>::scatter(y, t, my, B);
+  ff::FftS<S, false>::scatter(y, t, my, B);
   __syncthreads();
   if (live) {
 #pragma unroll
     for (int i = 0; i < LOW; ++i) {
       const int k = t + G * i;
       const float2 yk = my[ff::lds_pad(k) * B];
-      const float2 ym = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
+      const float2 ym = my[ff::lds_pad(k == 0 ? 0 : L2 - k) * B];
       const float2 qa = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
       const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
       st_nt<NT>(Q + tiled(ja, k, n1, ts), qa);
@@ -407,8 +431,8 @@ __global__ void __launch_bounds__((ColCfgP<LOGN1, PTS>::THREADS))
     }
     float2 o[IT * 6];
     fft6<LOGP, false, PTS>(v, o, t, my, T, tw);
-    const StepScalars sc = step_scalars(f, n, M1);
-    const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1).a : 0.f;  // the corrector's dt c_{n+1} / P
+    const StepScalars sc = step_scalars(f, n, M1, f.cols);
+    const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1, f.cols).a : 0.f;  // the corrector's dt c_{n+1} / P
     const float kap2c = f.s2 * (float)m;
     const float dtf = (float)f.dt;
 #pragma unroll
@@ -566,8 +590,8 @@ __global__ void __launch_bounds__((ColCfgQ<LOGN1>::THREADS)) __attribute__((amdg
       }
       float2 o[ITF * 6];
       fft6<LOGP, false, 8>(v, o, t8, buf0, T, twf);
-      const StepScalars sc = step_scalars(f, n, M1);
-      const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1).a : 0.f;  // the corrector's dt c_{n+1} / P
+      const StepScalars sc = step_scalars(f, n, M1, f.cols);
+      const float ac = VAR == VAR_HEUN_C ? step_scalars(f, n + 1, M1, f.cols).a : 0.f;  // the corrector's dt c_{n+1} / P
       const float kap2c = f.s2 * (float)m;
       const float dtf = (float)f.dt;
 #pragma unroll
@@ -776,6 +800,7 @@ struct ColTable {
   }
   template <int VAR>
   static KernelLaunch step_kernel_v(int pts) {
+    if (pts == 12) return KernelLaunch{nullptr, 0, 0};  // product grid only (ColPTable)
     if (pts == 8)
       return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, VAR>),
                           ColCfg<LOGN, 8>::THREADS, ColCfg<LOGN, 8>::LDS_BYTES};
@@ -817,6 +842,13 @@ struct RowTable {
   }
   template <bool NT>
   static KernelLaunch step_kernel_nt(int pts) {
+    if (pts == 12) {
+      if constexpr (LOGN >= kMinLogRow12)
+        return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 12, NT>),
+                            RowCfg<LOGN, 12>::THREADS, RowCfg<LOGN, 12>::LDS_BYTES};
+      else
+        return KernelLaunch{nullptr, 0, 0};
+    }
     if (pts == 8)
       return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8, NT>), RowCfg<LOGN, 8>::THREADS,
                           RowCfg<LOGN, 8>::LDS_BYTES};
@@ -845,8 +877,20 @@ struct ColPTable {
                         ColCfgQ<LOGN>::LDS_BYTES};
   }
   template <int VAR>
-  static KernelLaunch pick(int mode, int pts) { return pts == 8 ? split<VAR>(mode) : info<VAR>(mode); }
-  // pts 16: colp_kernel<., 16>; pts 8: the split kernel (8 points per thread in the forward transform)
+  static KernelLaunch twelve(int mode) {
+    if (mode == COL_FIRST)
+      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_FIRST, 12>),
+                          ColCfg<LOGN, 12>::THREADS, ColCfg<LOGN, 12>::LDS_BYTES};
+    return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 12, VAR>),
+                        ColCfg<LOGN, 12>::THREADS, ColCfg<LOGN, 12>::LDS_BYTES};
+  }
+  template <int VAR>
+  static KernelLaunch pick(int mode, int pts) {
+    return pts == 8 ? split<VAR>(mode) : (pts == 12 ? twelve<VAR>(mode) : info<VAR>(mode));
+  }
+  // pts 16: colp_kernel<., 16> (radix-16 passes, then radix 6); pts 8: the split
+  // kernel (8 points per thread in the forward transform); pts 12: col_kernel
+  // in the 12-point plan (ff::Shape12)
   static KernelLaunch step_kernel(int mode, int pts, int var) {
     switch (var) {
       case VAR_EULER_F: return pick<VAR_EULER_F>(mode, pts);
@@ -900,6 +944,7 @@ void launch_col(int logn1, int mode, int tiles, int nfl, hipStream_t st, const F
                 const void* src, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, int var) {
   if (mode == COL_STEP && (var != VAR_EULER || pts != ff::kPts || ev_start || ev_stop)) {
     const KernelLaunch kl = col_step_kernel(logn1, pts, var);
+    if (!kl.func) return;
     const long long* nb = nullptr;
     const float2* s = static_cast<const float2*>(src);
     void* args[] = {&fl, &n, &nb, &s};
@@ -916,6 +961,7 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
                 const float* in, float* out, int pts, hipEvent_t ev_start, hipEvent_t ev_stop, bool nt) {
   if (mode == ROW_STEP && (pts != ff::kPts || nt || ev_start || ev_stop)) {
     const KernelLaunch kl = row_step_kernel(logn2, pts, nt);
+    if (!kl.func) return;
     const long long* nb = nullptr;
     void* args[] = {&fl, &n, &nb, &in, &out};
     if (ev_start || ev_stop)
@@ -956,6 +1002,7 @@ int col_lds(int logn1) {
     if constexpr (L >= kMinLogProduct) {
       if (ColCfgP<L, 16>::LDS_BYTES > b) b = ColCfgP<L, 16>::LDS_BYTES;
       if (ColCfgQ<L>::LDS_BYTES > b) b = ColCfgQ<L>::LDS_BYTES;
+      if (ColCfg<L, 12>::LDS_BYTES > b) b = ColCfg<L, 12>::LDS_BYTES;
     }
     return b;
   }
@@ -966,7 +1013,11 @@ template <int L>
 int row_lds(int logn2) {
   if constexpr (L <= kMaxLog) {
     if (logn2 != L) return row_lds<L + 1>(logn2);
-    return RowCfg<L, 16>::LDS_BYTES > RowCfg<L, 8>::LDS_BYTES ? RowCfg<L, 16>::LDS_BYTES : RowCfg<L, 8>::LDS_BYTES;
+    int b = RowCfg<L, 16>::LDS_BYTES > RowCfg<L, 8>::LDS_BYTES ? RowCfg<L, 16>::LDS_BYTES : RowCfg<L, 8>::LDS_BYTES;
+    if constexpr (L >= kMinLogRow12) {
+      if (RowCfg<L, 12>::LDS_BYTES > b) b = RowCfg<L, 12>::LDS_BYTES;
+    }
+    return b;
   }
   return 0;
 }

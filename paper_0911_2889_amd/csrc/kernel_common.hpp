@@ -36,6 +36,21 @@ __device__ __forceinline__ void fft(float2 (&v)[PTS], int t, float2* lds, int st
   fft_passes<LOGN, INV, OUTER, PTS, 0>(v, t, lds, stride, tw);
 }
 
+// The same for any register shape S (ff::Shape, ff::Shape12); with
+// ff::Shape12, OUTER means the middle third of the registers vanishes.
+template <class S, bool INV, bool OUTER = false, int P = 0, class TW>
+__device__ __forceinline__ void fft_s(float2 (&v)[S::PTS], int t, float2* lds, int stride, const TW& tw) {
+  if constexpr (P < S::NPASS) {
+    ff::FftS<S, INV>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
+    if constexpr (P + 1 < S::NPASS) {
+      __syncthreads();
+      ff::FftS<S, INV>::gather(v, t, lds, stride);
+      __syncthreads();
+    }
+    fft_s<S, INV, OUTER, P + 1>(v, t, lds, stride, tw);
+  }
+}
+
 // Global-memory views: loads and stores through these pointers compile to
 // global_* instructions (flat ones would also wait on LDS counters).
 using v2f = float __attribute__((ext_vector_type(2)));
@@ -83,6 +98,59 @@ struct KernelTw {
       return Type(GlobalFetch{(const gf2*)tw}, t);
     } else {
       return Type{tw, t};
+    }
+  }
+};
+
+// Twiddles of a step kernel's transform along an axis of 2^LOGN points with
+// PTS points per thread: the power-of-two plans (tables p16, p8), or, for
+// PTS = 12, the length-3*2^LOGN/4 transform of the 12-point plan (table p12),
+// cached in registers.
+template <int LOGN, int PTS>
+struct AxisTw {
+  using Type = typename std::conditional<PTS == 12, ff::RegTwS<TShape<LOGN, PTS>, GlobalFetch, kTwCacheMinNs>,
+                                         typename KernelTw<LOGN, PTS == 12 ? 16 : PTS>::Type>::type;
+  static __device__ __forceinline__ Type make(const float2* p16, const float2* p8, const float2* p12, int t) {
+    if constexpr (PTS == 12) {
+      return Type(GlobalFetch{(const gf2*)p12}, t);
+    } else {
+      return KernelTw<LOGN, PTS>::make(PTS == 8 ? p8 : p16, t);
+    }
+  }
+};
+
+// Twiddle source for kernels short of registers: the passes with
+// Ns >= MIN_NS keep their twiddles in registers for the kernel's lifetime
+// (loaded from the global table), the passes with smaller Ns read theirs at
+// each use from a copy of the first LDS_ENTRIES entries of the table in LDS
+// (those passes' part), which the kernel writes before its first transform's
+// second pass. The passes with small Ns have few distinct twiddles, so the
+// lanes of a wave read few LDS addresses.
+template <class S, int MIN_NS>
+struct SplitTw {
+  using Reg = ff::RegTwS<S, GlobalFetch, MIN_NS>;
+  static constexpr int first_cached() {
+    int p = 1;
+    while (p < S::NBF && !Reg::cached(p)) ++p;
+    return p;
+  }
+  static constexpr int LDS_ENTRIES = S::tw_off(first_cached()) > 0 ? S::tw_off(first_cached()) : 1;
+  Reg reg;
+  const float2* tab;
+  int t;
+  __device__ __forceinline__ SplitTw(const float2* global_tab, const float2* lds_tab, int t_)
+      : reg(GlobalFetch{(const gf2*)global_tab}, t_), tab(lds_tab), t(t_) {}
+  // copy the table's first LDS_ENTRIES entries into LDS (every thread of the workgroup calls it)
+  static __device__ __forceinline__ void stage(float2* lds_tab, const float2* global_tab, int tid, int threads) {
+    for (int i = tid; i < LDS_ENTRIES; i += threads) lds_tab[i] = ld((const gf2*)global_tab + i);
+  }
+  template <int P>
+  __device__ __forceinline__ float2 get(int b, int r) const {
+    if constexpr (Reg::cached(P)) {
+      return reg.template get<P>(b, r);
+    } else {
+      constexpr int NS = S::ns(P);
+      return tab[S::tw_off(P) + (r - 1) * NS + ff::mod_ns<NS>(t + b * S::G)];
     }
   }
 };
@@ -143,14 +211,14 @@ __device__ __forceinline__ double r0_at(const FlameDev& f, long long n) {
 // Scalars of step n: c_n = 1/(2 r0(t_n)^2), I1 = int r0^-1, I2 = int r0^-2
 // over [t_n, t_{n+1}]: for r0(t) = t in closed form, I1 = ln(t_{n+1}/t_n),
 // I2 = 1/t_n - 1/t_{n+1} (the time formed in double); else from the table.
-// `rows` is the number of theta rows of the grid the quadratic term was
-// formed on (N1, or 3 N1/4 on the product grid): the forward transforms are
-// unnormalised, so a = dt c_n / (rows N2).
-__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n, int rows) {
+// `rows` x `cols` is the grid the quadratic term was formed on (N1 or
+// 3 N1/4 theta rows, N2 or 3 N2/4 phi points): the forward transforms are
+// unnormalised, so a = dt c_n / (rows cols).
+__device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long n, int rows, int cols) {
   StepScalars s;
   if (f.r0tab) {
     const double* e = r0_entry(f, n);
-    s.a = (float)(f.dt / (2.0 * e[0] * e[0] * (double)rows * (double)f.n2));
+    s.a = (float)(f.dt / (2.0 * e[0] * e[0] * (double)rows * (double)cols));
     s.i1 = (float)e[1];
     s.i2 = (float)e[2];
     return s;
@@ -158,7 +226,7 @@ __device__ __forceinline__ StepScalars step_scalars(const FlameDev& f, long long
   const float t = (float)(f.t0 + (double)n * f.dt);
   const float dt = (float)f.dt;
   const float x = dt / t;
-  s.a = 0.5f * x / (t * (float)rows * (float)f.n2);
+  s.a = 0.5f * x / (t * (float)rows * (float)cols);
   s.i1 = log1pf(x);
   s.i2 = x / (t + dt);
   return s;
@@ -219,12 +287,13 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
-// Register slot kk (0..PTS/2-1) of the kept spectral positions: registers
-// 0..PTS/4-1 hold k1 = t + G*i >= 0, registers 3PTS/4..PTS-1 hold
-// k1 = t + G*i - N1 < 0 (the first and last quarter of the padded length).
-template <int PTS>
+// Register slot kk (0..7) of the kept spectral positions: registers
+// 0..LOW-1 hold k = t + G*i >= 0, registers HIGH..PTS-1 hold k = t + G*i - L < 0
+// (the first and last quarter of a padded length L = N, or the first and
+// last third of a product-grid length L = 3N/4; TfShape).
+template <int LOGN, int PTS>
 __device__ __forceinline__ constexpr int kept_reg(int kk) {
-  return kk < PTS / 4 ? kk : kk + PTS / 2;
+  return kk < TfShape<LOGN, PTS>::LOW ? kk : kk + (TfShape<LOGN, PTS>::HIGH - TfShape<LOGN, PTS>::LOW);
 }
 
 

@@ -124,6 +124,59 @@ void run6(std::vector<float2>& x, int stride) {
     if (seen[i] != 1) x[i] = make_float2(1e30f, 1e30f);  // every position exactly once
 }
 
+// Shape12 (N = 12 * 2^E, 12 points per thread): the mixed-radix passes in
+// natural order, like Shape.
+template <int E, bool INV, int P, bool OUTER>
+void passes12(std::vector<Regs<12>>& v, float2* lds, int stride, const float2* tw, bool cached) {
+  using S = ff::Shape12<E>;
+  using F = ff::FftS<S, INV>;
+  if constexpr (P < S::NPASS) {
+    for (int t = 0; t < S::G; ++t) {
+      if (cached) {
+        ff::RegTwS<S, TableFetch, 2> rt(TableFetch{tw}, t);
+        F::template butterflies<P, decltype(rt), OUTER>(v[t].a, t, lds, stride, rt);
+      } else {
+        F::template butterflies<P, ff::GlobalTwS<S>, OUTER>(v[t].a, t, lds, stride, ff::GlobalTwS<S>{tw, t});
+      }
+    }
+    if constexpr (P + 1 < S::NPASS) {
+      for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
+    }
+    passes12<E, INV, P + 1, OUTER>(v, lds, stride, tw, cached);
+  }
+}
+
+template <int E, bool INV>
+void run12(std::vector<float2>& x, int stride, bool outer) {
+  using S = ff::Shape12<E>;
+  std::vector<float2> tw(S::plan.tw_size + 1);
+  ff::build_twiddles_plan(S::plan, tw.data());
+  std::vector<Regs<12>> v(S::G);
+  for (int t = 0; t < S::G; ++t)
+    for (int i = 0; i < 12; ++i) v[t].a[i] = x[t + S::G * i];
+  std::vector<float2> lds(size_t(S::LDS) * stride, make_float2(1e30f, 1e30f));
+  if (outer)
+    passes12<E, INV, 0, true>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  else
+    passes12<E, INV, 0, false>(v, lds.data() + (stride - 1), stride, tw.data(), stride % 2 == 1);
+  for (int t = 0; t < S::G; ++t)
+    for (int i = 0; i < 12; ++i) x[t + S::G * i] = v[t].a[i];
+}
+
+template <int E>
+bool dispatch12(int e, int inv, std::vector<float2>& x, int stride, bool outer) {
+  if constexpr (E > 9) {
+    return false;
+  } else {
+    if (e != E) return dispatch12<E + 1>(e, inv, x, stride, outer);
+    if (inv)
+      run12<E, true>(x, stride, outer);
+    else
+      run12<E, false>(x, stride, outer);
+    return true;
+  }
+}
+
 template <int LOGN>
 bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer, int pts) {
   if constexpr (LOGN > 13) {
@@ -169,13 +222,24 @@ bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride, int pts) {
 }  // namespace
 
 // Header: logn inv stride outer pts six. With six = 1 the length is
-// 6 * 2^logn (Shape6, outer unused).
+// 6 * 2^logn (Shape6, outer unused); with six = 2 it is 12 * 2^logn
+// (Shape12, pts unused; outer zeroes the middle third of the input).
 int main() {
   int hdr[6];
   if (fread(hdr, sizeof(int), 6, stdin) != 6) return 2;
   const int logn = hdr[0], inv = hdr[1], stride = hdr[2], outer = hdr[3], pts = hdr[4], six = hdr[5];
-  if (pts != 8 && pts != 16) return 3;
   if (stride < 1) return 3;
+  if (six == 2) {  // Shape12 with E = logn: length 12 * 2^E
+    if (logn < 2 || logn > 9) return 3;
+    std::vector<float2> x(size_t(12) << logn);
+    if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
+    if (outer)  // the pruned first pass assumes the middle third of the input is zero
+      for (size_t i = x.size() / 3; i < 2 * x.size() / 3; ++i) x[i] = make_float2(0.f, 0.f);
+    if (!dispatch12<2>(logn, inv, x, stride, outer != 0)) return 5;
+    fwrite(x.data(), sizeof(float2), x.size(), stdout);
+    return 0;
+  }
+  if (pts != 8 && pts != 16) return 3;
   if (six) {
     if (logn < 4 || logn > 10) return 3;
     std::vector<float2> x(size_t(6) << logn);

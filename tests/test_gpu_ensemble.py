@@ -116,14 +116,15 @@ def test_autotune_keeps_the_state_and_agrees_with_the_oracle(graph_steps):
         ens.set_spectrum(h, flame=f, n=0)
     ens.step(5)
     before = [ens.spectrum(f).cpu().numpy() for f in range(len(members))]
-    # per group: four points-per-thread choices on N1 rows, and four more on
-    # the product grid where n1 >= 128 (256x512 and 128x64), each with plain
-    # and with non-temporal stores
-    assert ens.autotune(steps=4) == 8 + 16 + 16
+    # per group: (col, row) points per thread in {16, 8} x {16, 8, 12} on N1
+    # rows (12 rows: the phi product grid, n2 >= 64), and {16, 8, 12}^2 on the
+    # theta product grid where n1 >= 128 (256x512 and 128x64), each with
+    # plain and with non-temporal stores
+    assert ens.autotune(steps=4) == 12 + 30 + 30
     assert ens.step_index == 5
     for f in range(len(members)):
         assert np.array_equal(ens.spectrum(f).cpu().numpy(), before[f])
-        assert ens.points_per_thread(members[f].n1, members[f].n2)[0] in (8, 16)
+        assert ens.points_per_thread(members[f].n1, members[f].n2)[0] in (8, 12, 16)
     ens.step(15)
     for f in range(len(members)):
         ref = oracle_trajectory(halves[f], oracle_params(members[f]), [20])[20]

@@ -145,3 +145,20 @@ def test_fft_engine_on_host_matches_numpy(tmp_path):
                 xd = x.astype(np.complex128)
                 ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
                 assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (logp, inv, stride, pts)
+    # length 12 * 2^e, 12 points per thread (radix 12, then radix 4 and 2): the
+    # product grids' transforms; outer = 1 zeroes the middle third of the input
+    # and uses the pruned first pass
+    for e in range(2, 10):
+        for inv in (0, 1):
+            for stride, outer in ((1, 0), (2, 0), (3, 0), (1, 1), (2, 1), (3, 1)):
+                n = 12 << e
+                rng = np.random.default_rng(e * 13 + inv)
+                x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+                if outer:
+                    x[n // 3: 2 * n // 3] = 0
+                out = subprocess.run([str(exe)], input=struct.pack("6i", e, inv, stride, outer, 12, 2) + x.tobytes(),
+                                     capture_output=True, check=True).stdout
+                y = np.frombuffer(out, dtype=np.complex64)
+                xd = x.astype(np.complex128)
+                ref = np.fft.ifft(xd) * n if inv else np.fft.fft(xd)
+                assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-7, (e, inv, stride, outer)
