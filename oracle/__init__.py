@@ -18,6 +18,8 @@ simulations of flames"):
 * Section 3, symmetrisation paragraph and its figure: the upper half of the
   spectrum is copied onto the lower half by Psi(-k) = conj(Psi(k)).
 * Section 3, averages paragraph and Section 2 (averaged flame velocity).
+* Section 2, the circular flames of the averaged-velocity figure: a reading
+  (the one-dimensional form of Eq. (1)) in ``circle.py``.
 
 Readings where the paper is silent are listed in ``model.py`` and in the
 design notes; the integrator (integrating-factor Euler) is one of them, so
@@ -36,4 +38,8 @@ from .model import (  # noqa: F401
 from .diagnostics import diagnostics  # noqa: F401
 from .adjoint import (  # noqa: F401
     area_gradient, step_adjoint, trajectory_gradient, area_excess,
+)
+from .circle import (  # noqa: F401
+    CircleParams, circle_symmetrise, circle_convolution_sum, circle_scalars, circle_step, circle_run,
+    circle_diagnostics, half_to_circle, circle_to_half,
 )

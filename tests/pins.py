@@ -413,3 +413,146 @@ def pin_forcing_geometric_series(R=30.0, n1=32, n2=64, dt=0.5, steps=25, mode=(2
     gain = e if integrator == "euler" else 0.5 * (1.0 + e)
     want = dt * f[a, b] * gain * (1.0 - e ** steps) / (1.0 - e)
     return max(abs(out[a, b] - want), abs(out[-a, -b] - np.conj(want))) / abs(want)
+
+
+# ---------------------------------------------------------------- circles
+# Pins of the circular-flame oracle (oracle/circle.py): the one-dimensional
+# form of Eq. (1). Each is written from the definitions, not from the
+# oracle's code.
+
+def random_circle(n, rng, amp):
+    """Hermitian coefficients on |k| <= K (full FFT-ordered array, Im of k = 0 zero)."""
+    K = oracle.truncation(n)
+    full = np.zeros(n, dtype=np.complex128)
+    for k in range(1, K + 1):
+        v = amp * (rng.standard_normal() + 1j * rng.standard_normal()) / k
+        full[k] = v
+        full[-k] = np.conj(v)
+    full[0] = amp * rng.standard_normal()
+    return full
+
+
+def pin_circle_literal_sum(n=21, seed=50, s=1.0):
+    """The oracle's FFT convolution against the literal double sum
+    sum_l kappa_l kappa_{k-l} Phi_l Phi_{k-l} over |l|, |k - l| <= K."""
+    rng = np.random.default_rng(seed)
+    p = oracle.CircleParams(n, seg=s)
+    full = random_circle(n, rng, 1.0)
+    K = oracle.truncation(n)
+    worst, scale = 0.0, 0.0
+    got = oracle.circle_convolution_sum(full, p)
+    for k in range(-K, K + 1):
+        acc = 0j
+        for l in range(-K, K + 1):
+            if abs(k - l) <= K:
+                acc += (s * l) * (s * (k - l)) * full[l % n] * full[(k - l) % n]
+        worst = max(worst, abs(got[k % n] - acc))
+        scale = max(scale, abs(acc))
+    return worst / scale
+
+
+def pin_circle_single_cosine(n=64, k=5, a=0.3, psi=0.7, s=2.0):
+    """Phi = a cos(k phi + psi): Phi_phi = -a kappa sin(.), so the sum is
+    -F[Phi_phi^2] with F[.]_0 = a^2 kappa^2/2 and F[.]_{+-2k} = -a^2 kappa^2/4 e^{+-2i psi}."""
+    p = oracle.CircleParams(n, seg=s)
+    full = np.zeros(n, dtype=np.complex128)
+    full[k] = 0.5 * a * np.exp(1j * psi)
+    full[-k] = np.conj(full[k])
+    got = oracle.circle_convolution_sum(full, p)
+    kap = s * k
+    want = np.zeros(n, dtype=np.complex128)
+    want[0] = -a * a * kap * kap / 2
+    if 2 * k <= oracle.truncation(n):  # outside the box the sum is not kept
+        want[2 * k] = a * a * kap * kap / 4 * np.exp(2j * psi)
+        want[-2 * k] = np.conj(want[2 * k])
+    return np.abs(got - want).max() / (a * a * kap * kap / 2)
+
+
+def pin_circle_linear_growth(n=256, k=30, dt=0.5, nsteps=40, t0=200.0, s=1.0):
+    """A tiny single mode grows as (t/t0)^(gamma kappa/2) exp(kappa^2 (1/t - 1/t0)),
+    the exact solution of the linear part with r0 = t."""
+    p = oracle.CircleParams(n, seg=s, t0=t0, dt=dt)
+    full = np.zeros(n, dtype=np.complex128)
+    full[k] = 1e-20 * (0.6 + 0.8j)
+    full[-k] = np.conj(full[k])
+    out = oracle.circle_run(full, p, nsteps)
+    t = t0 + nsteps * dt
+    kap = s * k
+    g = (t / t0) ** (0.8 * kap / 2) * np.exp(kap * kap * (1.0 / t - 1.0 / t0))
+    return abs(out[k] - g * full[k]) / abs(g * full[k])
+
+
+def pin_circle_is_sphere_restriction(n1=16, n=40, s=(0.7, 1.5), steps=6, seed=51):
+    """Eq. (1) maps states confined to k1 = 0 into themselves: the
+    two-dimensional oracle run on such a state (axis scales s) must equal the
+    circular oracle with segment integer s2, and keep every k1 != 0 mode zero."""
+    rng = np.random.default_rng(seed)
+    p2 = oracle.Params(n1, n, t0=3.0, dt=0.1, axis_scale=s)
+    pc = oracle.CircleParams(n, seg=s[1], t0=3.0, dt=0.1)
+    c = random_circle(n, rng, 0.3)
+    full2 = np.zeros((n1, n), dtype=np.complex128)
+    full2[0, :] = c
+    out2 = oracle.run(full2, p2, steps)
+    outc = oracle.circle_run(c, pc, steps)
+    off = np.abs(out2[1:, :]).max()
+    return max(np.abs(out2[0, :] - outc).max() / np.abs(outc).max(), off)
+
+
+def pin_circle_k0_parseval(n=48, seed=52, dt=0.3):
+    """k = 0 has sigma = 0, so one step adds dt c sum_l kappa_l^2 |Phi_l|^2 to Phi~_0."""
+    rng = np.random.default_rng(seed)
+    p = oracle.CircleParams(n, seg=1.3, t0=4.0, dt=dt)
+    full = random_circle(n, rng, 0.2)
+    out = oracle.circle_step(full, p, 0)
+    t = p.t0
+    kap = p.seg * oracle.wavenumbers(n)
+    want = full[0].real + dt / (2 * t * t) * float((kap * kap * np.abs(full) ** 2).sum())
+    return abs(out[0] - want) / abs(want)
+
+
+def pin_circle_convergence(n=24, seed=53, T=1.0, t0=2.0, amp=0.4):
+    """Integrating-factor Euler converges at first order to a DOP853 solution
+    of the ODE written with the literal sum (errors at 20, 40, 80 steps)."""
+    from scipy.integrate import solve_ivp
+    rng = np.random.default_rng(seed)
+    K = oracle.truncation(n)
+    c0 = random_circle(n, rng, amp)
+    ks = np.arange(-K, K + 1)
+
+    def rhs(t, y):
+        ph = y[: 2 * K + 1] + 1j * y[2 * K + 1:]
+        out = np.zeros(2 * K + 1, dtype=np.complex128)
+        for a, k in enumerate(ks):
+            acc = 0j
+            for b, l in enumerate(ks):
+                if abs(k - l) <= K:
+                    acc += l * (k - l) * ph[b] * ph[(k - l) + K]
+            sig = -k * k / t ** 2 + 0.8 * abs(k) / (2 * t)
+            out[a] = sig * ph[a] - acc / (2 * t * t)
+        return np.concatenate([out.real, out.imag])
+
+    y0 = np.array([c0[k % n] for k in ks])
+    sol = solve_ivp(rhs, (t0, t0 + T), np.concatenate([y0.real, y0.imag]), method="DOP853", rtol=1e-12, atol=1e-14)
+    ref = sol.y[: 2 * K + 1, -1] + 1j * sol.y[2 * K + 1:, -1]
+    errs = []
+    for steps in (20, 40, 80):
+        p = oracle.CircleParams(n, t0=t0, dt=T / steps)
+        out = oracle.circle_run(c0, p, steps)
+        errs.append(np.abs(np.array([out[k % n] for k in ks]) - ref).max() / np.abs(ref).max())
+    return errs
+
+
+def pin_circle_diagnostics(n=128, k=3, a=0.4, psi=0.2, mean=0.01, nstep=2):
+    """Single cosine: mean radius r0 + mean, <Phi_t> = a^2 kappa^2 / (4 r0^2),
+    length excess the series of <sqrt(1 + b sin^2) - 1>, b = a^2 kappa^2 / r0^2."""
+    p = oracle.CircleParams(n, seg=1.0, t0=3.0, dt=0.5)
+    full = np.zeros(n, dtype=np.complex128)
+    full[k] = 0.5 * a * np.exp(1j * psi)
+    full[-k] = np.conj(full[k])
+    full[0] = mean
+    r = 3.0 + nstep * 0.5
+    rbar, vel, exc = oracle.circle_diagnostics(full, p, nstep)
+    kap = float(k)
+    b = a * a * kap * kap / (r * r)
+    return max(abs(rbar - (r + mean)) / (r + mean), abs(vel - a * a * kap * kap / (4 * r * r)) / (a * a * kap * kap / (4 * r * r)),
+               abs(exc - area_series(b)) / area_series(b))
