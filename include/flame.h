@@ -302,6 +302,52 @@ int flame_set_graph_steps(flame_plan plan, int32_t steps);
  * waiting for the plan's stream. */
 int flame_destroy(flame_plan plan);
 
+/* Circular (two-dimensional) flames. Section 2 compares the spherical flames
+ * with circular ones but gives only Eq. (1); the library takes for them the
+ * one-dimensional form of Eq. (1), i.e. Eq. (1) on the modes k1 = 0 (a set
+ * the equation maps into itself), for the perturbation Phi(phi, t) of a
+ * circle of radius r0(t) = t:
+ *   dPhi~_k/dt = (-kappa_k^2/r0^2 + gamma |kappa_k|/(2 r0)) Phi~_k
+ *                - 1/(2 r0^2) sum_l kappa_l kappa_{k-l} Phi~_l Phi~_{k-l},
+ * kappa_k = seg k, truncated to |k| <= K = n/4 - 1 and evaluated on n points
+ * (the augmented-array rule of Section 3), stepped by integrating-factor
+ * Euler with Im Phi~_0 = 0 after each step, like flame_step.
+ *
+ * State of one circle: complex64 spec[k], k = 0 .. K (n/4 entries; the k < 0
+ * half follows from Phi~(-k) = conj(Phi~(k)); Im spec[0] must be 0). A batch
+ * is n_circles such arrays back to back (dev, caller-owned). The calls need
+ * no plan and no workspace: every circle's spectrum stays in registers
+ * during a launch, and the twiddles are computed on the device. */
+typedef struct {
+  int32_t n;        /* points per circle: a power of two in [16, 8192] */
+  double gamma;     /* density contrast, >= 0 */
+  double seg;       /* segment integer (1: the whole circle), > 0 */
+  double t0;        /* time of step index 0, > 0 */
+  double dt;        /* time step, > 0 */
+} flame_circle_desc;
+
+/* Bytes of one circle's state (n/4 complex64). */
+int flame_circle_state_bytes(const flame_circle_desc* desc, size_t* bytes);
+
+/* Advance every circle of the batch `states` (dev, n_circles states, 8-byte
+ * aligned) from step index n (time t0 + n dt) by nsteps >= 0 steps, in
+ * place, on hip_stream. Circles 2c and 2c + 1 are stepped as a pair that
+ * shares one complex transform: results do not depend on the batch's size or
+ * order beyond rounding, and are reproducible bit for bit for a fixed batch,
+ * but a circle whose state turns non-finite also spoils its partner. */
+int flame_circle_step(const flame_circle_desc* desc, int32_t n_circles, void* states, int64_t n, int32_t nsteps,
+                      void* hip_stream);
+
+/* Averages of each circle at step index n, in double (dev out4, 4 doubles
+ * per circle): [0] mean radius r0 + Re Phi~_0, [1] averaged velocity
+ * <Phi_t> = dPhi~_0/dt = sum_k w_k kappa_k^2 |Phi~_k|^2 / (2 r0^2) (w = 1 at
+ * k = 0, 2 elsewhere), [2] length excess: the grid mean of sqrt(1 + x) - 1,
+ * x = Phi_phi^2 / r0^2 (kappa scaling), as x / (1 + sqrt(1 + x)), [3] 1 if
+ * every stored coefficient is finite, else 0 (non-finite coefficients enter
+ * the averages as zero, so that they do not reach the partner circle's). */
+int flame_circle_diagnostics(const flame_circle_desc* desc, int32_t n_circles, const void* states, int64_t n,
+                             double* out4, void* hip_stream);
+
 /* Allocation-free stepping, for callers that cannot allocate device memory
  * or build a plan (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc). Advances one flame described by `desc`

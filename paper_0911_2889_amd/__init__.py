@@ -6,4 +6,4 @@ The compute path is the in-tree library libflamefront.so; importing the
 classes below requires it to be built (``python -m paper_0911_2889_amd.build``).
 """
 
-from .sim import FlameEnsemble, FlameSim, flame_area  # noqa: F401
+from .sim import CircleBatch, FlameEnsemble, FlameSim, flame_area  # noqa: F401

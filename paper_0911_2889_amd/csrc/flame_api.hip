@@ -539,6 +539,81 @@ extern "C" {
 
 const char* flame_last_error(void) { return g_last_error.c_str(); }
 
+// ------------------------------------------------------------ circular flames
+
+static int check_circle(const flame_circle_desc* d, int* logn) {
+  if (!d) return fail(FLAME_ERR_INVALID_ARG, "null flame_circle_desc");
+  const int l = ilog2_exact(d->n);
+  if (l < 0 || l < flame::kMinLog || l > flame::kMaxLog)
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "circle of %d points: a power of two in [16, 8192]", d->n);
+  if (!(std::isfinite(d->gamma) && d->gamma >= 0.0)) return fail(FLAME_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+  if (!(std::isfinite(d->seg) && d->seg > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "seg must be > 0");
+  if (!(std::isfinite(d->t0) && d->t0 > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "t0 must be > 0");
+  if (!(std::isfinite(d->dt) && d->dt > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "dt must be > 0");
+  if (logn) *logn = l;
+  return FLAME_OK;
+}
+
+static flame::CircleDev circle_dev(const flame_circle_desc* d, int32_t n_circles, void* states) {
+  flame::CircleDev cd;
+  std::memset(&cd, 0, sizeof cd);
+  cd.S = static_cast<float2*>(states);
+  cd.n_circles = n_circles;
+  cd.seg = (float)d->seg;
+  cd.gamma = (float)d->gamma;
+  cd.t0 = d->t0;
+  cd.dt = d->dt;
+  return cd;
+}
+
+int flame_circle_state_bytes(const flame_circle_desc* desc, size_t* bytes) {
+  if (!bytes) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  const int rc = check_circle(desc, nullptr);
+  if (rc) return rc;
+  *bytes = (size_t)(desc->n / 4) * sizeof(float2);
+  return FLAME_OK;
+}
+
+// Steps per launch: a launch keeps every spectrum in registers; longer runs
+// are split so that no single launch runs for long.
+constexpr int kCircleStepsPerLaunch = 2000;
+
+int flame_circle_step(const flame_circle_desc* desc, int32_t n_circles, void* states, int64_t n, int32_t nsteps,
+                      void* hip_stream) {
+  int logn = 0;
+  int rc = check_circle(desc, &logn);
+  if (rc) return rc;
+  if (n_circles < 0 || nsteps < 0) return fail(FLAME_ERR_INVALID_ARG, "n_circles and nsteps must be >= 0");
+  if (n_circles == 0 || nsteps == 0) return FLAME_OK;
+  if (!states) return fail(FLAME_ERR_INVALID_ARG, "null states pointer");
+  if (reinterpret_cast<uintptr_t>(states) % 8) return fail(FLAME_ERR_INVALID_ARG, "states must be 8-byte aligned");
+  const flame::CircleDev cd = circle_dev(desc, n_circles, states);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int32_t done = 0; done < nsteps;) {
+    const int k = std::min(kCircleStepsPerLaunch, nsteps - done);
+    if (!flame::launch_circle_step(logn, cd, n + done, k, st))
+      return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no circle kernel for %d points", desc->n);
+    done += k;
+  }
+  return last_launch("circle step launch");
+}
+
+int flame_circle_diagnostics(const flame_circle_desc* desc, int32_t n_circles, const void* states, int64_t n,
+                             double* out4, void* hip_stream) {
+  int logn = 0;
+  int rc = check_circle(desc, &logn);
+  if (rc) return rc;
+  if (n_circles < 0) return fail(FLAME_ERR_INVALID_ARG, "n_circles must be >= 0");
+  if (n_circles == 0) return FLAME_OK;
+  if (!states || !out4) return fail(FLAME_ERR_INVALID_ARG, "null states or output pointer");
+  if (reinterpret_cast<uintptr_t>(states) % 8 || reinterpret_cast<uintptr_t>(out4) % 8)
+    return fail(FLAME_ERR_INVALID_ARG, "states and out4 must be 8-byte aligned");
+  const flame::CircleDev cd = circle_dev(desc, n_circles, const_cast<void*>(states));
+  if (!flame::launch_circle_diag(logn, cd, n, out4, static_cast<hipStream_t>(hip_stream)))
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "no circle kernel for %d points", desc->n);
+  return last_launch("circle diagnostics launch");
+}
+
 int flame_step_noalloc(const flame_desc* desc, void* state, int64_t n, int32_t nsteps, void* hip_stream) {
   Sizes s{};
   int rc = check_desc(desc, &s);

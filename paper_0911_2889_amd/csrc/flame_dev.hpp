@@ -57,6 +57,17 @@ struct FlameDev {
   double t0, dt;
 };
 
+// A batch of circular flames (the one-dimensional form of Eq. (1)) of one
+// grid: spectra S[c][k], k = 0 .. N/4 - 1, complex64, caller-owned.
+struct CircleDev {
+  float2* S;
+  int n_circles;
+  float seg;     // segment integer: kappa_k = seg k
+  float gamma;
+  int pad_;
+  double t0, dt;
+};
+
 // Register shape of a length-N transform with PTS points per thread: the
 // power-of-two plans (8 or 16 points), or, for PTS = 12, the length-3N/4
 // transform of a product grid in the 12-point plan (ff::Shape12), which also

@@ -56,6 +56,12 @@ void launch_row(int logn2, int mode, int groups, int nfl, hipStream_t st, const 
                 const float* in, float* out, int pts = ff::kPts, hipEvent_t ev_start = nullptr,
                 hipEvent_t ev_stop = nullptr, bool nt = false);
 
+// Circular flames (circle_kernels.hip): nsteps steps of every circle of the
+// batch in one launch, or their diagnostics (4 doubles per circle); false if
+// the length 2^logn has no kernel.
+bool launch_circle_step(int logn, const CircleDev& d, long long n, int nsteps, hipStream_t st);
+bool launch_circle_diag(int logn, const CircleDev& d, long long n, double* out, hipStream_t st);
+
 void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half);
 void launch_get_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, void* half);
 void launch_diag_spectral(hipStream_t st, const FlameDev* fl, int flame, int blocks, double* part);

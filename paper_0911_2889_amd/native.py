@@ -25,6 +25,7 @@ EXPORTS = (
     "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
     "flame_get_product_grid", "flame_set_streaming_stores", "flame_get_streaming_stores", "flame_set_r0_table",
     "flame_set_forcing", "flame_autotune", "flame_destroy", "flame_step_noalloc",
+    "flame_circle_state_bytes", "flame_circle_step", "flame_circle_diagnostics",
     "flame_last_error",
 )
 
@@ -40,6 +41,16 @@ class FlameDesc(ctypes.Structure):
         ("axis_scale", ctypes.c_double * 2),
         ("r0_law", ctypes.c_int32),
         ("integrator", ctypes.c_int32),
+    ]
+
+
+class CircleDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("seg", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("dt", ctypes.c_double),
     ]
 
 
@@ -92,6 +103,9 @@ def load():
         "flame_timing_end": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)],
         "flame_destroy": [P],
         "flame_step_noalloc": [desc_p, P, i64, i32, P],
+        "flame_circle_state_bytes": [ctypes.POINTER(CircleDesc), ctypes.POINTER(sz)],
+        "flame_circle_step": [ctypes.POINTER(CircleDesc), i32, P, i64, i32, P],
+        "flame_circle_diagnostics": [ctypes.POINTER(CircleDesc), i32, P, i64, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -133,3 +147,10 @@ def workspace_bytes(descs):
     out = ctypes.c_size_t()
     check(load().flame_workspace_bytes(arr, len(descs), ctypes.byref(out)))
     return out.value
+
+
+def make_circle_desc(n, gamma=0.8, seg=1.0, t0=200.0, dt=0.25):
+    d = CircleDesc()
+    d.n = int(n)
+    d.gamma, d.seg, d.t0, d.dt = float(gamma), float(seg), float(t0), float(dt)
+    return d

@@ -305,3 +305,49 @@ def flame_area(phi0, sim, nsteps, checkpoint_every=50, flame=0):
     the library's adjoint (states are checkpointed every `checkpoint_every`
     steps and recomputed in the backward pass). The sim's state is overwritten."""
     return _FlameArea.apply(phi0, sim, int(nsteps), int(checkpoint_every), int(flame))
+
+
+class CircleBatch:
+    """A batch of circular flames of one grid (the one-dimensional form of
+    Eq. (1)): CircleBatch(n, count, gamma=0.8, seg=1.0, t0=200.0, dt=0.25).
+    The spectra live in one complex64 tensor of shape (count, n/4) on the
+    device (k = 0 .. n/4 - 1); every step runs in the HIP library."""
+
+    def __init__(self, n, count, device="cuda", **kw):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the flame stepper needs a ROCm GPU (torch.cuda is unavailable)")
+        self.lib = native.load()
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.desc = native.make_circle_desc(n, **kw)
+        nb = ctypes.c_size_t()
+        native.check(self.lib.flame_circle_state_bytes(ctypes.byref(self.desc), ctypes.byref(nb)))
+        self.count = int(count)
+        self.states = torch.zeros((self.count, nb.value // 8), dtype=torch.complex64, device=self.device)
+        self.n = 0
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_spectra(self, spectra, n=0):
+        """Load the spectra (count x n/4 complex, k = 0 .. n/4 - 1) at step index n."""
+        s = _dev_tensor(spectra, torch.complex64, self.device)
+        if tuple(s.shape) != tuple(self.states.shape):
+            raise ValueError(f"spectra have shape {tuple(s.shape)}, expected {tuple(self.states.shape)}")
+        self.states.copy_(s)
+        self.n = int(n)
+
+    def step(self, nsteps=1):
+        native.check(self.lib.flame_circle_step(ctypes.byref(self.desc), self.count,
+                                                ctypes.c_void_p(self.states.data_ptr()), self.n, int(nsteps),
+                                                self._stream()))
+        self.n += int(nsteps)
+
+    def diagnostics(self, out=None):
+        """(count, 4) float64 tensor: mean radius, <Phi_t>, length excess, finite flag."""
+        buf = out if out is not None else torch.empty((self.count, 4), dtype=torch.float64, device=self.device)
+        native.check(self.lib.flame_circle_diagnostics(ctypes.byref(self.desc), self.count,
+                                                       ctypes.c_void_p(self.states.data_ptr()), self.n,
+                                                       ctypes.c_void_p(buf.data_ptr()), self._stream()))
+        return buf

@@ -1,0 +1,153 @@
+"""Circular flames (the one-dimensional form of Eq. (1)) on the GPU, through
+the C ABI, against the FP64 circular oracle, and against the spherical step
+on states confined to k1 = 0."""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def flame():
+    import paper_0911_2889_amd
+    return paper_0911_2889_amd
+
+
+def circle_spectra(n, count, seed, amp):
+    """count seeded spectra k = 0 .. n/4 - 1 (complex64): amp xi_k / k over
+    every retained mode, random phases, Im of k = 0 zero."""
+    rng = np.random.default_rng(seed)
+    K = oracle.truncation(n)
+    k = np.arange(1, K + 1)
+    out = np.zeros((count, K + 1), dtype=np.complex64)
+    for c in range(count):
+        a = amp * rng.standard_normal(K) / k
+        psi = rng.uniform(0.0, 2.0 * np.pi, K)
+        out[c, 1:] = (0.5 * a * np.exp(1j * psi)).astype(np.complex64)
+    return out
+
+
+def rel_l2_circle(got, ref):
+    w = np.full(ref.shape, 2.0)
+    w[0] = 1.0
+    return float(np.sqrt((w * np.abs(got - ref) ** 2).sum() / (w * np.abs(ref) ** 2).sum()))
+
+
+def oracle_circle(spec, p, steps, n_start=0):
+    full = oracle.half_to_circle(spec.astype(np.complex128), p.n)
+    return oracle.circle_to_half(oracle.circle_run(full, p, steps, n_start))
+
+
+@pytest.mark.parametrize("n,count", [(16, 3), (64, 4), (256, 7), (1024, 2), (4096, 5), (8192, 1)])
+def test_circles_match_oracle(flame, n, count):
+    amp, t0, dt = 0.3, 5.0, 0.1
+    spec = circle_spectra(n, count, seed=n + count, amp=amp)
+    batch = flame.CircleBatch(n, count, gamma=0.8, seg=1.0, t0=t0, dt=dt)
+    batch.set_spectra(spec, n=3)
+    batch.step(1)
+    one = batch.states.cpu().numpy()
+    batch.step(49)
+    fifty = batch.states.cpu().numpy()
+    p = oracle.CircleParams(n, gamma=0.8, seg=1.0, t0=t0, dt=dt)
+    for c in range(count):
+        r1 = oracle_circle(spec[c], p, 1, 3)
+        r50 = oracle_circle(spec[c], p, 50, 3)
+        assert rel_l2_circle(r1, spec[c].astype(np.complex128)) > 1e-4
+        assert rel_l2_circle(one[c], r1) < 1e-6, (c, rel_l2_circle(one[c], r1))
+        assert rel_l2_circle(fifty[c], r50) < 1e-5, (c, rel_l2_circle(fifty[c], r50))
+
+
+def test_circle_segment_and_partner_independence(flame):
+    """seg != 1, and the same circle stepped beside different partners (pairs
+    share one transform) agrees to rounding."""
+    n = 512
+    spec = circle_spectra(n, 6, seed=9, amp=0.2)
+    p = oracle.CircleParams(n, gamma=0.8, seg=2.0, t0=8.0, dt=0.05)
+    outs = []
+    for order in ([0, 1, 2, 3, 4, 5], [5, 0, 4, 3, 2, 1]):
+        batch = flame.CircleBatch(n, 6, gamma=0.8, seg=2.0, t0=8.0, dt=0.05)
+        batch.set_spectra(spec[order])
+        batch.step(30)
+        got = batch.states.cpu().numpy()
+        outs.append({o: got[i] for i, o in enumerate(order)})
+    for c in range(6):
+        ref = oracle_circle(spec[c], p, 30)
+        assert rel_l2_circle(outs[0][c], ref) < 1e-5
+        assert rel_l2_circle(outs[0][c], outs[1][c]) < 1e-6
+
+
+def test_circles_are_the_sphere_step_on_k1_zero_states(flame):
+    """The spherical step (axis scales s1, s2) on a state with only k1 = 0
+    modes against the circular step with seg = s2: same k1 = 0 row to
+    rounding, and the other modes stay at rounding level."""
+    n1, n2, s = 64, 256, (1.3, 0.7)
+    spec = circle_spectra(n2, 1, seed=21, amp=0.2)[0]
+    sim = flame.FlameSim(n1, n2, gamma=0.8, theta_pi=1.0, t0=5.0, dt=0.1, axis_scale=s)
+    half = np.zeros(sim.half_shape(), dtype=np.complex64)
+    K1 = oracle.truncation(n1)
+    half[K1, :] = spec
+    sim.set_spectrum(half)
+    sim.step(20)
+    got2 = sim.spectrum().cpu().numpy()
+    batch = flame.CircleBatch(n2, 1, gamma=0.8, seg=s[1], t0=5.0, dt=0.1)
+    batch.set_spectra(spec[None, :])
+    batch.step(20)
+    got1 = batch.states.cpu().numpy()[0]
+    assert rel_l2_circle(got2[K1, :], got1) < 2e-6
+    off = np.abs(np.delete(got2, K1, axis=0)).max()
+    assert off < 1e-6 * np.abs(got1).max()
+
+
+def test_circle_diagnostics_match_oracle(flame):
+    n, count = 1024, 3
+    spec = circle_spectra(n, count, seed=31, amp=0.5)
+    batch = flame.CircleBatch(n, count, gamma=0.8, seg=1.0, t0=4.0, dt=0.1)
+    batch.set_spectra(spec, n=2)
+    batch.step(10)
+    d = batch.diagnostics().cpu().numpy()
+    got = batch.states.cpu().numpy()
+    p = oracle.CircleParams(n, gamma=0.8, seg=1.0, t0=4.0, dt=0.1)
+    for c in range(count):
+        ref = oracle.circle_diagnostics(oracle.half_to_circle(got[c].astype(np.complex128), n), p, 12)
+        assert abs(d[c, 0] - ref[0]) <= 1e-12 * ref[0]
+        assert abs(d[c, 1] - ref[1]) <= 2e-5 * ref[1]
+        assert abs(d[c, 2] - ref[2]) <= 2e-5 * ref[2]
+        assert d[c, 3] == 1.0
+    bad = batch.states.clone()
+    bad[1, 5] = complex(float("nan"), 0.0)
+    batch.states.copy_(bad)
+    d = batch.diagnostics().cpu().numpy()
+    assert d[1, 3] == 0.0 and d[0, 3] == 1.0 and d[2, 3] == 1.0
+
+
+def test_long_circle_runs_split_into_launches_bitwise(flame):
+    """Steps beyond one launch's share continue the same computation."""
+    n = 256
+    spec = circle_spectra(n, 2, seed=41, amp=0.01)
+    a = flame.CircleBatch(n, 2, t0=200.0, dt=0.05)
+    a.set_spectra(spec)
+    a.step(2500)
+    b = flame.CircleBatch(n, 2, t0=200.0, dt=0.05)
+    b.set_spectra(spec)
+    b.step(2000)
+    b.step(500)
+    got_a, got_b = a.states.cpu().numpy(), b.states.cpu().numpy()
+    assert np.isfinite(got_a).all()
+    assert np.array_equal(got_a, got_b)
+
+
+def test_circle_errors(flame):
+    import ctypes
+    lib = flame.native.load()
+    st = torch.zeros(8, dtype=torch.complex64, device="cuda")
+    for d, code in ((flame.native.make_circle_desc(100), -4), (flame.native.make_circle_desc(8), -4),
+                    (flame.native.make_circle_desc(64, dt=0.0), -1), (flame.native.make_circle_desc(64, seg=0.0), -1)):
+        assert lib.flame_circle_step(ctypes.byref(d), 1, ctypes.c_void_p(st.data_ptr()), 0, 1, None) == code
+    ok = flame.native.make_circle_desc(32)
+    assert lib.flame_circle_step(ctypes.byref(ok), 1, ctypes.c_void_p(st.data_ptr()), 0, -1, None) == -1
+    assert lib.flame_circle_step(ctypes.byref(ok), 1, None, 0, 1, None) == -1
