@@ -20,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CIRCLE_SOURCES = ("paper_0911_2889_amd/csrc/circle_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
+                  "paper_0911_2889_amd/csrc/kernel_common.hpp")
 KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
                   "paper_0911_2889_amd/csrc/flame_dev.hpp", "paper_0911_2889_amd/csrc/kernel_common.hpp")
 
@@ -67,8 +69,31 @@ def measured_traffic(kernel, workload, pts, rows, streaming=False):
     return None
 
 
-def cpu_oracle_baseline(w, half, seconds):
-    """Time the FP64 oracle on the host on a bounded sample of the same workload."""
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def circle_record(path=os.path.join(ROOT, "profiles", "circle_kernel_circles4096x2048_valu.json")):
+    """VALU instructions per wave and step of the circle kernel from the
+    committed counter record, if it was taken on the current circle sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for rel in CIRCLE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return rec if rec.get("source_digest") == h.hexdigest()[:16] else None
+
+
+def cpu_oracle_baseline(w, half, seconds, workers=None):
+    """Time the FP64 oracle on the host on a bounded sample of the same
+    workload: numpy's single-threaded transforms (workers None), or scipy.fft
+    with `workers` threads (oracle.set_fft_workers)."""
     import numpy as np
 
     import oracle
@@ -76,26 +101,26 @@ def cpu_oracle_baseline(w, half, seconds):
     p = oracle.Params(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
     cur = oracle.run(oracle.half_to_full(half.astype(np.complex128), w.n1, w.n2), p, 0)
     steps = 0
-    t0 = time.perf_counter()
-    while True:
-        cur = oracle.step(cur, p, steps)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or steps >= w.steps:
-            break
+    oracle.set_fft_workers(workers)
     try:
-        affinity = len(os.sched_getaffinity(0))
-    except AttributeError:
-        affinity = None
+        t0 = time.perf_counter()
+        while True:
+            cur = oracle.step(cur, p, steps)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= seconds or steps >= w.steps:
+                break
+    finally:
+        oracle.set_fft_workers(None)
+    fft = "single-threaded numpy pocketfft" if workers is None else f"scipy.fft, {workers} workers"
     return {
         "value": w.points * steps / el,
         "unit": "point-steps/s",
-        "cores": 1,
+        "cores": 1 if workers is None else workers,
         "kind": "oracle",
-        "sample": f"first {steps} steps of {w.name} from its initial condition, FP64 numpy "
-                  f"(single-threaded pocketfft), {el:.1f} s",
+        "sample": f"first {steps} steps of {w.name} from its initial condition, FP64 ({fft}), {el:.1f} s",
         "host_cpu_count": os.cpu_count(),
-        "host_affinity": affinity,
+        "host_affinity": host_cores(),
     }, steps, oracle.full_to_half(cur, w.n1, w.n2)
 
 
@@ -323,6 +348,96 @@ def long_run_leg(n=8192, t_end=2600.0, dt=0.1, every_t=5.0, fits_from=(1500.0,))
     }
 
 
+# One wave-instruction per CU per clock (4 SIMDs x 16 lanes, wave64, FP32
+# not packed): the vector-ALU issue peak of 256 CUs at 2.4 GHz, and its FP32
+# rate (an FMA is 2 flops per lane).
+VALU_PEAK_INSTR_S = 256 * 2.4e9
+FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def circle_leg(n=4096, count=2048, steps=200, valu_per_wave_step=None):
+    """Batched circular flames (the one-dimensional Eq. (1)): `count` circles
+    of n points stepped `steps` times in one launch, timed with in-dispatch
+    order HIP events. Roofline: vector ALU (the spectra stay in registers).
+    valu_per_wave_step: VALU instructions per wave per step from the counter
+    record (profiles/circle_kernel_*.md), for the issue fraction."""
+    import math
+
+    import torch
+
+    import synth
+    from paper_0911_2889_amd import CircleBatch
+
+    b = CircleBatch(n, count, t0=200.0, dt=0.25)
+    spec = synth.circle_spectra(n, count, seed=7, amp=1e-3)
+    b.set_spectra(spec)
+    b.step(20)  # warm-up
+    b.set_spectra(spec)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    pairs = (count + 1) // 2
+    # nominal FFT flops: one inverse and one forward complex transform of n points per pair and step
+    flops = pairs * steps * 2 * 5.0 * n * math.log2(n)
+    out = {"circles": count, "points": n, "steps": steps, "ms": ms, "us_per_step": ms * 1e3 / steps,
+           "point_steps_per_s": n * count * steps / (ms * 1e-3),
+           "nominal_fft_tflops": flops / (ms * 1e-3) / 1e12,
+           "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
+           "nominal_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+    if valu_per_wave_step:
+        g = n // 16
+        per_wg = max(1, 256 // g)  # circle pairs per workgroup
+        waves = -(-pairs // per_wg) * (per_wg * g) // 64
+        rate = valu_per_wave_step * waves * steps / (ms * 1e-3)
+        out["valu_per_wave_step"] = valu_per_wave_step
+        out["valu_issue_frac"] = rate / VALU_PEAK_INSTR_S
+    return out
+
+
+def circle_long_run_leg(n=8192, count=64, t_end=4000.0, dt=0.1, every_t=5.0, fits_from=(1500.0, 2500.0)):
+    """Long run of circular flames (Section 2's comparison of spherical with
+    circular flames): `count` circles of n points from seeded modal noise of
+    amplitude 1e-3 at t0 = 200, gamma = 0.8, integrating-factor Euler,
+    averages every `every_t`; the batch-mean <Phi_t> fitted by
+    A (t - t*)^alpha over t >= each of fits_from. Qualitative: the paper
+    reports that circular flames settle to alpha = 1/4."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0911_2889_amd import CircleBatch
+
+    every = int(round(every_t / dt))
+    b = CircleBatch(n, count, t0=200.0, dt=dt)
+    b.set_spectra(synth.circle_spectra(n, count, seed=11, amp=1e-3))
+    nd = int(round((t_end - 200.0) / dt)) // every
+    diag = torch.zeros((nd, count, 4), dtype=torch.float64, device=b.device)
+    torch.cuda.synchronize()
+    t_wall = time.time()
+    for i in range(nd):
+        b.step(every)
+        b.diagnostics(out=diag[i])
+    torch.cuda.synchronize()
+    wall = time.time() - t_wall
+    d = diag.cpu().numpy()
+    ts = 200.0 + dt * every * np.arange(1, nd + 1)
+    ok = (d[:, :, 3] == 1).all(axis=1)
+    vel = d[:, :, 1].mean(axis=1)
+    stride = max(1, int(round(100.0 / every_t)))
+    return {
+        "setting": f"{count} circles, modal noise amp 1e-3 (seed 11), t0 200, gamma 0.8, f = 0, IF-Euler",
+        "points": n, "dt": dt, "t_end": t_end, "steps": nd * every, "wall_s": wall,
+        "point_steps_per_s_with_diagnostics": n * count * nd * every / wall,
+        "first_nonfinite_t": float(ts[~ok][0]) if (~ok).any() else None,
+        "series_every_100": {"t": ts[stride - 1::stride].tolist(), "velocity": vel[stride - 1::stride].tolist()},
+        "power_law_fits": [power_law_fit(ts[ok], vel[ok], t_from) for t_from in fits_from],
+    }
+
+
 def ensemble_leg(steps, graph_steps):
     """The batched ensemble (256 flames of three grids) stepped in graphs of
     graph_steps steps, and with direct launches, timed with HIP events."""
@@ -396,6 +511,10 @@ def main():
                     help="skip the long-horizon run (8192 x 8192, Heun, t = 200 .. 2600)")
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the checkpointed adjoint leg on 1024x2048 (0 skips it)")
+    ap.add_argument("--circle-steps", type=int, default=200,
+                    help="steps of the batched circular-flame leg (2048 circles of 4096 points; 0 skips it)")
+    ap.add_argument("--no-circle-long-run", action="store_true",
+                    help="skip the long run of 64 circular flames of 8192 points to t = 4000")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 5 times (calibrates HBM counters)")
     args = ap.parse_args()
@@ -428,18 +547,30 @@ def main():
     sim = FlameSim(w.n1, w.n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
     diag_buf = torch.zeros((max(1, args.steps // max(1, args.diag_every)) + 1, 4), dtype=torch.float64,
                            device=sim.device)
+    sim_graph_steps = [0]
 
-    def run_steps(k, time_kernels):
+    ran = {"graph_replays": 0, "direct_steps": 0, "diagnostics": 0}
+
+    def run_steps(k, time_kernels, count=None):
+        """k steps with the diagnostics every diag_every steps (counted from
+        the start of this call); `count` (a dict) receives what ran."""
         if time_kernels:
             sim.timing_begin()
         done, d = 0, 0
+        gs = sim_graph_steps[0]
         while done < k:
             chunk = min(args.diag_every - (done % args.diag_every), k - done)
             sim.step(chunk)
+            if count is not None:
+                reps = chunk // gs if gs else 0
+                count["graph_replays"] += reps
+                count["direct_steps"] += chunk - reps * gs
             done += chunk
             if done % args.diag_every == 0:
                 sim.diagnostics(out=diag_buf[d % diag_buf.shape[0]])
                 d += 1
+                if count is not None:
+                    count["diagnostics"] += 1
         return sim.timing_end() if time_kernels else None
 
     # points per thread of the step kernels chosen by the library's autotuner
@@ -457,9 +588,11 @@ def main():
     rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
     streaming = sim.streaming_stores(w.n1, w.n2)
 
-    # steps between diagnostics run as one hipGraph replay
-    graph_steps = 0 if args.no_graph else args.diag_every
+    # steps between diagnostics run as one hipGraph replay (a shorter timed
+    # region replays graphs of its own length)
+    graph_steps = 0 if args.no_graph else min(args.diag_every, max(1, args.steps))
     sim.set_graph_steps(graph_steps)
+    sim_graph_steps[0] = graph_steps
 
     # warm-up from the initial condition (instantiates the graph)
     sim.set_spectrum(half)
@@ -473,7 +606,7 @@ def main():
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
-    run_steps(args.steps, False)
+    run_steps(args.steps, False, ran)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
@@ -481,6 +614,7 @@ def main():
     # timed region 2: the same steps launched directly, every step kernel carrying
     # its own start/stop events -> per-kernel durations for the roofline
     sim.set_graph_steps(0)
+    sim_graph_steps[0] = 0
     sim.set_spectrum(half)
     sim.step(0)
     torch.cuda.synchronize()
@@ -509,7 +643,11 @@ def main():
         "config": {"workload": w.name, "grid": [w.n1, w.n2], "dt": w.dt, "t0": w.t0, "gamma": w.gamma,
                    "diagnostics_every": args.diag_every, "ic": f"{w.rule} modes, amp {w.amp}, seed {w.seed}",
                    "points_per_thread": {"col": pts[0], "row": pts[1]}, "product_rows": rows,
-                   "streaming_stores": streaming, "graph_steps": graph_steps},
+                   "product_cols": 3 * w.n2 // 4 if pts[1] == 12 else w.n2,
+                   "streaming_stores": streaming, "graph_steps": graph_steps,
+                   # what the timed region ran: graph replays of graph_steps steps, steps
+                   # launched directly, and diagnostics (due every diagnostics_every steps)
+                   "timed_region": dict(ran, steps=args.steps)},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom}_kernel",
@@ -544,6 +682,13 @@ def main():
     if not args.no_long_run:
         result["long_run"] = long_run_leg()
 
+    if args.circle_steps > 0:
+        rec = circle_record()
+        result["circles"] = circle_leg(steps=args.circle_steps,
+                                       valu_per_wave_step=rec.get("valu_per_wave_step") if rec else None)
+    if not args.no_circle_long_run:
+        result["circle_long_run"] = circle_long_run_leg()
+
     if args.adjoint_steps > 0:
         result["adjoint"] = adjoint_leg(args.adjoint_steps, 50)
     if args.ensemble_steps > 0:
@@ -552,6 +697,7 @@ def main():
     if not args.no_cpu:
         base, nref, ref = cpu_oracle_baseline(w, half, args.cpu_seconds)
         result["cpu_baseline"] = base
+        result["cpu_baseline_all_cores"] = cpu_oracle_baseline(w, half, args.cpu_seconds, workers=host_cores())[0]
         sim.set_spectrum(half)
         sim.step(nref)
         got = sim.spectrum().cpu().numpy().astype(np.complex128)

@@ -33,7 +33,7 @@ from .spectral import (  # noqa: F401
 )
 from .model import (  # noqa: F401
     Params, step_scalars, growth_exponent, convolution_sum, rhs, symmetrise,
-    step, run,
+    step, run, set_fft_workers,
 )
 from .diagnostics import diagnostics  # noqa: F401
 from .adjoint import (  # noqa: F401

@@ -115,6 +115,25 @@ def growth_exponent(p, n):
     return -kap2 * i2 + 0.5 * p.gamma * np.sqrt(kap2) * i1
 
 
+# Threads of the one-dimensional transforms of convolution_sum: None uses
+# numpy's (single-threaded) FFT; an integer uses scipy.fft with that many
+# workers (the same transforms, for timing the oracle on all host cores).
+_FFT_WORKERS = None
+
+
+def set_fft_workers(workers):
+    """None: numpy.fft (the default); k: scipy.fft with k worker threads."""
+    global _FFT_WORKERS
+    _FFT_WORKERS = None if workers is None else int(workers)
+
+
+def _fft(x, axis, inverse):
+    if _FFT_WORKERS is None:
+        return np.fft.ifft(x, axis=axis) if inverse else np.fft.fft(x, axis=axis)
+    import scipy.fft
+    return (scipy.fft.ifft if inverse else scipy.fft.fft)(x, axis=axis, workers=_FFT_WORKERS)
+
+
 def convolution_sum(full, p):
     """sum_l kappa_l . kappa_{k-l} Phi~_l Phi~_{k-l} for every k in the box.
 
@@ -127,13 +146,13 @@ def convolution_sum(full, p):
     """
     n1, n2 = p.n1, p.n2
     k1, k2 = p.kappa()
-    h1 = np.fft.ifft(k1 * full, axis=0) * n1
-    h2 = np.fft.ifft(k2 * full, axis=0) * n1
-    h1 = np.fft.ifft(h1, axis=1) * n2
-    h2 = np.fft.ifft(h2, axis=1) * n2
+    h1 = _fft(k1 * full, 0, True) * n1
+    h2 = _fft(k2 * full, 0, True) * n1
+    h1 = _fft(h1, 1, True) * n2
+    h2 = _fft(h2, 1, True) * n2
     prod = h1 * h1 + h2 * h2
-    back = np.fft.fft(prod, axis=1) / n2
-    back = np.fft.fft(back, axis=0) / n1
+    back = _fft(prod, 1, False) / n2
+    back = _fft(back, 0, False) / n1
     return back * box_mask(n1, n2)
 
 

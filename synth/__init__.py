@@ -6,6 +6,7 @@ path and the oracle can consume what it makes.
 """
 
 from .ics import (  # noqa: F401
-    ENSEMBLE_GROUPS, WORKLOADS, Workload, ensemble_members, forcing_spectrum, half_dims, mode_table,
+    ENSEMBLE_GROUPS, WORKLOADS, Workload, circle_spectra, ensemble_members, forcing_spectrum, half_dims,
+    mode_table,
     modal_spectrum, physical_noise, workload_spectrum,
 )

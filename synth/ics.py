@@ -169,3 +169,21 @@ def forcing_spectrum(w, amp=1e-5, seed=None):
     canonical half array, complex64."""
     k1, k2, a, psi = mode_table(w.n1, w.n2, "all", amp, -1.0, w.seed + 7919 if seed is None else seed)
     return modal_spectrum(w.n1, w.n2, k1, k2, a, psi)
+
+
+def circle_spectra(n, count, seed, amp, power=-1.0):
+    """Seeded initial spectra of `count` circular flames of n points: for each
+    circle in turn, amplitudes xi_k ~ N(0, 1) for k = 1 .. K, then phases
+    psi_k ~ U(0, 2 pi), with generator numpy.random.default_rng(seed);
+    Phi~_k = (a_k / 2) exp(i psi_k), a_k = amp xi_k k^power (the cosine
+    modes a_k cos(k phi + psi_k)), Phi~_0 = 0. Returns a complex64 array of
+    shape (count, K + 1), K = floor((n - 1)/4), entry k = 0 .. K."""
+    rng = np.random.default_rng(seed)
+    K = (n - 1) // 4
+    k = np.arange(1, K + 1, dtype=np.float64)
+    out = np.zeros((count, K + 1), dtype=np.complex64)
+    for c in range(count):
+        a = amp * rng.standard_normal(K) * k ** power
+        psi = rng.uniform(0.0, 2.0 * np.pi, K)
+        out[c, 1:] = (0.5 * a * np.exp(1j * psi)).astype(np.complex64)
+    return out

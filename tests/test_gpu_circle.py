@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -19,17 +20,7 @@ def flame():
 
 
 def circle_spectra(n, count, seed, amp):
-    """count seeded spectra k = 0 .. n/4 - 1 (complex64): amp xi_k / k over
-    every retained mode, random phases, Im of k = 0 zero."""
-    rng = np.random.default_rng(seed)
-    K = oracle.truncation(n)
-    k = np.arange(1, K + 1)
-    out = np.zeros((count, K + 1), dtype=np.complex64)
-    for c in range(count):
-        a = amp * rng.standard_normal(K) / k
-        psi = rng.uniform(0.0, 2.0 * np.pi, K)
-        out[c, 1:] = (0.5 * a * np.exp(1j * psi)).astype(np.complex64)
-    return out
+    return synth.circle_spectra(n, count, seed, amp)
 
 
 def rel_l2_circle(got, ref):

@@ -292,3 +292,21 @@ def test_heun_with_time_dependent_forcing_converges_at_second_order():
         errs.append(np.linalg.norm(oracle.run(full0, p, nsteps) - ref) / np.linalg.norm(ref))
     for a, b in zip(errs, errs[1:]):
         assert 3.4 < a / b < 4.6, errs
+
+
+def test_threaded_transforms_match_the_default_to_round_off():
+    """set_fft_workers (timing the oracle on all host cores) computes the same
+    step as the default single-threaded transforms, up to rounding."""
+    import os
+    rng = np.random.default_rng(12)
+    n1, n2 = 64, 96
+    p = oracle.Params(n1, n2, t0=5.0, dt=0.2)
+    full = oracle.symmetrise(pins.dict_to_full(pins.random_hermitian(n1, n2, rng, 0.3), n1, n2))
+    ref = oracle.run(full, p, 3)
+    try:
+        oracle.set_fft_workers(os.cpu_count() or 2)
+        got = oracle.run(full, p, 3)
+    finally:
+        oracle.set_fft_workers(None)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert pins.pin_convolution_direct(16, 24, seed=40) < 1e-12
