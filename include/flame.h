@@ -29,8 +29,10 @@
  *    queue device work do not synchronise.
  *  - A plan is not thread-safe; use one plan per stream.
  *
- * Supported grids: N1 and N2 powers of two with 16 <= N_i <= 8192 (flame_init
+ * Supported grids: N1 and N2 powers of two with 16 <= N_i <= 16384 (flame_init
  * also checks that every kernel of the grid fits the device's LDS per workgroup).
+ * A 16384-point transform runs on 1024 threads of one workgroup with 16 (or,
+ * for 3/4 of the length, 12) points each; 8 points per thread stop at 8192.
  *
  * State layout (internal to the stepper but documented for checkpointing):
  * complex64 S[m][s], m = k2 in [0, N2/4), s in [0, N1/2) with k1 = s - N1/4;
@@ -63,7 +65,7 @@ typedef struct flame_plan_s* flame_plan;
 /* Problem description of one flame (Section 2: gamma = 0.8, t0 = 200 in the
  * paper's runs; theta_pi is the segment integer; dt is the fixed step). */
 typedef struct {
-  int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 8192] */
+  int32_t n1, n2;         /* physical grid, theta x phi; powers of two in [16, 16384] */
   double gamma;           /* density contrast 1 - rho_b/rho_u, >= 0 */
   double theta_pi;        /* segment integer theta_pi, > 0 */
   double t0;              /* time of step index 0, > 0 */
@@ -88,8 +90,8 @@ int flame_workspace_bytes(const flame_desc* descs, int32_t n_flames, size_t* byt
  * once to float) and copies them into ws on the stream. The states are not
  * initialised: call flame_set_spectrum or flame_set_state next. Fails with
  * FLAME_ERR_UNSUPPORTED_SIZE if a kernel of some flame's grid needs more LDS
- * per workgroup than the device offers (the 8192-point transforms use up to
- * 104 KB). */
+ * per workgroup than the device offers (the 16384-point transforms use up to
+ * 139 KB). */
 int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, void* ws, size_t ws_bytes,
                void* hip_stream, flame_plan* out);
 
@@ -141,6 +143,13 @@ int flame_step(flame_plan plan, int32_t nsteps);
  *   out4[3] = 1 if every state entry is finite, else 0.
  * out4 is dev memory (4 doubles), written on the stream. */
 int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
+
+/* The same averages written to host memory (host_out4, 4 doubles), for
+ * callers that check a run as it goes: queues flame_diagnostics into the
+ * plan's workspace, copies the result and waits for the plan's stream.
+ * Returns FLAME_ERR_NONFINITE (with host_out4 filled) when some state entry
+ * is not finite, FLAME_OK otherwise. */
+int flame_diagnostics_host(flame_plan plan, int32_t flame, double* host_out4);
 
 /* Adjoint of one step (integrating-factor Euler; the paper has no adjoint).
  * Cotangents are the Fourier coefficients of the gradient with respect to the
@@ -220,7 +229,8 @@ int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
 /* Points per thread of the step kernels for the flames of grid n1 x n2: each
  * length-N transform is owned by N/pts threads holding pts points, with
  * radix-pts passes (col_pts for the column kernel, row_pts for the row
- * kernel; 8 or 16, default 16). pts = 12 selects the 12-point plan (a
+ * kernel; 8 or 16, default 16; 8 only for lengths up to 8192,
+ * FLAME_ERR_UNSUPPORTED_SIZE beyond). pts = 12 selects the 12-point plan (a
  * radix-12 pass, then radix 4 and 2) for transforms of 3/4 of the grid on
  * N/16 threads: col_pts = 12 runs the column transforms of the product grid
  * (it needs flame_set_product_grid enabled, FLAME_ERR_INVALID_ARG
@@ -319,7 +329,7 @@ int flame_destroy(flame_plan plan);
  * no plan and no workspace: every circle's spectrum stays in registers
  * during a launch, and the twiddles are computed on the device. */
 typedef struct {
-  int32_t n;        /* points per circle: a power of two in [16, 8192] */
+  int32_t n;        /* points per circle: a power of two in [16, 16384] */
   double gamma;     /* density contrast, >= 0 */
   double seg;       /* segment integer (1: the whole circle), > 0 */
   double t0;        /* time of step index 0, > 0 */

@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(CircleCfg<LOGN>::THREADS)
   using S = typename Cfg::S;
   constexpr int G = S::G, B = Cfg::B, N = S::N, H = N / 4;
   extern __shared__ float2 lds[];
-  __shared__ double red[3][Cfg::THREADS];
+  static_assert(3 * Cfg::THREADS * 8 <= Cfg::LDS_BYTES, "reduction area in the transform's LDS");
+  double(*red)[Cfg::THREADS] = reinterpret_cast<double(*)[Cfg::THREADS]>(lds);  // after the transform
   const int tid = threadIdx.x;
   const int p = tid % B, t = tid / B;
   const int pair = blockIdx.x * B + p;
@@ -213,7 +214,9 @@ __global__ void __launch_bounds__(CircleCfg<LOGN>::THREADS)
     ja += xa / (1.0 + sqrt(1.0 + xa));
     jb += xb / (1.0 + sqrt(1.0 + xb));
   }
-  // per pair: tree sums over the G threads of column p (stride B)
+  // per pair: tree sums over the G threads of column p (stride B); the
+  // transform's last pass left the LDS free
+  __syncthreads();
   for (int half = 0; half < 2; ++half) {
     red[0][tid] = half ? vb : va;
     red[1][tid] = half ? jb : ja;

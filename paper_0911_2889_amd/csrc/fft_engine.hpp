@@ -1,6 +1,6 @@
 // Register/LDS Stockham FFT engine for gfx950 (wave64).
 //
-// One length-N transform (N = 2^LOGN, 16 <= N <= 8192) is owned by a group
+// One length-N transform (N = 2^LOGN, 16 <= N <= 16384) is owned by a group
 // of G = N/PTS threads (PTS = 16 or 8 points per thread). Thread t holds the
 // points x[t + G*i], i = 0..PTS-1, in registers. A pass of radix R (PTS, or
 // the smaller power-of-two remainder in the last pass) lets each thread run
@@ -108,7 +108,7 @@ struct Shape {
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
-  static_assert(LOGN >= 4 && LOGN <= 13, "transform length must be 16..8192");
+  static_assert(LOGN >= 4 && LOGN <= 14, "transform length must be 16..16384");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
 
@@ -137,7 +137,7 @@ struct Shape6 {
   static constexpr int radix(int p) { return p < NBF ? plan.radix[p] : 6; }
   static constexpr int ns(int p) { return p < NBF ? plan.ns[p] : N6; }
   static constexpr int tw_off(int p) { return p < NBF ? plan.tw_off[p] : TW6; }
-  static_assert(LOGP >= 4 && LOGP <= 10, "power-of-two part must be 16..1024");
+  static_assert(LOGP >= 4 && LOGP <= 11, "power-of-two part must be 16..2048");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
 
@@ -158,7 +158,7 @@ struct Shape12 {
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
-  static_assert(E >= 2 && E <= 9, "length 48..6144");
+  static_assert(E >= 2 && E <= 10, "length 48..12288");
 };
 
 // k mod ns for k >= 0 (ns a compile-time constant, not always a power of two)

@@ -60,7 +60,7 @@ int check_desc(const flame_desc* d, Sizes* s) {
   const int l1 = ilog2_exact(d->n1), l2 = ilog2_exact(d->n2);
   if (l1 < 0 || l2 < 0) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must be powers of two", d->n1, d->n2);
   if (l1 < flame::kMinLog || l1 > flame::kMaxLog || l2 < flame::kMinLog || l2 > flame::kMaxLog)
-    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must lie in [16, 8192]", d->n1, d->n2);
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "grid %d x %d: sizes must lie in [16, 16384]", d->n1, d->n2);
   if (!(std::isfinite(d->gamma) && d->gamma >= 0.0)) return fail(FLAME_ERR_INVALID_ARG, "gamma must be finite and >= 0");
   if (!(std::isfinite(d->theta_pi) && d->theta_pi > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "theta_pi must be > 0");
   if (!(std::isfinite(d->t0) && d->t0 > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "t0 must be > 0");
@@ -102,6 +102,7 @@ struct Layout {
   size_t off_dev;
   size_t off_dev_full;  // device flame table whose W is the adjoint scratch (physical-grid W for diagnostics)
   size_t off_counter;  // step index read by graph replays
+  size_t off_diag;     // 4 doubles per flame: flame_diagnostics_host's device copy
   size_t total;
 };
 
@@ -155,6 +156,8 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   off = align_up(off + (size_t)nfl * sizeof(flame::FlameDev));
   L->off_counter = off;
   off = align_up(off + sizeof(long long));
+  L->off_diag = off;
+  off = align_up(off + 4 * sizeof(double) * (size_t)nfl);
   L->total = off;
   return FLAME_OK;
 }
@@ -545,7 +548,7 @@ static int check_circle(const flame_circle_desc* d, int* logn) {
   if (!d) return fail(FLAME_ERR_INVALID_ARG, "null flame_circle_desc");
   const int l = ilog2_exact(d->n);
   if (l < 0 || l < flame::kMinLog || l > flame::kMaxLog)
-    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "circle of %d points: a power of two in [16, 8192]", d->n);
+    return fail(FLAME_ERR_UNSUPPORTED_SIZE, "circle of %d points: a power of two in [16, 16384]", d->n);
   if (!(std::isfinite(d->gamma) && d->gamma >= 0.0)) return fail(FLAME_ERR_INVALID_ARG, "gamma must be finite and >= 0");
   if (!(std::isfinite(d->seg) && d->seg > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "seg must be > 0");
   if (!(std::isfinite(d->t0) && d->t0 > 0.0)) return fail(FLAME_ERR_INVALID_ARG, "t0 must be > 0");
@@ -1070,6 +1073,23 @@ int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
   return last_launch("diagnostics launch");
 }
 
+int flame_diagnostics_host(flame_plan p, int32_t flame, double* host_out4) {
+  int rc = check_plan(p, flame);
+  if (rc) return rc;
+  if (!host_out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  double* dev = reinterpret_cast<double*>(reinterpret_cast<char*>(p->ddev) - p->layout.off_dev + p->layout.off_diag) +
+                4 * (size_t)flame;
+  rc = flame_diagnostics(p, flame, dev);
+  if (rc) return rc;
+  DeviceGuard g(p->device);
+  hipError_t e = hipMemcpyAsync(host_out4, dev, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostics copy");
+  if (host_out4[3] != 1.0)
+    return fail(FLAME_ERR_NONFINITE, "flame %d: the state at step index %lld holds non-finite values", flame, p->n);
+  return FLAME_OK;
+}
+
 int flame_adjoint_step(flame_plan p, int32_t flame, int64_t n, const void* state_n, const void* lam_in,
                        void* lam_out) {
   int rc = check_plan(p, flame);
@@ -1203,6 +1223,8 @@ int flame_set_points_per_thread(flame_plan p, int32_t n1, int32_t n2, int32_t co
                   1 << flame::kMinLogProduct);
     if (row_pts == 12 && gr.logn2 < flame::kMinLogRow12)
       return fail(FLAME_ERR_UNSUPPORTED_SIZE, "row_pts = 12 needs n2 >= %d", 1 << flame::kMinLogRow12);
+    if ((col_pts == 8 && gr.logn1 > flame::kMaxLog8) || (row_pts == 8 && gr.logn2 > flame::kMaxLog8))
+      return fail(FLAME_ERR_UNSUPPORTED_SIZE, "8 points per thread needs lengths up to %d", 1 << flame::kMaxLog8);
   }
   if (!found) return fail(FLAME_ERR_INVALID_ARG, "no flame of grid %d x %d in this plan", n1, n2);
   DeviceGuard g(p->device);
@@ -1314,13 +1336,20 @@ struct TuneCfg {
 
 static std::vector<TuneCfg> tune_cfgs(const Group& gr) {
   std::vector<TuneCfg> cfgs;
-  std::vector<int> rows = {16, 8};
+  std::vector<int> rows = {16};
+  if (gr.logn2 <= flame::kMaxLog8) rows.push_back(8);
   if (gr.logn2 >= flame::kMinLogRow12) rows.push_back(12);
+  std::vector<int> cols = {16}, pcols = {16};
+  if (gr.logn1 <= flame::kMaxLog8) {
+    cols.push_back(8);
+    pcols.push_back(8);
+  }
+  pcols.push_back(12);
   for (bool nt : {false, true}) {
-    for (int c : {16, 8})
+    for (int c : cols)
       for (int r : rows) cfgs.push_back(TuneCfg{false, c, r, nt});
     if (gr.logn1 >= flame::kMinLogProduct)
-      for (int c : {16, 8, 12})
+      for (int c : pcols)
         for (int r : rows) cfgs.push_back(TuneCfg{true, c, r, nt});
   }
   return cfgs;

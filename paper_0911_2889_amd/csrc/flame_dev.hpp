@@ -228,7 +228,11 @@ constexpr bool kPrune = FLAME_PRUNE != 0;
 
 
 constexpr int kMinLog = 4;
-constexpr int kMaxLog = 13;
+constexpr int kMaxLog = 14;
+// Lengths up to 2^kMaxLog8 have the 8-points-per-thread kernels (beyond it
+// they would need more than 1024 threads per workgroup), and so does the
+// split product-grid column kernel.
+constexpr int kMaxLog8 = 13;
 constexpr int kDiagThreads = 256;
 
 }  // namespace flame

@@ -801,9 +801,13 @@ struct ColTable {
   template <int VAR>
   static KernelLaunch step_kernel_v(int pts) {
     if (pts == 12) return KernelLaunch{nullptr, 0, 0};  // product grid only (ColPTable)
-    if (pts == 8)
-      return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, VAR>),
-                          ColCfg<LOGN, 8>::THREADS, ColCfg<LOGN, 8>::LDS_BYTES};
+    if (pts == 8) {
+      if constexpr (LOGN <= kMaxLog8)
+        return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, 8, VAR>),
+                            ColCfg<LOGN, 8>::THREADS, ColCfg<LOGN, 8>::LDS_BYTES};
+      else
+        return KernelLaunch{nullptr, 0, 0};
+    }
     return KernelLaunch{reinterpret_cast<const void*>(&col_kernel<LOGN, COL_STEP, ff::kPts, VAR>),
                         ColCfg<LOGN>::THREADS, ColCfg<LOGN>::LDS_BYTES};
   }
@@ -849,9 +853,13 @@ struct RowTable {
       else
         return KernelLaunch{nullptr, 0, 0};
     }
-    if (pts == 8)
-      return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8, NT>), RowCfg<LOGN, 8>::THREADS,
-                          RowCfg<LOGN, 8>::LDS_BYTES};
+    if (pts == 8) {
+      if constexpr (LOGN <= kMaxLog8)
+        return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, 8, NT>),
+                            RowCfg<LOGN, 8>::THREADS, RowCfg<LOGN, 8>::LDS_BYTES};
+      else
+        return KernelLaunch{nullptr, 0, 0};
+    }
     return KernelLaunch{reinterpret_cast<const void*>(&row_kernel<LOGN, ROW_STEP, ff::kPts, NT>),
                         RowCfg<LOGN>::THREADS, RowCfg<LOGN>::LDS_BYTES};
   }
@@ -870,11 +878,15 @@ struct ColPTable {
   }
   template <int VAR>
   static KernelLaunch split(int mode) {
-    if (mode == COL_FIRST)
-      return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_FIRST>), ColCfgQ<LOGN>::THREADS,
+    if constexpr (LOGN > kMaxLog8) {
+      return KernelLaunch{nullptr, 0, 0};
+    } else {
+      if (mode == COL_FIRST)
+        return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_FIRST>), ColCfgQ<LOGN>::THREADS,
+                            ColCfgQ<LOGN>::LDS_BYTES};
+      return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP, VAR>), ColCfgQ<LOGN>::THREADS,
                           ColCfgQ<LOGN>::LDS_BYTES};
-    return KernelLaunch{reinterpret_cast<const void*>(&colq_kernel<LOGN, COL_STEP, VAR>), ColCfgQ<LOGN>::THREADS,
-                        ColCfgQ<LOGN>::LDS_BYTES};
+    }
   }
   template <int VAR>
   static KernelLaunch twelve(int mode) {
@@ -1001,7 +1013,8 @@ int col_lds(int logn1) {
     int b = ColCfg<L, 16>::LDS_BYTES > ColCfg<L, 8>::LDS_BYTES ? ColCfg<L, 16>::LDS_BYTES : ColCfg<L, 8>::LDS_BYTES;
     if constexpr (L >= kMinLogProduct) {
       if (ColCfgP<L, 16>::LDS_BYTES > b) b = ColCfgP<L, 16>::LDS_BYTES;
-      if (ColCfgQ<L>::LDS_BYTES > b) b = ColCfgQ<L>::LDS_BYTES;
+      if constexpr (L <= kMaxLog8)
+        if (ColCfgQ<L>::LDS_BYTES > b) b = ColCfgQ<L>::LDS_BYTES;
       if (ColCfg<L, 12>::LDS_BYTES > b) b = ColCfg<L, 12>::LDS_BYTES;
     }
     return b;

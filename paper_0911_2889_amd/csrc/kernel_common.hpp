@@ -89,12 +89,18 @@ struct GlobalFetch {
   __device__ __forceinline__ float2 operator()(int i) const { return ld(tw + i); }
 };
 
+// 16384-point transforms take 1024 threads per workgroup, i.e. at most 128
+// registers per thread: there they read the twiddles from the table (cached
+// in L1/L2) at each use instead of holding 42 of them in registers.
+template <int LOGN>
+constexpr bool cache_twiddles() { return kCacheTwiddles && LOGN <= 13; }
+
 template <int LOGN, int PTS = ff::kPts>
 struct KernelTw {
-  using Type = typename std::conditional<kCacheTwiddles, ff::RegTw<LOGN, GlobalFetch, kTwCacheMinNs, PTS>,
+  using Type = typename std::conditional<cache_twiddles<LOGN>(), ff::RegTw<LOGN, GlobalFetch, kTwCacheMinNs, PTS>,
                                          ff::GlobalTw<LOGN, PTS>>::type;
   static __device__ __forceinline__ Type make(const float2* tw, int t) {
-    if constexpr (kCacheTwiddles) {
+    if constexpr (cache_twiddles<LOGN>()) {
       return Type(GlobalFetch{(const gf2*)tw}, t);
     } else {
       return Type{tw, t};

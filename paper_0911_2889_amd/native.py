@@ -25,7 +25,7 @@ EXPORTS = (
     "flame_set_points_per_thread", "flame_get_points_per_thread", "flame_set_product_grid",
     "flame_get_product_grid", "flame_set_streaming_stores", "flame_get_streaming_stores", "flame_set_r0_table",
     "flame_set_forcing", "flame_autotune", "flame_destroy", "flame_step_noalloc",
-    "flame_circle_state_bytes", "flame_circle_step", "flame_circle_diagnostics",
+    "flame_circle_state_bytes", "flame_circle_step", "flame_circle_diagnostics", "flame_diagnostics_host",
     "flame_last_error",
 )
 
@@ -86,6 +86,7 @@ def load():
         "flame_step_index": [P, ctypes.POINTER(i64)],
         "flame_step": [P, i32],
         "flame_diagnostics": [P, i32, P],
+        "flame_diagnostics_host": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "flame_adjoint_step": [P, i32, i64, P, P, P],
         "flame_area_gradient": [P, i32, i64, P, P],
         "flame_synthesize": [P, i32, P, P],

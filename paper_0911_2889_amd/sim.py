@@ -119,6 +119,14 @@ class FlameEnsemble:
         v = buf.cpu().tolist()
         return {"mean_radius": v[0], "velocity": v[1], "area_excess": v[2], "finite": bool(v[3] == 1.0)}
 
+    def check_finite(self, flame=0):
+        """Averages in host memory (waits for the stream); raises FlameError with
+        code FLAME_ERR_NONFINITE if the state holds non-finite values."""
+        self._check_flame(flame)
+        out = (ctypes.c_double * 4)()
+        native.check(self.lib.flame_diagnostics_host(self.plan, flame, out))
+        return {"mean_radius": out[0], "velocity": out[1], "area_excess": out[2], "finite": out[3] == 1.0}
+
     # ------------------------------------------------------------ adjoint
     def new_cotangent(self, flame=0):
         """Zeroed buffer in the state layout (for cotangents and saved states)."""

@@ -165,7 +165,7 @@ void run12(std::vector<float2>& x, int stride, bool outer) {
 
 template <int E>
 bool dispatch12(int e, int inv, std::vector<float2>& x, int stride, bool outer) {
-  if constexpr (E > 9) {
+  if constexpr (E > 10) {
     return false;
   } else {
     if (e != E) return dispatch12<E + 1>(e, inv, x, stride, outer);
@@ -179,7 +179,7 @@ bool dispatch12(int e, int inv, std::vector<float2>& x, int stride, bool outer) 
 
 template <int LOGN>
 bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer, int pts) {
-  if constexpr (LOGN > 13) {
+  if constexpr (LOGN > 14) {
     return false;
   } else {
     if (logn != LOGN) return dispatch<LOGN + 1>(logn, inv, x, stride, outer, pts);
@@ -200,7 +200,7 @@ bool dispatch(int logn, int inv, std::vector<float2>& x, int stride, bool outer,
 
 template <int LOGP>
 bool dispatch6(int logp, int inv, std::vector<float2>& x, int stride, int pts) {
-  if constexpr (LOGP > 10) {
+  if constexpr (LOGP > 11) {
     return false;
   } else {
     if (logp != LOGP) return dispatch6<LOGP + 1>(logp, inv, x, stride, pts);
@@ -230,7 +230,7 @@ int main() {
   const int logn = hdr[0], inv = hdr[1], stride = hdr[2], outer = hdr[3], pts = hdr[4], six = hdr[5];
   if (stride < 1) return 3;
   if (six == 2) {  // Shape12 with E = logn: length 12 * 2^E
-    if (logn < 2 || logn > 9) return 3;
+    if (logn < 2 || logn > 10) return 3;
     std::vector<float2> x(size_t(12) << logn);
     if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
     if (outer)  // the pruned first pass assumes the middle third of the input is zero
@@ -241,14 +241,14 @@ int main() {
   }
   if (pts != 8 && pts != 16) return 3;
   if (six) {
-    if (logn < 4 || logn > 10) return 3;
+    if (logn < 4 || logn > 11) return 3;
     std::vector<float2> x(size_t(6) << logn);
     if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
     if (!dispatch6<4>(logn, inv, x, stride, pts)) return 5;
     fwrite(x.data(), sizeof(float2), x.size(), stdout);
     return 0;
   }
-  if (logn < 4 || logn > 13) return 3;
+  if (logn < 4 || logn > 14) return 3;
   std::vector<float2> x(size_t(1) << logn);
   if (fread(x.data(), sizeof(float2), x.size(), stdin) != x.size()) return 4;
   if (outer)  // the pruned first pass assumes the middle half of the input is zero

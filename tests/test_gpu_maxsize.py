@@ -1,7 +1,7 @@
-"""The largest supported transform length, 8192, against the FP64 oracle: the
-step on both grids and points-per-thread variants, the adjoint step, the area
-gradient, projection and synthesis, and a property check of one step of an
-8192 x 8192 flame."""
+"""The largest supported transform lengths, 8192 and 16384, against the FP64
+oracle: the step on both grids and points-per-thread variants, the adjoint
+step, the area gradient, projection and synthesis, circles of 16384 points,
+and a property check of one step of an 8192 x 8192 flame."""
 
 import numpy as np
 import pytest
@@ -34,7 +34,9 @@ def workload(n1, n2, seed, amp=0.05, t0=5.0, dt=0.2, max_norm=24):
 @pytest.mark.parametrize("n1,n2,product,pts", [
     (8192, 64, None, (16, 16)), (8192, 64, None, (8, 8)), (64, 8192, None, (16, 16)), (64, 8192, None, (8, 8)),
     (8192, 128, True, (16, 16)), (8192, 128, True, (8, 16)), (8192, 128, False, (16, 8)),
-    (128, 8192, True, (16, 16))])
+    (128, 8192, True, (16, 16)),
+    (16384, 64, True, (16, 16)), (16384, 64, False, (16, 16)), (16384, 64, True, (12, 16)),
+    (64, 16384, None, (16, 16)), (64, 16384, None, (16, 12)), (128, 16384, True, (12, 12))])
 def test_step_at_the_largest_lengths_matches_oracle(n1, n2, product, pts):
     # modes up to |k| = 1000 reach deep into the long axis's box (K = 2047)
     w = workload(n1, n2, seed=n1 + n2 + pts[0], amp=0.02, max_norm=1000)
@@ -63,7 +65,7 @@ def from_internal(t, n1, n2):
     return t.cpu().numpy().reshape(n2 // 4, n1 // 2)[:, 1:].T.copy()
 
 
-@pytest.mark.parametrize("n1,n2", [(8192, 64), (64, 8192), (8192, 128)])
+@pytest.mark.parametrize("n1,n2", [(8192, 64), (64, 8192), (8192, 128), (16384, 64), (64, 16384), (16384, 128)])
 def test_adjoint_and_area_gradient_at_the_largest_lengths(n1, n2):
     t0, dt, n = 5.0, 0.2, 2
     state = synth.workload_spectrum(synth.Workload("s", n1, n2, 1, dt, "all", 0.3, -1.0, 5))
@@ -83,7 +85,7 @@ def test_adjoint_and_area_gradient_at_the_largest_lengths(n1, n2):
     assert rel_l2(from_internal(g, n1, n2), ref_g) < 1e-5
 
 
-@pytest.mark.parametrize("n1,n2", [(8192, 32), (32, 8192)])
+@pytest.mark.parametrize("n1,n2", [(8192, 32), (32, 8192), (16384, 32), (32, 16384)])
 def test_projection_and_synthesis_at_the_largest_lengths(n1, n2):
     phi = synth.physical_noise(n1, n2, seed=3, kind="uniform", scale=1e-3)
     sim = sim_or_skip(n1, n2)
@@ -122,3 +124,37 @@ def test_full_8192_square_step_moves_the_mean_mode_by_the_velocity(product):
     # state must stay Hermitian in its k2 = 0 column after the symmetrisation
     col0 = spec[:, 0].cpu().numpy()
     assert np.array_equal(col0[:k1max], np.conj(col0[k1max + 1:][::-1]))
+
+
+def test_eight_points_per_thread_stops_at_8192():
+    from paper_0911_2889_amd import native
+    sim = sim_or_skip(16384, 64)
+    with pytest.raises(native.FlameError) as err:
+        sim.set_points_per_thread(16384, 64, 8, 16)
+    assert err.value.code == native.FLAME_ERR_UNSUPPORTED_SIZE
+    tried = sim.autotune(steps=1)
+    assert sim.points_per_thread(16384, 64)[0] in (12, 16)
+    assert tried == 2 * (1 * 3 + 2 * 3)  # (16 | 16, 12) x rows (16, 8, 12), plain and non-temporal
+
+
+def test_circles_of_16384_points_match_oracle():
+    from paper_0911_2889_amd import CircleBatch
+    n, count = 16384, 3
+    spec = synth.circle_spectra(n, count, seed=4, amp=0.2)
+    b = CircleBatch(n, count, gamma=0.8, seg=1.0, t0=6.0, dt=0.1)
+    b.set_spectra(spec)
+    b.step(1)
+    one = b.states.cpu().numpy()
+    b.step(9)
+    ten = b.states.cpu().numpy()
+    p = oracle.CircleParams(n, gamma=0.8, seg=1.0, t0=6.0, dt=0.1)
+    w = np.full(n // 4, 2.0)
+    w[0] = 1.0
+    for c in range(count):
+        f0 = oracle.half_to_circle(spec[c].astype(np.complex128), n)
+        for got, steps, tol in ((one[c], 1, 1e-6), (ten[c], 10, 1e-5)):
+            ref = oracle.circle_to_half(oracle.circle_run(f0, p, steps))
+            err = np.sqrt((w * np.abs(got - ref) ** 2).sum() / (w * np.abs(ref) ** 2).sum())
+            assert err < tol, (c, steps, err)
+    d = b.diagnostics().cpu().numpy()
+    assert (d[:, 3] == 1.0).all()

@@ -162,6 +162,14 @@ def test_nonfinite_state_is_flagged(flame):
     sim = make_sim(flame, w)
     sim.set_spectrum(half)
     assert not sim.diagnostics()["finite"]
+    # the host-synchronising call reports it as FLAME_ERR_NONFINITE
+    with pytest.raises(flame.native.FlameError) as err:
+        sim.check_finite()
+    assert err.value.code == flame.native.FLAME_ERR_NONFINITE
+    ok = make_sim(flame, w)
+    ok.set_spectrum(synth.workload_spectrum(w))
+    d = ok.check_finite()
+    assert d["finite"] and d == ok.diagnostics()
 
 
 def test_ensemble_members_match_solo_runs(flame):
