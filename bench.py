@@ -465,11 +465,11 @@ def ensemble_leg(steps, graph_steps):
                  for w in members)
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
            "points": points, "step_bytes": nbytes, "points_per_thread": tuned}
-    for mode, gs in (("graph", graph_steps), ("direct", 0)):
-        ens.set_graph_steps(gs)
+
+    def timed(warm):
         for f, h in enumerate(halves):
             ens.set_spectrum(h, flame=f)
-        ens.step(gs if gs else 10)  # warm-up (builds the graph)
+        ens.step(warm)  # warm-up (builds the graph, or the persistent partition)
         for f, h in enumerate(halves):
             ens.set_spectrum(h, flame=f)
         ens.step(0)
@@ -480,8 +480,31 @@ def ensemble_leg(steps, graph_steps):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        out[mode] = {"ms_per_step": ms / steps, "point_steps_per_s": points * steps / (ms * 1e-3),
-                     "step_hbm_frac": nbytes / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        return {"ms_per_step": ms / steps, "point_steps_per_s": points * steps / (ms * 1e-3),
+                "step_hbm_frac": nbytes / (ms / steps * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    for mode, gs in (("graph", graph_steps), ("direct", 0)):
+        ens.set_graph_steps(gs)
+        out[mode] = timed(gs if gs else 10)
+    # A/B of the persistent launch: every group on the persistent kernel's
+    # configuration (product grid, 12 column and 16 row points per thread,
+    # plain stores), against graph replays of the same kernels' bodies
+    for n1, n2 in grids:
+        ens.set_points_per_thread(n1, n2, 12, 16)
+        ens.set_product_grid(n1, n2, True)
+        ens.set_streaming_stores(n1, n2, False)
+    ens.set_graph_steps(graph_steps)
+    out["graph_persistent_config"] = timed(graph_steps)
+    ens.set_graph_steps(0)
+    runs = {}
+    for wgs in (0, 256):
+        ens.set_persistent(True, workgroups=wgs)
+        r = timed(10)
+        r["workgroups"] = ens.persistent()[1]
+        runs[wgs] = r
+    ens.set_persistent(False)
+    best = min(runs.values(), key=lambda r: r["ms_per_step"])
+    out["persistent"] = dict(best, grids_tried={str(r["workgroups"]): r["ms_per_step"] for r in runs.values()})
     return out
 
 

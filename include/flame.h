@@ -59,6 +59,7 @@ extern "C" {
 #define FLAME_ERR_HIP (-3)
 #define FLAME_ERR_UNSUPPORTED_SIZE (-4)
 #define FLAME_ERR_NONFINITE (-5)
+#define FLAME_ERR_TIMEOUT (-6)
 
 typedef struct flame_plan_s* flame_plan;
 
@@ -307,6 +308,35 @@ int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
  * discard the graph (a new graph length, points per thread, grid or forcing
  * group) first wait for the plan's stream. */
 int flame_set_graph_steps(flame_plan plan, int32_t steps);
+
+/* Run flame_step as one persistent launch (enable = 1) instead of per-group
+ * kernels or graphs: a cooperative launch of one co-resident grid whose
+ * workgroups step every flame of the plan for up to 1000 steps per launch.
+ * Each workgroup runs the step kernels' work (Section 3's two transform
+ * passes with the Eq. (1) update between them) on its share of the flames:
+ * several small flames alone, or a part of a large flame's row-pair groups
+ * and column tiles, meeting that flame's other workgroups at a device-memory
+ * counter after each pass. The arithmetic is that of the per-group kernels,
+ * so the results are the same bit for bit. Shares are sized so that every
+ * workgroup has about the same number of tiles per step.
+ *
+ * workgroups: the grid size (0: every workgroup that fits on the device,
+ * two per compute unit). wait_limit_us: the bound of each wait at a counter,
+ * in microseconds (0: 2 s); a wait that runs out makes every workgroup stop,
+ * and flame_step returns FLAME_ERR_TIMEOUT with the states undefined. In
+ * this mode flame_step waits for the plan's stream before it returns (to
+ * read that status); graph_steps is not used.
+ *
+ * Requires every group of the plan on the product grid with col_pts = 12,
+ * row_pts = 16, plain stores, integrator 0 and no forcing, with n1 in
+ * [128, 1024] and n2 in [128, 2048] (FLAME_ERR_INVALID_ARG otherwise, also
+ * from flame_step if a later call changes a group's configuration), and a
+ * device with cooperative launches (FLAME_ERR_UNSUPPORTED_SIZE). enable = 0
+ * returns to the per-group launches. */
+int flame_set_persistent(flame_plan plan, int32_t enable, int32_t workgroups, int32_t wait_limit_us);
+/* *enabled: whether flame_step runs persistent launches; *workgroups: the
+ * grid of the last one (0 before the first). */
+int flame_get_persistent(flame_plan plan, int32_t* enabled, int32_t* workgroups);
 
 /* Release the plan's host metadata (device buffers stay the caller's), after
  * waiting for the plan's stream. */

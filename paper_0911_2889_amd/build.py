@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libflamefront.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["flame_kernels.hip", "adjoint_kernels.hip", "circle_kernels.hip", "flame_api.hip"]
+SOURCES = ["flame_kernels.hip", "ensemble_kernel.hip", "adjoint_kernels.hip", "circle_kernels.hip", "flame_api.hip"]
 ARCH = "gfx950"
 
 

@@ -36,6 +36,11 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 constexpr size_t kAlign = 256;
+// Workgroups of the persistent ensemble launch at most (its item table in the workspace).
+constexpr int kMaxEnsItems = 4096;
+// Steps per persistent launch at most, and the default bound of each of its waits.
+constexpr int kEnsMaxSteps = 1000;
+constexpr long long kEnsDefaultWaitUs = 2000000;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int ilog2_exact(int n) {
@@ -103,6 +108,7 @@ struct Layout {
   size_t off_dev_full;  // device flame table whose W is the adjoint scratch (physical-grid W for diagnostics)
   size_t off_counter;  // step index read by graph replays
   size_t off_diag;     // 4 doubles per flame: flame_diagnostics_host's device copy
+  size_t off_ens_items, off_ens_arrive, off_ens_err;  // persistent ensemble launch
   size_t total;
 };
 
@@ -158,6 +164,12 @@ int plan_layout(const flame_desc* descs, int nfl, Layout* L) {
   off = align_up(off + sizeof(long long));
   L->off_diag = off;
   off = align_up(off + 4 * sizeof(double) * (size_t)nfl);
+  L->off_ens_items = off;
+  off = align_up(off + sizeof(flame::EnsembleItem) * (size_t)kMaxEnsItems);
+  L->off_ens_arrive = off;
+  off = align_up(off + sizeof(unsigned) * flame::kEnsArriveStride * (size_t)nfl);
+  L->off_ens_err = off;
+  off = align_up(off + sizeof(int));
   L->total = off;
   return FLAME_OK;
 }
@@ -229,6 +241,15 @@ struct flame_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long* counter = nullptr;
+  // persistent ensemble launch (flame_set_persistent)
+  bool persistent = false;
+  int ens_wgs = 0;                              // requested workgroups (0: all that fit)
+  unsigned long long ens_limit = 0;             // bound of each wait, wall-clock ticks
+  std::vector<flame::EnsembleItem> ens_items;   // the partition in use (empty: to be built)
+  std::vector<int> ens_sig;                     // the group configuration it was built for
+  flame::EnsembleItem* d_items = nullptr;
+  unsigned* d_arrive = nullptr;
+  int* d_err = nullptr;
   ~flame_plan_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -911,6 +932,9 @@ int flame_init(const flame_desc* descs, int32_t n_flames, void* const* states, v
   p->ddev = reinterpret_cast<flame::FlameDev*>(base + L.off_dev);
   p->ddev_full = reinterpret_cast<flame::FlameDev*>(base + L.off_dev_full);
   p->counter = reinterpret_cast<long long*>(base + L.off_counter);
+  p->d_items = reinterpret_cast<flame::EnsembleItem*>(base + L.off_ens_items);
+  p->d_arrive = reinterpret_cast<unsigned*>(base + L.off_ens_arrive);
+  p->d_err = reinterpret_cast<int*>(base + L.off_ens_err);
   e = hipMemcpyAsync(p->ddev, p->hdev.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(p->ddev_full, p->hdev_full.data(), sizeof(flame::FlameDev) * n_flames, hipMemcpyHostToDevice,
@@ -993,6 +1017,129 @@ int flame_step_index(flame_plan p, int64_t* n) {
   return FLAME_OK;
 }
 
+namespace {
+
+// Why the flames of group gr cannot run in the persistent ensemble kernel
+// (null if they can).
+const char* ens_reason(const Group& gr) {
+  if (!flame::ensemble_supports(gr.logn1, gr.logn2)) return "the persistent kernel has bodies for n1 in [128, 1024], n2 in [128, 2048]";
+  if (!gr.product || gr.col_pts != 12) return "the persistent kernel steps the product grid with 12 column points per thread";
+  if (gr.row_pts != 16) return "the persistent kernel's row transforms use 16 points per thread";
+  if (gr.streaming) return "the persistent kernel uses plain stores";
+  if (gr.integrator != 0 || gr.forced) return "the persistent kernel runs unforced integrating-factor Euler";
+  return nullptr;
+}
+
+int ens_check(flame_plan p) {
+  for (const Group& gr : p->groups)
+    if (const char* why = ens_reason(gr))
+      return fail(FLAME_ERR_INVALID_ARG, "flames of grid %d x %d: %s", 1 << gr.logn1, 1 << gr.logn2, why);
+  return FLAME_OK;
+}
+
+std::vector<int> ens_signature(flame_plan p, int wgs) {
+  std::vector<int> sig{wgs};
+  for (const Group& gr : p->groups) sig.insert(sig.end(), {gr.first, gr.count, gr.rgroups(), gr.tiles});
+  return sig;
+}
+
+// Split the flames over at most `wgs` workgroups with about equal work: each
+// flame has u = row-pair groups + column tiles of work per step; with a
+// target of t per workgroup, a flame with u >= t is shared by ceil(u / t)
+// workgroups (no more than it has tiles in a phase), and flames with u < t
+// go floor(t / u) to a workgroup. t starts at the total work over wgs and
+// grows until the items fit.
+int ens_partition(flame_plan p, int wgs, std::vector<flame::EnsembleItem>* out) {
+  long long total = 0;
+  for (const Group& gr : p->groups) total += (long long)gr.count * (gr.rgroups() + gr.tiles);
+  std::vector<flame::EnsembleItem> items;
+  for (long long t = std::max(1LL, (total + wgs - 1) / wgs); t <= total; ++t) {
+    items.clear();
+    for (const Group& gr : p->groups) {
+      const int rt = gr.rgroups(), ct = gr.tiles, u = rt + ct;
+      if (u >= t) {
+        const int parts = (int)std::min<long long>((u + t - 1) / t, std::max(rt, ct));
+        for (int f = gr.first; f < gr.first + gr.count; ++f)
+          for (int part = 0; part < parts; ++part)
+            items.push_back(flame::EnsembleItem{f, 1, part, parts, gr.logn1, gr.logn2, rt, ct});
+      } else {
+        const int fpw = (int)(t / u);
+        for (int f = gr.first; f < gr.first + gr.count; f += fpw)
+          items.push_back(
+              flame::EnsembleItem{f, std::min(fpw, gr.first + gr.count - f), 0, 1, gr.logn1, gr.logn2, rt, ct});
+      }
+    }
+    if ((long long)items.size() <= wgs) {
+      *out = std::move(items);
+      return FLAME_OK;
+    }
+  }
+  return fail(FLAME_ERR_UNSUPPORTED_SIZE, "%zu grid groups do not fit %d persistent workgroups", p->groups.size(), wgs);
+}
+
+// The partition for the current group configuration, built and uploaded
+// when it changed.
+int ens_prepare(flame_plan p) {
+  int rc = ens_check(p);
+  if (rc) return rc;
+  int per_cu = flame::ensemble_blocks_per_cu(), cus = 0;
+  if (per_cu <= 0) return fail(FLAME_ERR_HIP, "occupancy query of the persistent kernel failed");
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute(multiprocessor count)");
+  int wgs = std::min(per_cu * cus, kMaxEnsItems);
+  if (p->ens_wgs > 0) wgs = std::min(wgs, p->ens_wgs);
+  const std::vector<int> sig = ens_signature(p, wgs);
+  if (!p->ens_items.empty() && sig == p->ens_sig) return FLAME_OK;
+  // an earlier upload may still read the host table
+  e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronise");
+  std::vector<flame::EnsembleItem> items;
+  rc = ens_partition(p, wgs, &items);
+  if (rc) return rc;
+  p->ens_items = std::move(items);
+  p->ens_sig = sig;
+  e = hipMemcpyAsync(p->d_items, p->ens_items.data(), sizeof(flame::EnsembleItem) * p->ens_items.size(),
+                     hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) {
+    p->ens_items.clear();
+    return hip_fail(e, "persistent item table upload");
+  }
+  return FLAME_OK;
+}
+
+// nsteps steps of every flame in persistent launches of at most kEnsMaxSteps
+// steps; waits for them and reports a wait that ran out.
+int ens_steps(flame_plan p, int nsteps) {
+  int rc = ens_prepare(p);
+  if (rc) return rc;
+  bool first = true;
+  while (nsteps > 0) {
+    const int k = std::min(nsteps, kEnsMaxSteps);
+    {
+      Timed tm(p, KIND_GRAPH);
+      const hipError_t e = flame::launch_ensemble(p->stream, p->ddev, p->d_items, (int)p->ens_items.size(),
+                                                  p->d_arrive, p->nfl * flame::kEnsArriveStride, p->d_err, first,
+                                                  p->n, k, p->ens_limit);
+      if (e != hipSuccess) return hip_fail(e, "persistent ensemble launch");
+    }
+    first = false;
+    p->n += k;
+    nsteps -= k;
+  }
+  break_chain(p);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, p->d_err, sizeof flag, hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return hip_fail(e, "persistent ensemble status");
+  if (flag)
+    return fail(FLAME_ERR_TIMEOUT,
+                "a wait of the persistent ensemble kernel ran out before step index %lld; the states are undefined",
+                p->n);
+  return FLAME_OK;
+}
+
+}  // namespace
+
 int flame_step(flame_plan p, int32_t nsteps) {
   int rc = check_plan(p);
   if (rc) return rc;
@@ -1007,6 +1154,7 @@ int flame_step(flame_plan p, int32_t nsteps) {
       rc = rebuild_w(p, f);
       if (rc) return rc;
     }
+  if (p->persistent) return nsteps > 0 ? ens_steps(p, nsteps) : FLAME_OK;
   if (p->graph_steps > 0 && nsteps >= p->graph_steps) {
     if (!p->graph_exec) {
       rc = build_graph(p);
@@ -1558,6 +1706,41 @@ int flame_set_graph_steps(flame_plan p, int32_t steps) {
     drop_graph(p);
     p->graph_steps = steps;
   }
+  return FLAME_OK;
+}
+
+int flame_set_persistent(flame_plan p, int32_t enable, int32_t workgroups, int32_t wait_limit_us) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (enable != 0 && enable != 1) return fail(FLAME_ERR_INVALID_ARG, "enable must be 0 or 1");
+  if (workgroups < 0) return fail(FLAME_ERR_INVALID_ARG, "workgroups must be >= 0");
+  if (wait_limit_us < 0) return fail(FLAME_ERR_INVALID_ARG, "wait_limit_us must be >= 0");
+  if (!enable) {
+    p->persistent = false;
+    return FLAME_OK;
+  }
+  rc = ens_check(p);
+  if (rc) return rc;
+  DeviceGuard g(p->device);
+  int coop = 0, khz = 0;
+  hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  if (!coop) return fail(FLAME_ERR_UNSUPPORTED_SIZE, "the device has no cooperative launches");
+  if (khz <= 0) return fail(FLAME_ERR_HIP, "the device reports no wall-clock rate");
+  const long long us = wait_limit_us > 0 ? wait_limit_us : kEnsDefaultWaitUs;
+  p->ens_limit = (unsigned long long)us * (unsigned long long)khz / 1000ULL;
+  p->ens_wgs = workgroups;
+  p->persistent = true;
+  return FLAME_OK;
+}
+
+int flame_get_persistent(flame_plan p, int32_t* enabled, int32_t* workgroups) {
+  int rc = check_plan(p);
+  if (rc) return rc;
+  if (!enabled || !workgroups) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
+  *enabled = p->persistent ? 1 : 0;
+  *workgroups = p->persistent ? (int32_t)p->ens_items.size() : 0;
   return FLAME_OK;
 }
 

@@ -235,4 +235,23 @@ constexpr int kMaxLog = 14;
 constexpr int kMaxLog8 = 13;
 constexpr int kDiagThreads = 256;
 
+// Persistent ensemble kernel: one co-resident grid of workgroups steps every
+// flame of a plan for all steps of a launch. A workgroup's share is either
+// `nfl` whole flames from `flame` on, which it steps alone (parts == 1), or
+// part `part` of the `parts` workgroups that share flame `flame`: it takes
+// the row-pair groups and column tiles part, part + parts, ... of each step
+// and meets the others at that flame's arrival counter after each phase.
+struct EnsembleItem {
+  int flame, nfl, part, parts;
+  int logn1, logn2;    // the grid of its flames
+  int rtiles, ctiles;  // row-pair groups and column tiles of one flame
+};
+// Its step kernels' bodies: the product-grid column transforms with 12
+// points per thread (N1 = 2^7 .. 2^10) and the row transforms with 16 (N2 =
+// 2^7 .. 2^11), all of them 256 threads per workgroup.
+constexpr int kEnsThreads = 256;
+constexpr int kEnsMinLog1 = 7, kEnsMaxLog1 = 10;
+constexpr int kEnsMinLog2 = 7, kEnsMaxLog2 = 11;
+constexpr int kEnsArriveStride = 32;  // 128 bytes between two flames' arrival counters
+
 }  // namespace flame

@@ -15,6 +15,7 @@ FLAME_ERR_WORKSPACE_TOO_SMALL = -2
 FLAME_ERR_HIP = -3
 FLAME_ERR_UNSUPPORTED_SIZE = -4
 FLAME_ERR_NONFINITE = -5
+FLAME_ERR_TIMEOUT = -6
 
 # every symbol the C header declares
 EXPORTS = (
@@ -26,7 +27,7 @@ EXPORTS = (
     "flame_get_product_grid", "flame_set_streaming_stores", "flame_get_streaming_stores", "flame_set_r0_table",
     "flame_set_forcing", "flame_autotune", "flame_destroy", "flame_step_noalloc",
     "flame_circle_state_bytes", "flame_circle_step", "flame_circle_diagnostics", "flame_diagnostics_host",
-    "flame_last_error",
+    "flame_set_persistent", "flame_get_persistent", "flame_last_error",
 )
 
 
@@ -91,6 +92,8 @@ def load():
         "flame_area_gradient": [P, i32, i64, P, P],
         "flame_synthesize": [P, i32, P, P],
         "flame_set_graph_steps": [P, i32],
+        "flame_set_persistent": [P, i32, i32, i32],
+        "flame_get_persistent": [P, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "flame_set_points_per_thread": [P, i32, i32, i32, i32],
         "flame_get_points_per_thread": [P, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "flame_autotune": [P, i32, ctypes.POINTER(i32)],

@@ -238,6 +238,18 @@ class FlameEnsemble:
         """Step in hipGraphs of `steps` steps (0: direct launches)."""
         native.check(self.lib.flame_set_graph_steps(self.plan, int(steps)))
 
+    def set_persistent(self, enable=True, workgroups=0, wait_limit_us=0):
+        """Step every flame in one persistent (cooperative) launch per call
+        (workgroups 0: all that fit; wait_limit_us 0: 2 s per wait)."""
+        native.check(self.lib.flame_set_persistent(self.plan, int(bool(enable)), int(workgroups),
+                                                   int(wait_limit_us)))
+
+    def persistent(self):
+        """(enabled, workgroups of the last persistent launch)."""
+        on, wgs = ctypes.c_int32(0), ctypes.c_int32(0)
+        native.check(self.lib.flame_get_persistent(self.plan, ctypes.byref(on), ctypes.byref(wgs)))
+        return bool(on.value), wgs.value
+
     def timing_begin(self):
         native.check(self.lib.flame_timing_begin(self.plan))
 

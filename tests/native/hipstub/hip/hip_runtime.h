@@ -29,7 +29,12 @@ extern dim3 threadIdx, blockIdx, blockDim, gridDim;
 enum hipError_t { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorInvalidResourceHandle = 400 };
 enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                      hipMemcpyDeviceToDevice = 3 };
-enum hipDeviceAttribute_t { hipDeviceAttributeMaxSharedMemoryPerBlock = 74 };
+enum hipDeviceAttribute_t {
+  hipDeviceAttributeMaxSharedMemoryPerBlock = 74,
+  hipDeviceAttributeMultiprocessorCount = 75,
+  hipDeviceAttributeWallClockRate = 76,
+  hipDeviceAttributeCooperativeLaunch = 77
+};
 
 typedef struct ihipStream_t* hipStream_t;
 typedef struct ihipEvent_t* hipEvent_t;

@@ -94,7 +94,13 @@ hipError_t hipGetDevice(int* dev) {
 }
 hipError_t hipSetDevice(int dev) { return dev == 0 ? hipSuccess : hipErrorInvalidValue; }
 hipError_t hipDeviceGetAttribute(int* v, hipDeviceAttribute_t a, int) {
-  *v = a == hipDeviceAttributeMaxSharedMemoryPerBlock ? 160 * 1024 : 0;
+  switch (a) {
+    case hipDeviceAttributeMaxSharedMemoryPerBlock: *v = 160 * 1024; break;
+    case hipDeviceAttributeMultiprocessorCount: *v = 256; break;
+    case hipDeviceAttributeWallClockRate: *v = 100000; break;
+    case hipDeviceAttributeCooperativeLaunch: *v = 1; break;
+    default: *v = 0;
+  }
   return hipSuccess;
 }
 hipError_t hipGetLastError(void) { return hipSuccess; }
@@ -314,6 +320,51 @@ void launch_diag_spectral(hipStream_t st, const FlameDev* fl, int flame, int, do
 void launch_diag_final(hipStream_t st, const FlameDev* fl, int flame, long long, int, int, double*) {
   touch(fl + flame, 1);
   hip_stub_launch(kDummyKernel, st);
+}
+bool ensemble_supports(int logn1, int logn2) {
+  return logn1 >= kEnsMinLog1 && logn1 <= kEnsMaxLog1 && logn2 >= kEnsMinLog2 && logn2 <= kEnsMaxLog2;
+}
+KernelLaunch ensemble_kernel_info() { return KernelLaunch{kDummyKernel, kEnsThreads, 1024}; }
+int ensemble_blocks_per_cu() { return 2; }
+// Reads every item and the flames it names, and checks the partition: every
+// flame is stepped either whole by exactly one item or by parts 0 .. parts-1,
+// each exactly once, and its arrival counter lies inside the counter array.
+hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleItem* items, int nitems,
+                           unsigned* arrive, int narrive, int* err, bool clear_err, long long, int steps,
+                           unsigned long long) {
+  if (nitems <= 0 || nitems > 2 * 256) violation("persistent grid outside the co-resident capacity");
+  if (steps <= 0) violation("persistent launch of no steps");
+  if (narrive % kEnsArriveStride) violation("arrival counters not a whole number of flames");
+  const int nfl = narrive / kEnsArriveStride;
+  std::vector<std::vector<int>> seen(nfl);
+  for (int i = 0; i < nitems; ++i) {
+    EnsembleItem it;
+    std::memcpy(&it, items + i, sizeof it);
+    if (it.flame < 0 || it.nfl < 1 || it.flame + it.nfl > nfl) violation("persistent item names flames outside the plan");
+    if (it.parts < 1 || it.part < 0 || it.part >= it.parts) violation("persistent item part out of range");
+    if (it.parts > 1 && it.nfl != 1) violation("a shared persistent item holds several flames");
+    if (it.parts > 1 && it.parts > (it.rtiles > it.ctiles ? it.rtiles : it.ctiles))
+      violation("more parts than tiles in a phase");
+    touch(fls + it.flame, it.nfl);
+    for (int f = it.flame; f < it.flame + it.nfl; ++f) {
+      FlameDev d;
+      std::memcpy(&d, fls + f, sizeof d);
+      if (d.n1 != 1 << it.logn1 || d.n2 != 1 << it.logn2) violation("persistent item grid differs from its flame's");
+      if (seen[f].empty()) seen[f].assign(it.parts, 0);
+      if ((int)seen[f].size() != it.parts) violation("flame split into differing part counts");
+      ++seen[f][it.part];
+    }
+  }
+  for (int f = 0; f < nfl; ++f) {
+    if (seen[f].empty()) violation("flame left out of the persistent partition");
+    for (int c : seen[f])
+      if (c != 1) violation("flame part stepped other than once");
+  }
+  std::memset(arrive, 0, sizeof(unsigned) * (size_t)narrive);
+  if (clear_err) *err = 0;
+  hip_stub_launch(kDummyKernel, st);
+  hip_stub_launch(kDummyKernel, st);
+  return hipSuccess;
 }
 bool launch_circle_step(int, const CircleDev&, long long, int, hipStream_t st) {
   hip_stub_launch(kDummyKernel, st);

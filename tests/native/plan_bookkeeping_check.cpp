@@ -170,6 +170,46 @@ int main(int argc, char** argv) {
     CHECK(flame_timing_begin(p));
     CHECK(flame_step(p, 7));
   }
+  // persistent launches: the bench ensemble's grids and an uneven mix, on
+  // every grid size, with the configuration changed between steps
+  {
+    std::vector<flame_desc> ds;
+    for (int i = 0; i < 128; ++i) ds.push_back(desc(128, 256));
+    for (int i = 0; i < 96; ++i) ds.push_back(desc(256, 512));
+    for (int i = 0; i < 32; ++i) ds.push_back(desc(512, 1024));
+    Plan pl(ds, st);
+    const int grids[3][2] = {{128, 256}, {256, 512}, {512, 1024}};
+    for (const auto& g : grids) CHECK(flame_set_points_per_thread(pl.p, g[0], g[1], 12, 16));
+    CHECK(flame_set_persistent(pl.p, 1, 0, 0));
+    CHECK(flame_step(pl.p, 3));
+    int32_t on = 0, wgs = 0;
+    CHECK(flame_get_persistent(pl.p, &on, &wgs));
+    if (on != 1 || wgs != 512) {
+      std::fprintf(stderr, "persistent grid %d (enabled %d), expected 512\n", wgs, on);
+      return 5;
+    }
+    for (int w : {3, 7, 100, 300, 512, 0}) {
+      CHECK(flame_set_persistent(pl.p, 1, w, 50));
+      CHECK(flame_step(pl.p, 2));
+    }
+    // a configuration the persistent kernel lacks is refused, then restored
+    CHECK(flame_set_points_per_thread(pl.p, 256, 512, 16, 16));
+    if (flame_step(pl.p, 1) != FLAME_ERR_INVALID_ARG) return 6;
+    CHECK(flame_set_points_per_thread(pl.p, 256, 512, 12, 16));
+    CHECK(flame_step(pl.p, 1001));
+    CHECK(flame_set_persistent(pl.p, 0, 0, 0));
+    CHECK(flame_step(pl.p, 2));
+  }
+  {
+    std::vector<flame_desc> ds = {desc(1024, 2048), desc(128, 128), desc(128, 128), desc(128, 128),
+                                  desc(512, 256),   desc(256, 2048)};
+    Plan pl(ds, st);
+    for (const flame_desc& d : ds) CHECK(flame_set_points_per_thread(pl.p, d.n1, d.n2, 12, 16));
+    for (int w : {0, 4, 6, 40}) {
+      CHECK(flame_set_persistent(pl.p, 1, w, 0));
+      CHECK(flame_step(pl.p, 4));
+    }
+  }
   // the allocation-free step and the circles
   {
     flame_desc d = desc(256, 512);
