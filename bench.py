@@ -22,8 +22,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 CIRCLE_SOURCES = ("paper_0911_2889_amd/csrc/circle_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
                   "paper_0911_2889_amd/csrc/kernel_common.hpp")
-KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
-                  "paper_0911_2889_amd/csrc/flame_dev.hpp", "paper_0911_2889_amd/csrc/kernel_common.hpp")
+KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/step_bodies.hpp",
+                  "paper_0911_2889_amd/csrc/fft_engine.hpp", "paper_0911_2889_amd/csrc/flame_dev.hpp",
+                  "paper_0911_2889_amd/csrc/kernel_common.hpp")
 
 
 def algorithmic_bytes(n1, n2, rows=None, forcing=False):
@@ -44,6 +45,11 @@ def algorithmic_bytes(n1, n2, rows=None, forcing=False):
     return {"row": row, "col": col}
 
 
+# store kinds of flame_set_streaming_stores: names on the command line and in the record
+STORE_KINDS = {"plain": 0, "streaming": 1, "nt-w": 2, "nt-q": 3}
+STORE_KIND_NAMES = {0: "plain", 1: "streaming", 2: "nt-w", 3: "nt-q"}
+
+
 def source_digest():
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -52,10 +58,12 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, pts, rows, streaming=False):
+def measured_traffic(kernel, workload, pts, rows, streaming=0):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources and lists the same variant of the
-    kernel (points per thread, product-grid rows, store kind); else None."""
+    kernel (points per thread, product-grid rows, and a store-kind code of
+    flame_set_streaming_stores that runs it: `streaming_codes`, or one
+    `streaming` code where true stands for 1); else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_kernel_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -64,7 +72,8 @@ def measured_traffic(kernel, workload, pts, rows, streaming=False):
     if rec.get("source_digest") != source_digest():
         return None
     for v in rec.get("variants", []):
-        if v.get("points_per_thread") == pts and v.get("rows") == rows and v.get("streaming", False) == streaming:
+        codes = v.get("streaming_codes", [int(v.get("streaming", 0))])
+        if v.get("points_per_thread") == pts and v.get("rows") == rows and streaming in codes:
             return v.get("hbm_bytes_per_launch")
     return None
 
@@ -460,7 +469,7 @@ def ensemble_leg(steps, graph_steps):
     ens.autotune(steps=30)
     grids = ((128, 256), (256, 512), (512, 1024))
     tuned = {f"{n1}x{n2}": list(ens.points_per_thread(n1, n2)) + ["product" if ens.product_grid(n1, n2) else "n1"]
-             + ["streaming" if ens.streaming_stores(n1, n2) else "plain"] for n1, n2 in grids}
+             + [STORE_KIND_NAMES[ens.streaming_stores(n1, n2)]] for n1, n2 in grids}
     nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2, 3 * w.n1 // 4 if ens.product_grid(w.n1, w.n2) else w.n1).values())
                  for w in members)
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
@@ -522,8 +531,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch every step directly (no hipGraph replays)")
     ap.add_argument("--grid", choices=("product", "n1"),
                     help="form the quadratic term on 3*N1/4 rows or on N1 rows (default: autotuned)")
-    ap.add_argument("--stores", choices=("plain", "streaming"),
-                    help="store kind of the step's intermediates Q and W (default: autotuned)")
+    ap.add_argument("--stores", choices=tuple(STORE_KINDS),
+                    help="store kind of the step's intermediates Q and W: plain, non-temporal for both "
+                         "('streaming'), for W only or for Q only (default: autotuned)")
     ap.add_argument("--ensemble-steps", type=int, default=200,
                     help="steps of the 256-flame ensemble leg (0 skips it)")
     ap.add_argument("--forcing-steps", type=int, default=200,
@@ -604,7 +614,7 @@ def main():
         if args.pts:
             sim.set_points_per_thread(w.n1, w.n2, *args.pts)
         if args.stores:
-            sim.set_streaming_stores(w.n1, w.n2, args.stores == "streaming")
+            sim.set_streaming_stores(w.n1, w.n2, STORE_KINDS[args.stores])
     else:
         sim.autotune(steps=20)
     pts = sim.points_per_thread(w.n1, w.n2)

@@ -263,9 +263,14 @@ int flame_get_product_grid(flame_plan plan, int32_t n1, int32_t n2, int32_t* ena
 
 /* Store kind of the step's intermediates for the flames of grid n1 x n2:
  * enable = 1 makes the row kernel write Q, and the column kernel write Wp and
- * Wm, with non-temporal stores (the lines are not kept in L2 for reuse); 0,
- * the default, uses plain stores. The arithmetic and the results are the same
- * either way, bit for bit. Non-temporal stores shorten the kernel that writes
+ * Wm, with non-temporal stores (the lines are not kept in L2 for reuse);
+ * enable = 2 makes only Wp and Wm non-temporal, enable = 3 only Q; 0, the
+ * default, uses plain stores (other values: FLAME_ERR_INVALID_ARG). The
+ * getter returns the same code. The arithmetic and the results are the same
+ * either way, bit for bit. A workgroup writes pieces of half a 128-byte line
+ * of W (and at some grids of Q); non-temporal pieces are written back
+ * without being merged with the other half, so each non-temporal buffer
+ * moves more HBM bytes than its plain stores would. Non-temporal stores shorten the kernel that writes
  * and lengthen the one that reads next, which then misses in the caches more
  * often; which way the step gains depends on the grid and on what runs beside
  * it, so flame_autotune measures both. The state, the diagnostics and the
@@ -285,7 +290,10 @@ int flame_get_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t*
  * The configurations are (col_pts, row_pts) in {16, 8} x {16, 8, 12} on the
  * N1-row grid and, for n1 >= 128, {16, 8, 12}^2 on the product grid (row_pts
  * 12 only where n2 >= 64), each with plain and with non-temporal stores
- * (flame_set_streaming_stores). When graphs are in use
+ * (flame_set_streaming_stores). If a group's choice has both Q and W
+ * non-temporal, the same kernels with only W and with only Q non-temporal are
+ * timed as well, and the faster of the two replaces it if it runs in at most
+ * 1/0.98 of its time (it moves fewer bytes). When graphs are in use
  * (flame_set_graph_steps > 0) and the plan has several groups, whose chains
  * run concurrently in a replay, the choices are then refined jointly:
  * coordinate descent over the groups, each trial running `steps` steps of

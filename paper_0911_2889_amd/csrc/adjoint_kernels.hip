@@ -444,8 +444,8 @@ __global__ void __launch_bounds__(RowCfg<LOGN2>::THREADS) __attribute__((amdgpu_
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k = t + G * i;
-        const float2 xk = my[ff::lds_pad(k) * B];
-        const float2 xm = my[ff::lds_pad((N2 - k) & (N2 - 1)) * B];
+        const float2 xk = my[ff::Shape<LOGN2>::nat(k) * B];
+        const float2 xm = my[ff::Shape<LOGN2>::nat((N2 - k) & (N2 - 1)) * B];
         // row transform of w1: (Xi(k) + conj(Xi(-k)))/2; of i kappa2 w2: kappa2 (Xi(k) - conj(Xi(-k)))/2
         const float2 u1 = make_float2(0.5f * (xk.x + xm.x), 0.5f * (xk.y - xm.y));
         const float h = 0.5f * f.s2 * (float)k;

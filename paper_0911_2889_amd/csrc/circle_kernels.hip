@@ -137,8 +137,8 @@ __global__ void __launch_bounds__(CircleCfg<LOGN>::THREADS)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int k = t + G * i;
-      const float2 yk = my[ff::lds_pad(k) * B];
-      const float2 ym = my[ff::lds_pad(k == 0 ? 0 : N - k) * B];
+      const float2 yk = my[S::nat(k) * B];
+      const float2 ym = my[S::nat(k == 0 ? 0 : N - k) * B];
       const float2 na = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
       const float2 nb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
       const float kk = kap[i] * kap[i];

@@ -11,8 +11,9 @@
 // consecutive threads touch consecutive positions.
 //
 // Several groups share a workgroup by interleaving: group g of B stores
-// element idx at lds[pad(idx) * B + g]; pad() inserts one slot every 16
-// entries to break the power-of-two bank strides of the first passes.
+// element idx at lds[slot(idx) * B + g], where the slot map of each exchange
+// inserts spare slots to break the power-of-two bank strides (lds_pad,
+// lds_pad32 and lds_pad32_256 below; a Shape chooses them per exchange).
 //
 // Twiddles come from a table built on the host in double precision and
 // rounded once to float: pass p >= 1 with Ns = 16^p and radix R stores
@@ -94,7 +95,23 @@ constexpr PassPlan make_plan12(int e) {
   return p;
 }
 
+// LDS layouts of a transform's exchange areas (slots of 8 bytes; the LDS has
+// 64 banks of 4 bytes, and a wave's 8-byte accesses go 32 lanes at a time, so
+// an access is free of bank conflicts when its 32 lanes hit 32 distinct slots
+// modulo 32).
+// lds_pad: a spare slot after every 16 elements (N + N/16 slots). With
+// several transforms interleaved in one area (stride > 1) it keeps both the
+// strided writes of the butterflies and the unit-stride reads free of
+// conflicts; with one transform per area (stride 1) the unit-stride reads
+// take two passes over the banks.
 __host__ __device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
+// For one transform per area: a spare slot after every 32 elements keeps the
+// unit-stride reads and the stride-16 writes of a first radix-16 pass (Ns = 1)
+// free of conflicts; the second pass (Ns = 16) writes two runs of 16 elements
+// 256 apart, which 8 more slots after every 256 elements put into the other
+// half of the banks. Both fit in N + N/16 slots.
+__host__ __device__ __forceinline__ constexpr int lds_pad32(int idx) { return idx + (idx >> 5); }
+__host__ __device__ __forceinline__ constexpr int lds_pad32_256(int idx) { return idx + (idx >> 5) + 8 * (idx >> 8); }
 
 template <int LOGN, int PTS_ = kPts>
 struct Shape {
@@ -108,6 +125,16 @@ struct Shape {
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
+  // The kernels give transforms of N >= 4096 an exchange area of their own
+  // (stride 1); those use the layouts for one transform per area.
+  static constexpr bool SOLO = LOGN >= 12 && PTS == 16;
+  // slot of element i in the exchange after pass P, and in a natural-order exchange (scatter)
+  template <int P>
+  static __host__ __device__ __forceinline__ constexpr int slot(int i) {
+    if constexpr (SOLO) return ns(P) == 16 ? lds_pad32_256(i) : lds_pad32(i);
+    return lds_pad(i);
+  }
+  static __host__ __device__ __forceinline__ constexpr int nat(int i) { return SOLO ? lds_pad32(i) : lds_pad(i); }
   static_assert(LOGN >= 4 && LOGN <= 14, "transform length must be 16..16384");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
@@ -137,6 +164,9 @@ struct Shape6 {
   static constexpr int radix(int p) { return p < NBF ? plan.radix[p] : 6; }
   static constexpr int ns(int p) { return p < NBF ? plan.ns[p] : N6; }
   static constexpr int tw_off(int p) { return p < NBF ? plan.tw_off[p] : TW6; }
+  template <int P>
+  static __host__ __device__ __forceinline__ constexpr int slot(int i) { return lds_pad(i); }
+  static __host__ __device__ __forceinline__ constexpr int nat(int i) { return lds_pad(i); }
   static_assert(LOGP >= 4 && LOGP <= 11, "power-of-two part must be 16..2048");
   static_assert(PTS == 8 || PTS == 16, "8 or 16 points per thread");
 };
@@ -158,6 +188,9 @@ struct Shape12 {
   static constexpr int radix(int p) { return plan.radix[p]; }
   static constexpr int ns(int p) { return plan.ns[p]; }
   static constexpr int tw_off(int p) { return plan.tw_off[p]; }
+  template <int P>
+  static __host__ __device__ __forceinline__ constexpr int slot(int i) { return lds_pad(i); }
+  static __host__ __device__ __forceinline__ constexpr int nat(int i) { return lds_pad(i); }
   static_assert(E >= 2 && E <= 10, "length 48..12288");
 };
 
@@ -591,7 +624,7 @@ struct FftS {
       } else {
         const int base = (j - k) * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lds_pad(base + r * NS) * stride] = x[r];
+        for (int r = 0; r < R; ++r) lds[S::template slot<P>(base + r * NS) * stride] = x[r];
       }
     }
   }
@@ -610,7 +643,7 @@ struct FftS {
       float2 x[6];
       if (it + 1 < S::IT6 || j < S::N6) {
 #pragma unroll
-        for (int r = 0; r < 6; ++r) x[r] = lds[lds_pad(j + r * S::N6) * stride];
+        for (int r = 0; r < 6; ++r) x[r] = lds[S::template slot<S::NBF - 1>(j + r * S::N6) * stride];
 #pragma unroll
         for (int r = 1; r < 6; ++r) {
           float2 wr = tw.get6(it, r);
@@ -627,14 +660,17 @@ struct FftS {
     }
   }
 
+  // Natural-order read of the exchange after pass P (the next pass's inputs).
+  template <int P>
   static __host__ __device__ __forceinline__ void gather(float2 (&v)[PTS], int t, const float2* lds, int stride) {
 #pragma unroll
-    for (int i = 0; i < PTS; ++i) v[i] = lds[lds_pad(t + S::G * i) * stride];
+    for (int i = 0; i < PTS; ++i) v[i] = lds[S::template slot<P>(t + S::G * i) * stride];
   }
 
+  // Natural-order write of the registers (position t + G*i at slot S::nat).
   static __host__ __device__ __forceinline__ void scatter(const float2 (&v)[PTS], int t, float2* lds, int stride) {
 #pragma unroll
-    for (int i = 0; i < PTS; ++i) lds[lds_pad(t + S::G * i) * stride] = v[i];
+    for (int i = 0; i < PTS; ++i) lds[S::nat(t + S::G * i) * stride] = v[i];
   }
 };
 template <int LOGN, bool INV, int PTS = kPts>

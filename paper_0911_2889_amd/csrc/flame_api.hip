@@ -178,16 +178,18 @@ struct Group {
   int logn1, logn2, first, count, tiles, rpairs;
   int col_pts = ff::kPts, row_pts = ff::kPts;  // points per thread of the step kernels
   bool product = false;                        // step on the 3N1/4-row product grid
-  bool streaming = false;                      // non-temporal stores of Q and W in the step
+  int nt = 0;                                  // non-temporal stores: 0 none, 1 Q and W, 2 W, 3 Q
   bool forced = false;                         // some flame of the group has a forcing bound
   int integrator = 0;                          // 0: IF-Euler (one pass per step); 1: IF-Heun (two passes)
   int passes() const { return integrator == 1 ? 2 : 1; }
   // the column kernel's variant in pass 0 or 1 of a step
   int col_var(int pass) const {
-    const int nt = streaming ? flame::VAR_NT : 0;
-    if (integrator == 1) return (pass == 0 ? flame::VAR_HEUN_P : flame::VAR_HEUN_C) | nt;
-    return (forced ? flame::VAR_EULER_F : flame::VAR_EULER) | nt;
+    const int ntv = nt_w() ? flame::VAR_NT : 0;
+    if (integrator == 1) return (pass == 0 ? flame::VAR_HEUN_P : flame::VAR_HEUN_C) | ntv;
+    return (forced ? flame::VAR_EULER_F : flame::VAR_EULER) | ntv;
   }
+  bool nt_q() const { return nt == 1 || nt == 3; }  // the row kernel's stores of Q
+  bool nt_w() const { return nt == 1 || nt == 2; }  // the column kernel's stores of Wp and Wm
   int rows() const { return product ? 3 * (1 << logn1) / 4 : (1 << logn1); }
   // phi points of the quadratic term's grid: the 12-point row kernel forms it on 3 N2/4
   int cols() const { return row_pts == 12 ? 3 * (1 << logn2) / 4 : (1 << logn2); }
@@ -390,7 +392,7 @@ int apply_rows(flame_plan p, int gi) {
 void launch_step_row(flame_plan p, const Group& gr, long long n, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr,
                      hipStream_t st = nullptr) {
   flame::launch_row(gr.logn2, flame::ROW_STEP, gr.rgroups(), gr.count, st ? st : p->stream, p->ddev + gr.first, n,
-                    nullptr, nullptr, gr.row_pts, e0, e1, gr.streaming);
+                    nullptr, nullptr, gr.row_pts, e0, e1, gr.nt_q());
 }
 
 void launch_step_col(flame_plan p, const Group& gr, long long n, int pass, hipEvent_t e0 = nullptr,
@@ -426,7 +428,7 @@ int build_graph(flame_plan p) {
   // one pass of group gi at step offset s: row node, then column node, chained after the group's last node
   auto add_pass = [&](size_t gi, int s, int pass) -> int {
     const Group& gr = p->groups[gi];
-    const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts, gr.streaming);
+    const flame::KernelLaunch rk = flame::row_step_kernel(gr.logn2, gr.row_pts, gr.nt_q());
     const flame::KernelLaunch ck =
         gr.product ? flame::colp_kernel_info(gr.logn1, flame::COL_STEP, gr.col_pts, gr.col_var(pass))
                    : flame::col_step_kernel(gr.logn1, gr.col_pts, gr.col_var(pass));
@@ -1025,7 +1027,7 @@ const char* ens_reason(const Group& gr) {
   if (!flame::ensemble_supports(gr.logn1, gr.logn2)) return "the persistent kernel has bodies for n1 in [128, 1024], n2 in [128, 2048]";
   if (!gr.product || gr.col_pts != 12) return "the persistent kernel steps the product grid with 12 column points per thread";
   if (gr.row_pts != 16) return "the persistent kernel's row transforms use 16 points per thread";
-  if (gr.streaming) return "the persistent kernel uses plain stores";
+  if (gr.nt != 0) return "the persistent kernel uses plain stores";
   if (gr.integrator != 0 || gr.forced) return "the persistent kernel runs unforced integrating-factor Euler";
   return nullptr;
 }
@@ -1445,10 +1447,11 @@ int flame_get_product_grid(flame_plan p, int32_t n1, int32_t n2, int32_t* enable
 int flame_set_streaming_stores(flame_plan p, int32_t n1, int32_t n2, int32_t enable) {
   int rc = check_plan(p);
   if (rc) return rc;
+  if (enable < 0 || enable > 3) return fail(FLAME_ERR_INVALID_ARG, "store kind %d: 0, 1, 2 or 3", enable);
   bool found = false;
   for (Group& gr : p->groups) {
     if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
-      gr.streaming = enable != 0;
+      gr.nt = enable;
       found = true;
     }
   }
@@ -1464,7 +1467,7 @@ int flame_get_streaming_stores(flame_plan p, int32_t n1, int32_t n2, int32_t* en
   if (!enabled) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
   for (const Group& gr : p->groups) {
     if ((1 << gr.logn1) == n1 && (1 << gr.logn2) == n2) {
-      *enabled = gr.streaming ? 1 : 0;
+      *enabled = gr.nt;
       return FLAME_OK;
     }
   }
@@ -1478,7 +1481,7 @@ constexpr float kAutotuneMargin = 0.98f;
 struct TuneCfg {
   bool product;
   int c, r;
-  bool nt;
+  int nt;  // store kind, as Group::nt
   bool operator==(const TuneCfg& o) const { return product == o.product && c == o.c && r == o.r && nt == o.nt; }
 };
 
@@ -1493,7 +1496,7 @@ static std::vector<TuneCfg> tune_cfgs(const Group& gr) {
     pcols.push_back(8);
   }
   pcols.push_back(12);
-  for (bool nt : {false, true}) {
+  for (int nt : {0, 1}) {
     for (int c : cols)
       for (int r : rows) cfgs.push_back(TuneCfg{false, c, r, nt});
     if (gr.logn1 >= flame::kMinLogProduct)
@@ -1508,7 +1511,7 @@ static int tune_select(flame_plan p, size_t gi, const TuneCfg& cf) {
   const bool grid_change = gr.product != cf.product || (gr.row_pts == 12) != (cf.r == 12);
   gr.col_pts = cf.c;
   gr.row_pts = cf.r;
-  gr.streaming = cf.nt;
+  gr.nt = cf.nt;
   gr.product = cf.product;
   if (grid_change) return apply_rows(p, (int)gi);
   return FLAME_OK;
@@ -1570,7 +1573,7 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
     bool improved = false;
     for (size_t gi = 0; rc == FLAME_OK && gi < ng; ++gi) {
       const Group& gr = p->groups[gi];
-      const TuneCfg cur{gr.product, gr.col_pts, gr.row_pts, gr.streaming};
+      const TuneCfg cur{gr.product, gr.col_pts, gr.row_pts, gr.nt};
       TuneCfg keep = cur;
       for (const TuneCfg& cf : tune_cfgs(gr)) {
         if (cf == cur) continue;
@@ -1607,37 +1610,46 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
 // configurations run on a GPU that is still raising its clocks), then select
 // the fastest unless the default (16 points per thread, product grid where it
 // exists, plain stores) is within kAutotuneMargin of it, so that choices
-// within timing noise of each other do not flip between runs.
+// within timing noise of each other do not flip between runs. If the choice
+// has both Q and W non-temporal, the same kernels with only one of them
+// non-temporal are timed too (two rounds), and the faster of those is kept
+// if it is within the margin: non-temporal pieces of half a line are written
+// back unmerged, so one non-temporal buffer moves fewer bytes than two.
 static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipEvent_t ev0, hipEvent_t ev1,
                           int* tried) {
   const Group& gr = p->groups[gi];
+  auto time_cfg = [&](const TuneCfg& cf, float* out) -> int {
+    int rc = tune_select(p, gi, cf);
+    for (int f = gr.first; rc == FLAME_OK && f < gr.first + gr.count; ++f)
+      if (!p->w_valid[f]) rc = rebuild_w(p, f);
+    if (rc) return rc;
+    // one untimed step, then `steps` timed steps of this group alone
+    hipError_t e = hipSuccess;
+    for (int s = 0; s <= steps; ++s) {
+      if (s == 1) e = hipEventRecord(ev0, p->stream);
+      for (int pass = 0; pass < gr.passes(); ++pass) {
+        launch_step_row(p, gr, n0);
+        launch_step_col(p, gr, n0, pass);
+      }
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev1, p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    rc = last_launch("autotune launch");
+    if (rc) return rc;
+    *out = std::min(*out, ms);
+    return FLAME_OK;
+  };
   const std::vector<TuneCfg> cfgs = tune_cfgs(gr);
-  const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts, false};
+  const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts, 0};
   std::vector<float> t_best(cfgs.size(), 1e30f);
   for (int round = 0; round < 2; ++round) {
     for (size_t ci = 0; ci < cfgs.size(); ++ci) {
-      int rc = tune_select(p, gi, cfgs[ci]);
-      for (int f = gr.first; rc == FLAME_OK && f < gr.first + gr.count; ++f)
-        if (!p->w_valid[f]) rc = rebuild_w(p, f);
-      if (rc) return rc;
-      // one untimed step, then `steps` timed steps of this group alone
-      hipError_t e = hipSuccess;
-      for (int s = 0; s <= steps; ++s) {
-        if (s == 1) e = hipEventRecord(ev0, p->stream);
-        for (int pass = 0; pass < gr.passes(); ++pass) {
-          launch_step_row(p, gr, n0);
-          launch_step_col(p, gr, n0, pass);
-        }
-      }
-      if (e == hipSuccess) e = hipEventRecord(ev1, p->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(ev1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-      if (e != hipSuccess) return hip_fail(e, "autotune timing");
-      rc = last_launch("autotune launch");
+      const int rc = time_cfg(cfgs[ci], &t_best[ci]);
       if (rc) return rc;
       if (round == 0) ++*tried;
-      t_best[ci] = std::min(t_best[ci], ms);
     }
   }
   size_t best = 0, dflt = 0;
@@ -1646,7 +1658,20 @@ static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipE
     if (cfgs[ci] == default_cfg) dflt = ci;
   }
   if (t_best[best] > kAutotuneMargin * t_best[dflt]) best = dflt;
-  return tune_select(p, gi, cfgs[best]);
+  TuneCfg pick = cfgs[best];
+  if (pick.nt == 1) {
+    const TuneCfg alt[2] = {TuneCfg{pick.product, pick.c, pick.r, 2}, TuneCfg{pick.product, pick.c, pick.r, 3}};
+    float t_alt[2] = {1e30f, 1e30f};
+    for (int round = 0; round < 2; ++round)
+      for (int k = 0; k < 2; ++k) {
+        const int rc = time_cfg(alt[k], &t_alt[k]);
+        if (rc) return rc;
+        if (round == 0) ++*tried;
+      }
+    const int k = t_alt[0] <= t_alt[1] ? 0 : 1;
+    if (kAutotuneMargin * t_alt[k] <= t_best[best]) pick = alt[k];
+  }
+  return tune_select(p, gi, pick);
 }
 
 int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {

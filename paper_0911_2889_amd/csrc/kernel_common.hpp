@@ -18,7 +18,7 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[PTS], int t, float2* lds,
     ff::Fft<LOGN, INV, PTS>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
     if constexpr (P + 1 < S::NPASS) {
       __syncthreads();
-      ff::Fft<LOGN, INV, PTS>::gather(v, t, lds, stride);
+      ff::Fft<LOGN, INV, PTS>::template gather<P>(v, t, lds, stride);
       __syncthreads();
     }
     fft_passes<LOGN, INV, OUTER, PTS, P + 1>(v, t, lds, stride, tw);
@@ -44,7 +44,7 @@ __device__ __forceinline__ void fft_s(float2 (&v)[S::PTS], int t, float2* lds, i
     ff::FftS<S, INV>::template butterflies<P, TW, OUTER>(v, t, lds, stride, tw);
     if constexpr (P + 1 < S::NPASS) {
       __syncthreads();
-      ff::FftS<S, INV>::gather(v, t, lds, stride);
+      ff::FftS<S, INV>::template gather<P>(v, t, lds, stride);
       __syncthreads();
     }
     fft_s<S, INV, OUTER, P + 1>(v, t, lds, stride, tw);
@@ -186,7 +186,7 @@ __device__ __forceinline__ void fft6(Regs<PTS>& v, Out6<LOGP, PTS>& o, int t, fl
     F::template butterflies<P, TW, false>(v, t, lds, stride, tw);
     __syncthreads();
     if constexpr (P + 1 < S::NBF) {
-      F::gather(v, t, lds, stride);
+      F::template gather<P>(v, t, lds, stride);
       __syncthreads();
     }
     fft6<LOGP, INV, PTS, TW, P + 1>(v, o, t, lds, stride, tw);

@@ -334,8 +334,8 @@ __device__ __forceinline__ void row_body(const FlameDev& f, long long n, const f
 #pragma unroll
     for (int i = 0; i < LOW; ++i) {
       const int k = t + G * i;
-      const float2 yk = my[ff::lds_pad(k) * B];
-      const float2 ym = my[ff::lds_pad(k == 0 ? 0 : L2 - k) * B];
+      const float2 yk = my[S::nat(k) * B];
+      const float2 ym = my[S::nat(k == 0 ? 0 : L2 - k) * B];
       const float2 qa = make_float2(0.5f * (yk.x + ym.x), 0.5f * (yk.y - ym.y));
       const float2 qb = make_float2(0.5f * (yk.y + ym.y), 0.5f * (ym.x - yk.x));
       st_nt<NT>(Q + tiled(ja, k, n1, ts), qa);

@@ -217,14 +217,16 @@ class FlameEnsemble:
         return bool(v.value)
 
     def set_streaming_stores(self, n1, n2, enable):
-        """Write the step's intermediates Q and W of the flames of grid n1 x n2 with
-        non-temporal stores (True) or plain ones (False); the results are identical."""
-        native.check(self.lib.flame_set_streaming_stores(self.plan, int(n1), int(n2), int(bool(enable))))
+        """Write the step's intermediates of the flames of grid n1 x n2 with
+        non-temporal stores: True or 1 both Q and W, 2 W only, 3 Q only; False
+        or 0 plain stores. The results are identical."""
+        native.check(self.lib.flame_set_streaming_stores(self.plan, int(n1), int(n2), int(enable)))
 
     def streaming_stores(self, n1, n2):
+        """The store kind: 0 plain, 1 non-temporal Q and W, 2 W only, 3 Q only."""
         v = ctypes.c_int32()
         native.check(self.lib.flame_get_streaming_stores(self.plan, int(n1), int(n2), ctypes.byref(v)))
-        return bool(v.value)
+        return v.value
 
     def autotune(self, steps=20):
         """Time every grid, points-per-thread and store-kind choice per grid group and

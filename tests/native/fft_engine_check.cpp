@@ -41,7 +41,7 @@ void passes(std::vector<Regs<PTS>>& v, float2* lds, int stride, const float2* tw
       }
     }
     if constexpr (P + 1 < S::NPASS) {
-      for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
+      for (int t = 0; t < S::G; ++t) F::template gather<P>(v[t].a, t, lds, stride);
     }
     passes<LOGN, INV, P + 1, OUTER, PTS>(v, lds, stride, tw, cached);
   }
@@ -82,7 +82,7 @@ void passes6(std::vector<Regs<PTS>>& v, std::vector<std::vector<float2>>& o, flo
       }
     }
     if constexpr (P + 1 < S::NBF) {
-      for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
+      for (int t = 0; t < S::G; ++t) F::template gather<P>(v[t].a, t, lds, stride);
     }
     passes6<LOGP, INV, PTS, P + 1>(v, o, lds, stride, tw, cached);
   } else {
@@ -140,7 +140,7 @@ void passes12(std::vector<Regs<12>>& v, float2* lds, int stride, const float2* t
       }
     }
     if constexpr (P + 1 < S::NPASS) {
-      for (int t = 0; t < S::G; ++t) F::gather(v[t].a, t, lds, stride);
+      for (int t = 0; t < S::G; ++t) F::template gather<P>(v[t].a, t, lds, stride);
     }
     passes12<E, INV, P + 1, OUTER>(v, lds, stride, tw, cached);
   }

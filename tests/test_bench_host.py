@@ -47,13 +47,20 @@ def test_traffic_lookup_needs_digest_and_variant(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     rec = {"kernel": "col_kernel", "workload": "w", "source_digest": bench.source_digest(),
            "variants": [{"points_per_thread": 16, "rows": 1536, "hbm_bytes_per_launch": 1.5e7},
-                        {"points_per_thread": 16, "rows": 1536, "streaming": True, "hbm_bytes_per_launch": 1.6e7}]}
+                        {"points_per_thread": 16, "rows": 1536, "streaming": True, "hbm_bytes_per_launch": 1.6e7},
+                        {"points_per_thread": 12, "rows": 1536, "streaming": 2, "hbm_bytes_per_launch": 1.7e7},
+                        {"points_per_thread": 12, "rows": 2048, "streaming_codes": [1, 2], "hbm_bytes_per_launch": 1.8e7}]}
     (tmp_path / "profiles" / "col_kernel_w_traffic.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "source_digest", lambda: rec["source_digest"])
     assert bench.measured_traffic("col", "w", 16, 1536) == 1.5e7
     assert bench.measured_traffic("col", "w", 16, 1536, streaming=True) == 1.6e7
     assert bench.measured_traffic("col", "w", 8, 1536, streaming=True) is None
+    assert bench.measured_traffic("col", "w", 12, 1536, streaming=2) == 1.7e7  # W only non-temporal
+    assert bench.measured_traffic("col", "w", 12, 1536, streaming=1) is None
+    assert bench.measured_traffic("col", "w", 12, 2048, streaming=1) == 1.8e7  # one kernel serves codes 1 and 2
+    assert bench.measured_traffic("col", "w", 12, 2048, streaming=2) == 1.8e7
+    assert bench.measured_traffic("col", "w", 12, 2048, streaming=3) is None
     assert bench.measured_traffic("col", "w", 8, 1536) is None
     assert bench.measured_traffic("col", "w", 16, 2048) is None
     assert bench.measured_traffic("row", "w", 16, 1536) is None

@@ -120,7 +120,9 @@ def test_autotune_keeps_the_state_and_agrees_with_the_oracle(graph_steps):
     # rows (12 rows: the phi product grid, n2 >= 64), and {16, 8, 12}^2 on the
     # theta product grid where n1 >= 128 (256x512 and 128x64), each with
     # plain and with non-temporal stores
-    assert ens.autotune(steps=4) == 12 + 30 + 30
+    # (a group whose choice has Q and W non-temporal also times W only and Q only)
+    tried = ens.autotune(steps=4)
+    assert tried - (12 + 30 + 30) in (0, 2, 4, 6), tried
     assert ens.step_index == 5
     for f in range(len(members)):
         assert np.array_equal(ens.spectrum(f).cpu().numpy(), before[f])

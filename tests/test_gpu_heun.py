@@ -128,7 +128,7 @@ def test_heun_autotune_keeps_state_and_adjoint_is_refused(flame):
     sim.set_spectrum(half)
     sim.step(3)
     before = sim.spectrum().cpu().numpy()
-    assert sim.autotune(steps=2) == 30  # (grid, points per thread, store kind)
+    assert sim.autotune(steps=2) in (30, 32)  # (grid, points per thread, store kind), + W only / Q only
     assert sim.step_index == 3
     assert np.array_equal(sim.spectrum().cpu().numpy(), before)
     sim.step(5)

@@ -1,5 +1,5 @@
 """Non-temporal stores of the step's intermediates (flame_set_streaming_stores):
-the same kernels with another store kind for Q and W, so every result must be
+the same kernels with another store kind for Q, W or both, so every result must be
 bitwise the plain-store result, for each kernel variant (both grids, both
 points-per-thread choices, the split product kernel, forcing, Heun, graph
 replays, ensembles), and the oracle's within the step's tolerance."""
@@ -54,6 +54,8 @@ def test_streaming_stores_give_the_plain_bits(flame, n1, n2, product, pts):
     plain = run(flame, w, half, 6, False, product, pts)
     streamed = run(flame, w, half, 6, True, product, pts)
     assert np.array_equal(plain, streamed)
+    for kind in (2, 3):  # W only, Q only
+        assert np.array_equal(plain, run(flame, w, half, 6, kind, product, pts)), kind
     p = oracle.Params(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
     ref = oracle_trajectory(half, p, [6])[6]
     assert rel_l2(ref, half) > 1e-3
@@ -99,6 +101,8 @@ def test_streaming_is_set_per_grid_in_an_ensemble(flame):
         ens.set_streaming_stores(128, 128, True)
     with pytest.raises(flame.native.FlameError):
         ens.streaming_stores(512, 512)
+    with pytest.raises(flame.native.FlameError):
+        ens.set_streaming_stores(256, 512, 4)
 
 
 def test_switching_the_store_kind_between_graph_replays(flame):
@@ -111,7 +115,7 @@ def test_switching_the_store_kind_between_graph_replays(flame):
     sim = flame.FlameSim(n1, n2, gamma=w.gamma, theta_pi=w.theta_pi, t0=w.t0, dt=w.dt)
     sim.set_graph_steps(5)
     sim.set_spectrum(half)
-    for k, streaming in enumerate((False, True, False, True)):
+    for k, streaming in enumerate((False, True, 2, 3)):
         sim.set_streaming_stores(n1, n2, streaming)
         sim.step(5)
         assert sim.step_index == 5 * (k + 1)
