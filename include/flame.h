@@ -114,10 +114,12 @@ int flame_set_state(flame_plan plan, int32_t flame, const float* phi, int64_t n)
  * n1 x n2 row-major): Phi(x_j) = sum_k Phi~_k exp(i k.x_j). */
 int flame_get_state(flame_plan plan, int32_t flame, float* phi);
 
-/* The caller wrote the state buffers directly (e.g. restored a checkpoint
- * with a device copy): set the step index to n and mark the plan's
- * intermediate arrays stale so the next step rebuilds them. */
-int flame_state_modified(flame_plan plan, int64_t n);
+/* The caller wrote the state buffer of flame `flame` directly (e.g. restored
+ * a checkpoint with a device copy), or those of every flame with flame = -1:
+ * set the plan's step index to n (one index for all flames) and mark the
+ * intermediate arrays of that flame (or of all) stale, so the next step
+ * rebuilds them (the column pass a1 of Section 3). */
+int flame_state_modified(flame_plan plan, int32_t flame, int64_t n);
 
 /* Step index of the plan (time of flame f is t0_f + index * dt_f). */
 int flame_step_index(flame_plan plan, int64_t* n);
@@ -142,11 +144,15 @@ int flame_step(flame_plan plan, int32_t nsteps);
  *   out4[2] = area excess J = mean over the grid of sqrt(1 + x) - 1,
  *             x = |grad Phi|^2 / r0^2, evaluated as x / (1 + sqrt(1 + x)),
  *   out4[3] = 1 if every state entry is finite, else 0.
- * out4 is dev memory (4 doubles), written on the stream. */
-int flame_diagnostics(flame_plan plan, int32_t flame, double* out4);
+ * out4 is dev memory (4 doubles), written on the stream. dJ_dstate
+ * (nullable, dev, the state layout): when given, also the adjoint seed
+ * dJ/dPhi at the current state as a cotangent, i.e. flame_area_gradient
+ * at the current step index and state; that uses the plan's workspace, so
+ * the next step rebuilds the flame's intermediates. */
+int flame_diagnostics(flame_plan plan, int32_t flame, double* out4, void* dJ_dstate);
 
 /* The same averages written to host memory (host_out4, 4 doubles), for
- * callers that check a run as it goes: queues flame_diagnostics into the
+ * callers that check a run as it goes: queues flame_diagnostics (no seed) into the
  * plan's workspace, copies the result and waits for the plan's stream.
  * Returns FLAME_ERR_NONFINITE (with host_out4 filled) when some state entry
  * is not finite, FLAME_OK otherwise. */

@@ -1003,11 +1003,16 @@ int flame_get_state(flame_plan p, int32_t flame, float* phi) {
   return last_launch("get_state launch");
 }
 
-int flame_state_modified(flame_plan p, int64_t n) {
+int flame_state_modified(flame_plan p, int32_t flame, int64_t n) {
   int rc = check_plan(p);
   if (rc) return rc;
+  if (flame < -1 || flame >= p->nfl)
+    return fail(FLAME_ERR_INVALID_ARG, "flame index %d out of range [-1, %d)", flame, p->nfl);
   p->n = n;
-  for (auto& v : p->w_valid) v = 0;
+  if (flame < 0)
+    for (auto& v : p->w_valid) v = 0;
+  else
+    p->w_valid[flame] = 0;
   return FLAME_OK;
 }
 
@@ -1195,7 +1200,7 @@ int flame_step(flame_plan p, int32_t nsteps) {
   return last_launch("step launch");
 }
 
-int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
+int flame_diagnostics(flame_plan p, int32_t flame, double* out4, void* dJ_dstate) {
   int rc = check_plan(p, flame);
   if (rc) return rc;
   if (!out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
@@ -1220,7 +1225,9 @@ int flame_diagnostics(flame_plan p, int32_t flame, double* out4) {
     flame::launch_diag_final(p->stream, p->ddev, flame, p->n, s.rgroups, s.n_spec, out4);
   }
   break_chain(p);
-  return last_launch("diagnostics launch");
+  rc = last_launch("diagnostics launch");
+  if (rc || !dJ_dstate) return rc;
+  return flame_area_gradient(p, flame, p->n, p->hdev[flame].S, dJ_dstate);
 }
 
 int flame_diagnostics_host(flame_plan p, int32_t flame, double* host_out4) {
@@ -1229,7 +1236,7 @@ int flame_diagnostics_host(flame_plan p, int32_t flame, double* host_out4) {
   if (!host_out4) return fail(FLAME_ERR_INVALID_ARG, "null output pointer");
   double* dev = reinterpret_cast<double*>(reinterpret_cast<char*>(p->ddev) - p->layout.off_dev + p->layout.off_diag) +
                 4 * (size_t)flame;
-  rc = flame_diagnostics(p, flame, dev);
+  rc = flame_diagnostics(p, flame, dev, nullptr);
   if (rc) return rc;
   DeviceGuard g(p->device);
   hipError_t e = hipMemcpyAsync(host_out4, dev, 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream);

@@ -83,10 +83,10 @@ def load():
         "flame_get_spectrum": [P, i32, P],
         "flame_set_state": [P, i32, P, i64],
         "flame_get_state": [P, i32, P],
-        "flame_state_modified": [P, i64],
+        "flame_state_modified": [P, i32, i64],
         "flame_step_index": [P, ctypes.POINTER(i64)],
         "flame_step": [P, i32],
-        "flame_diagnostics": [P, i32, P],
+        "flame_diagnostics": [P, i32, P, ctypes.c_void_p],
         "flame_diagnostics_host": [P, i32, ctypes.POINTER(ctypes.c_double)],
         "flame_adjoint_step": [P, i32, i64, P, P, P],
         "flame_area_gradient": [P, i32, i64, P, P],

@@ -96,8 +96,12 @@ class FlameEnsemble:
         native.check(self.lib.flame_get_state(self.plan, flame, ctypes.c_void_p(out.data_ptr())))
         return out
 
-    def state_modified(self, n):
-        native.check(self.lib.flame_state_modified(self.plan, int(n)))
+    def state_modified(self, n, flame=-1):
+        """The state buffer of `flame` (-1: of every flame) was written directly:
+        set the step index to n and rebuild that flame's intermediates at the next step."""
+        if flame != -1:
+            self._check_flame(flame)
+        native.check(self.lib.flame_state_modified(self.plan, int(flame), int(n)))
 
     @property
     def step_index(self):
@@ -109,11 +113,14 @@ class FlameEnsemble:
     def step(self, nsteps=1):
         native.check(self.lib.flame_step(self.plan, int(nsteps)))
 
-    def diagnostics(self, flame=0, out=None):
-        """Mean radius, averaged velocity, area excess and finite flag (doubles)."""
+    def diagnostics(self, flame=0, out=None, dJ_dstate=None):
+        """Mean radius, averaged velocity, area excess and finite flag (doubles);
+        with dJ_dstate (a device tensor in the state layout) also the adjoint seed
+        dJ/dPhi at the current state, written there."""
         self._check_flame(flame)
         buf = out if out is not None else torch.empty(4, dtype=torch.float64, device=self.device)
-        native.check(self.lib.flame_diagnostics(self.plan, flame, ctypes.c_void_p(buf.data_ptr())))
+        seed = ctypes.c_void_p(dJ_dstate.data_ptr()) if dJ_dstate is not None else None
+        native.check(self.lib.flame_diagnostics(self.plan, flame, ctypes.c_void_p(buf.data_ptr()), seed))
         if out is not None:
             return out
         v = buf.cpu().tolist()

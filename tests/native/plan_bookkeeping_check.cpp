@@ -145,10 +145,11 @@ int main(int argc, char** argv) {
     double ms[4];
     int64_t cnt[4];
     double out4[4 * 5];
+    std::vector<float> seed(256 * 512, 0.f);  // the adjoint seed of any flame of the plan
     for (int it = 0; it < 20; ++it) {
       CHECK(flame_timing_begin(p));
       CHECK(flame_step(p, 1 + it % 4));
-      CHECK(flame_diagnostics(p, it % 5, out4));
+      CHECK(flame_diagnostics(p, it % 5, out4, it % 4 == 1 ? seed.data() : nullptr));
       if (it % 3) CHECK(flame_timing_end(p, ms, cnt));
     }
     // autotuning alone and jointly (graphs set, several groups)
@@ -165,7 +166,9 @@ int main(int argc, char** argv) {
     CHECK(flame_synthesize(p, 2, pl.states[2], phi.data()));
     CHECK(flame_get_state(p, 2, phi.data()));
     CHECK(flame_set_state(p, 2, phi.data(), 5));
-    CHECK(flame_state_modified(p, 5));
+    CHECK(flame_state_modified(p, 2, 5));
+    CHECK(flame_state_modified(p, -1, 5));
+    if (flame_state_modified(p, 5, 5) != FLAME_ERR_INVALID_ARG) return 7;
     CHECK(flame_step(p, 6));
     CHECK(flame_timing_begin(p));
     CHECK(flame_step(p, 7));

@@ -71,6 +71,57 @@ def test_area_gradient_matches_oracle(n1, n2):
     assert rel_l2(got, ref) < 1e-5
 
 
+@pytest.mark.parametrize("n1,n2", [(64, 128), (256, 512)])
+def test_diagnostics_seed_is_the_area_gradient(n1, n2):
+    """flame_diagnostics with a seed buffer writes the area gradient at the
+    current state and step index (the oracle's, and area_gradient's bits),
+    besides the averages; after it the step rebuilds its intermediates."""
+    t0, dt, steps = 3.0, 0.1, 5
+    half = spectrum(n1, n2, 31 + n1, 0.3)
+    sim = make(n1, n2, t0, dt)
+    sim.set_spectrum(half)
+    sim.step(steps)
+    seed = sim.new_cotangent()
+    d = sim.diagnostics(dJ_dstate=seed)
+    assert d["finite"]
+    lo = sim.new_cotangent()
+    sim.area_gradient(steps, sim.states[0].clone(), lo)
+    assert torch.equal(seed, lo)
+    state = oracle.half_to_full(sim.spectrum().cpu().numpy().astype(np.complex128), n1, n2)
+    p = oracle.Params(n1, n2, t0=t0, dt=dt)
+    ref = oracle.full_to_half(oracle.area_gradient(state, p, steps), n1, n2)
+    assert rel_l2(from_internal(seed, n1, n2), ref) < 1e-5
+    # the intermediates are rebuilt: the next steps equal an undisturbed run's
+    ref_sim = make(n1, n2, t0, dt)
+    ref_sim.set_spectrum(half)
+    ref_sim.step(steps + 3)
+    sim.step(3)
+    assert np.array_equal(sim.spectrum().cpu().numpy(), ref_sim.spectrum().cpu().numpy())
+
+
+def test_state_modified_marks_one_flame_or_all():
+    from paper_0911_2889_amd import FlameEnsemble, native
+    descs = [dict(n1=64, n2=128, t0=3.0, dt=0.1), dict(n1=128, n2=256, t0=3.0, dt=0.1)]
+    halves = [spectrum(d["n1"], d["n2"], 40 + i, 0.2) for i, d in enumerate(descs)]
+    ens = FlameEnsemble(descs)
+    for f, h in enumerate(halves):
+        ens.set_spectrum(h, flame=f)
+    ens.step(4)
+    saved = ens.states[1].clone()
+    ens.step(2)
+    ens.states[1].copy_(saved)  # restore flame 1 only
+    assert ens.lib.flame_state_modified(ens.plan, 2, 6) == native.FLAME_ERR_INVALID_ARG  # no flame 2
+    ens.state_modified(4, flame=1)  # one step index for the plan: flame 0 goes on from 6 as if at 4
+    ens.step(2)
+    ref = FlameEnsemble(descs[1:])
+    ref.set_spectrum(halves[1], flame=0)
+    ref.step(6)
+    assert np.array_equal(ens.spectrum(1).cpu().numpy(), ref.spectrum(0).cpu().numpy())
+    ens.state_modified(6, flame=-1)
+    ens.step(1)
+    assert ens.step_index == 7
+
+
 def test_synthesize_matches_get_state():
     n1, n2 = 128, 256
     half = spectrum(n1, n2, 5, 0.1)
