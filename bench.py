@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 CIRCLE_SOURCES = ("paper_0911_2889_amd/csrc/circle_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
+                  "paper_0911_2889_amd/csrc/flame_dev.hpp",
                   "paper_0911_2889_amd/csrc/kernel_common.hpp")
 KERNEL_SOURCES = ("paper_0911_2889_amd/csrc/flame_kernels.hip", "paper_0911_2889_amd/csrc/step_bodies.hpp",
                   "paper_0911_2889_amd/csrc/fft_engine.hpp", "paper_0911_2889_amd/csrc/flame_dev.hpp",
