@@ -543,6 +543,8 @@ def main():
                     help="steps of the integrating-factor Heun leg on the same workload; 0 skips it")
     ap.add_argument("--no-long-run", action="store_true",
                     help="skip the long-horizon run (8192 x 8192, Heun, t = 200 .. 2600)")
+    ap.add_argument("--long-run-t-end", type=float, default=2600.0,
+                    help="end time of the long-horizon run (a shorter one serves profiling of its kernels)")
     ap.add_argument("--adjoint-steps", type=int, default=100,
                     help="steps of the checkpointed adjoint leg on 1024x2048 (0 skips it)")
     ap.add_argument("--circle-steps", type=int, default=200,
@@ -714,7 +716,7 @@ def main():
         result["heun"] = heun_leg(w, half, args.heun_steps, graph_steps, args.diag_every, ms / args.steps)
 
     if not args.no_long_run:
-        result["long_run"] = long_run_leg()
+        result["long_run"] = long_run_leg(t_end=args.long_run_t_end)
 
     if args.circle_steps > 0:
         rec = circle_record()
