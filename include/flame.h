@@ -228,7 +228,8 @@ int flame_timing_begin(flame_plan plan);
 /* Stop timing, synchronise the plan's stream and report the summed
  * durations in milliseconds and the counts, per kind: [0] row step kernels,
  * [1] column step kernels, [2] diagnostics and other kernels, [3] graph
- * launches (each covering steps_per_graph steps). Bracketed launches that
+ * launches (each covering steps_per_graph steps) and persistent launches
+ * (each covering the steps of one flame_step call, up to 1000). Bracketed launches that
  * follow each other share their boundary event, so their intervals include
  * the launch gap. ms4 and counts4 are host arrays of 4 entries. */
 int flame_timing_end(flame_plan plan, double* ms4, int64_t* counts4);
@@ -307,7 +308,9 @@ int flame_get_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t*
  * in at most 98 % of the best time so far. The states
  * and the step index are saved in the workspace and restored afterwards,
  * also when a trial fails, so the call does not change the simulation; it
- * synchronises the stream.
+ * synchronises the stream. With the persistent launch enabled
+ * (flame_set_persistent), whose kernels are fixed, it fails with
+ * FLAME_ERR_INVALID_ARG.
  * *n_configs_tried (nullable) receives the number of timed configurations. */
 int flame_autotune(flame_plan plan, int32_t steps, int32_t* n_configs_tried);
 

@@ -1685,6 +1685,8 @@ int flame_autotune(flame_plan p, int32_t steps, int32_t* n_configs_tried) {
   int rc = check_plan(p);
   if (rc) return rc;
   if (steps <= 0) return fail(FLAME_ERR_INVALID_ARG, "steps must be > 0");
+  if (p->persistent)
+    return fail(FLAME_ERR_INVALID_ARG, "the persistent launch runs fixed kernels: disable it before autotuning");
   rc = check_r0(p, 0, p->nfl, p->n, p->n, true);  // every timed step runs at the current index
   if (rc) return rc;
   DeviceGuard g(p->device);

@@ -184,6 +184,7 @@ int main(int argc, char** argv) {
     const int grids[3][2] = {{128, 256}, {256, 512}, {512, 1024}};
     for (const auto& g : grids) CHECK(flame_set_points_per_thread(pl.p, g[0], g[1], 12, 16));
     CHECK(flame_set_persistent(pl.p, 1, 0, 0));
+    if (flame_autotune(pl.p, 1, nullptr) != FLAME_ERR_INVALID_ARG) return 8;
     CHECK(flame_step(pl.p, 3));
     int32_t on = 0, wgs = 0;
     CHECK(flame_get_persistent(pl.p, &on, &wgs));

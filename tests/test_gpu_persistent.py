@@ -115,6 +115,9 @@ def test_persistent_refuses_configurations_it_has_no_kernel_for():
     ok = FlameEnsemble([dict(n1=128, n2=256)])
     ok.set_points_per_thread(128, 256, 12, 16)
     ok.set_persistent(True)
+    with pytest.raises(native.FlameError) as exc:
+        ok.autotune(steps=1)  # the persistent kernel's configuration is fixed
+    assert exc.value.code == native.FLAME_ERR_INVALID_ARG
     ok.set_streaming_stores(128, 256, True)
     with pytest.raises(native.FlameError) as exc:
         ok.step(1)  # a later change the persistent kernel lacks is refused at the step
