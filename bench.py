@@ -328,6 +328,7 @@ def long_run_leg(n=8192, t_end=2600.0, dt=0.1, every_t=5.0, fits_from=(1500.0,))
     every = int(round(every_t / dt))
     sim = FlameSim(n, n, gamma=0.8, theta_pi=1.0, t0=200.0, dt=dt, integrator=1)
     sim.set_phi(synth.physical_noise(n, n, seed=0, kind="uniform", scale=1e-3))
+    sim.autotune(steps=3)  # leaves the state and the step index as they are
     sim.set_graph_steps(every)
     nd = int(round((t_end - 200.0) / dt)) // every
     diag = torch.zeros((nd, 4), dtype=torch.float64, device=sim.device)
@@ -346,6 +347,8 @@ def long_run_leg(n=8192, t_end=2600.0, dt=0.1, every_t=5.0, fits_from=(1500.0,))
     return {
         "setting": "node noise eps*eta (eps 1e-3, seed 0), t0 200, gamma 0.8, f = 0 (Section 2)",
         "grid": [n, n], "integrator": "integrating-factor Heun", "dt": dt, "t_end": t_end,
+        "points_per_thread": list(sim.points_per_thread(n, n)), "product_grid": sim.product_grid(n, n),
+        "store_kind": STORE_KIND_NAMES[sim.streaming_stores(n, n)],
         "steps": nd * every, "wall_s": wall, "point_steps_per_s_with_diagnostics": n * n * nd * every / wall,
         "first_nonfinite_t": float(ts[bad[0]]) if len(bad) else None,
         "series_every_100": {"t": ts[stride - 1::stride].tolist(), "velocity": d[stride - 1::stride, 1].tolist(),
