@@ -622,7 +622,9 @@ def main():
         if args.stores:
             sim.set_streaming_stores(w.n1, w.n2, STORE_KINDS[args.stores])
     else:
-        sim.autotune(steps=20)
+        # 100 timed steps per trial: with 20 the choice between configurations within
+        # 2 % of each other followed the trials' timing noise from box to box
+        sim.autotune(steps=100)
     pts = sim.points_per_thread(w.n1, w.n2)
     rows = 3 * w.n1 // 4 if sim.product_grid(w.n1, w.n2) else w.n1
     streaming = sim.streaming_stores(w.n1, w.n2)

@@ -289,8 +289,8 @@ int flame_get_streaming_stores(flame_plan plan, int32_t n1, int32_t n2, int32_t*
 
 /* Choose the step kernels of each grid group by timing. For every group of
  * equal grids, each configuration runs one untimed and `steps` timed steps of
- * that group (HIP events on the plan's stream), twice in two rounds over all
- * configurations (the faster time counts), and the fastest is kept if
+ * that group (HIP events on the plan's stream), in three rounds over all
+ * configurations (the fastest time counts), and the fastest is kept if
  * it runs in at most 98 % of the default's time (16 points per thread, on
  * the product grid where n1 >= 128, plain stores), else the default, so that
  * choices within timing noise of each other do not change from run to run.

@@ -1484,6 +1484,9 @@ int flame_get_streaming_stores(flame_plan p, int32_t n1, int32_t n2, int32_t* en
 // A configuration replaces the default only if it runs in at most this
 // fraction of the default's time.
 constexpr float kAutotuneMargin = 0.98f;
+// Rounds over all configurations (each keeps its fastest time; the first also
+// runs while the GPU raises its clocks).
+constexpr int kAutotuneRounds = 3;
 
 struct TuneCfg {
   bool product;
@@ -1612,14 +1615,14 @@ static int autotune_jointly(flame_plan p, int steps, long long n0, hipEvent_t ev
   return rc;
 }
 
-// Each group alone: time every configuration of tune_cfgs in two rounds
-// (keeping each one's faster time: in the first round the early
+// Each group alone: time every configuration of tune_cfgs in kAutotuneRounds
+// rounds (keeping each one's fastest time: in the first round the early
 // configurations run on a GPU that is still raising its clocks), then select
 // the fastest unless the default (16 points per thread, product grid where it
 // exists, plain stores) is within kAutotuneMargin of it, so that choices
 // within timing noise of each other do not flip between runs. If the choice
 // has both Q and W non-temporal, the same kernels with only one of them
-// non-temporal are timed too (two rounds), and the faster of those is kept
+// non-temporal are timed too (as many rounds), and the faster of those is kept
 // if it is within the margin: non-temporal pieces of half a line are written
 // back unmerged, so one non-temporal buffer moves fewer bytes than two.
 static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipEvent_t ev0, hipEvent_t ev1,
@@ -1652,7 +1655,7 @@ static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipE
   const std::vector<TuneCfg> cfgs = tune_cfgs(gr);
   const TuneCfg default_cfg{gr.logn1 >= flame::kMinLogProduct, ff::kPts, ff::kPts, 0};
   std::vector<float> t_best(cfgs.size(), 1e30f);
-  for (int round = 0; round < 2; ++round) {
+  for (int round = 0; round < kAutotuneRounds; ++round) {
     for (size_t ci = 0; ci < cfgs.size(); ++ci) {
       const int rc = time_cfg(cfgs[ci], &t_best[ci]);
       if (rc) return rc;
@@ -1669,7 +1672,7 @@ static int autotune_alone(flame_plan p, size_t gi, int steps, long long n0, hipE
   if (pick.nt == 1) {
     const TuneCfg alt[2] = {TuneCfg{pick.product, pick.c, pick.r, 2}, TuneCfg{pick.product, pick.c, pick.r, 3}};
     float t_alt[2] = {1e30f, 1e30f};
-    for (int round = 0; round < 2; ++round)
+    for (int round = 0; round < kAutotuneRounds; ++round)
       for (int k = 0; k < 2; ++k) {
         const int rc = time_cfg(alt[k], &t_alt[k]);
         if (rc) return rc;
