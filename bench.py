@@ -515,9 +515,14 @@ def ensemble_leg(steps, graph_steps):
         r = timed(10)
         r["workgroups"] = ens.persistent()[1]
         runs[wgs] = r
-    ens.set_persistent(False)
     best = min(runs.values(), key=lambda r: r["ms_per_step"])
     out["persistent"] = dict(best, grids_tried={str(r["workgroups"]): r["ms_per_step"] for r in runs.values()})
+    # the same launch captured in a graph of graph_steps steps (counter reset
+    # node + cooperative kernel node), replayed
+    ens.set_persistent(True, workgroups=best["workgroups"])
+    ens.set_graph_steps(graph_steps)
+    out["persistent_graph"] = dict(timed(graph_steps), workgroups=ens.persistent()[1], graph_steps=graph_steps)
+    ens.set_persistent(False)
     return out
 
 

@@ -342,7 +342,11 @@ int flame_set_graph_steps(flame_plan plan, int32_t steps);
  * in microseconds (0: 2 s); a wait that runs out makes every workgroup stop,
  * and flame_step returns FLAME_ERR_TIMEOUT with the states undefined. In
  * this mode flame_step waits for the plan's stream before it returns (to
- * read that status); graph_steps is not used.
+ * read that status). With flame_set_graph_steps(k), 0 < k <= 1000, the
+ * launches are replays of a hipGraph holding k steps: a node that zeroes the
+ * counters, then the persistent kernel as a cooperative kernel node that
+ * reads the step index from the workspace; remaining steps run as direct
+ * cooperative launches.
  *
  * Requires every group of the plan on the product grid with col_pts = 12,
  * row_pts = 16, plain stores, integrator 0 and no forcing, with n1 in

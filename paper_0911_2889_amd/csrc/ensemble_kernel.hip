@@ -120,13 +120,14 @@ __device__ bool ens_meet(unsigned* cnt, unsigned target, int* err, unsigned long
 
 }  // namespace
 
-// Steps n0 .. n0 + steps - 1 of every flame, one EnsembleItem per workgroup.
-// A launch that finds *err already set (by an earlier launch of the same
-// call) does nothing.
+// Steps n0 .. n0 + steps - 1 of every flame, one EnsembleItem per workgroup
+// (graph replays add the step index *nbase to n0). A launch that finds *err
+// already set (by an earlier launch of the same call) does nothing.
 __global__ void __launch_bounds__(kEnsThreads) __attribute__((amdgpu_waves_per_eu(COL_WAVES_PER_EU)))
     ensemble_kernel(const FlameDev* __restrict__ fls, const EnsembleItem* __restrict__ items,
-                    unsigned* __restrict__ arrive, int* __restrict__ err, long long n0, int steps,
-                    unsigned long long limit) {
+                    unsigned* __restrict__ arrive, int* __restrict__ err, long long n0,
+                    const long long* __restrict__ nbase, int steps, unsigned long long limit) {
+  if (nbase) n0 += *nbase;
   const EnsembleItem it = items[blockIdx.x];
   if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   unsigned* const cnt = arrive + (size_t)it.flame * kEnsArriveStride;
@@ -169,15 +170,24 @@ int ensemble_blocks_per_cu() {
   return nb;
 }
 
-hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleItem* items, int nitems,
-                           unsigned* arrive, int narrive, int* err, bool clear_err, long long n0, int steps,
-                           unsigned long long limit) {
+KernelLaunch ensemble_reset_info() {
+  return KernelLaunch{reinterpret_cast<const void*>(&ensemble_reset_kernel), 256, 0};
+}
+
+void launch_ensemble_reset(hipStream_t st, unsigned* arrive, int narrive, int* err, bool clear_err) {
   const int rb = (narrive + 255) / 256 < 1024 ? (narrive + 255) / 256 : 1024;
   hipLaunchKernelGGL(ensemble_reset_kernel, dim3(rb > 0 ? rb : 1), dim3(256), 0, st, arrive, narrive, err,
                      clear_err ? 1 : 0);
+}
+
+hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleItem* items, int nitems,
+                           unsigned* arrive, int narrive, int* err, long long n0, int steps,
+                           unsigned long long limit) {
+  launch_ensemble_reset(st, arrive, narrive, err, false);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  void* args[] = {&fls, &items, &arrive, &err, &n0, &steps, &limit};
+  const long long* nbase = nullptr;
+  void* args[] = {&fls, &items, &arrive, &err, &n0, &nbase, &steps, &limit};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&ensemble_kernel), dim3(nitems),
                                     dim3(kEnsThreads), args, (unsigned)kEnsLds, st);
 }

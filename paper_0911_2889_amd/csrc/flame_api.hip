@@ -252,9 +252,13 @@ struct flame_plan_s {
   flame::EnsembleItem* d_items = nullptr;
   unsigned* d_arrive = nullptr;
   int* d_err = nullptr;
+  hipGraph_t ens_graph = nullptr;  // graph_steps steps of the persistent launch
+  hipGraphExec_t ens_graph_exec = nullptr;
   ~flame_plan_s() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (ens_graph_exec) (void)hipGraphExecDestroy(ens_graph_exec);
+    if (ens_graph) (void)hipGraphDestroy(ens_graph);
     std::vector<hipEvent_t> all(ev_pool);
     for (auto& v : ev_used) all.insert(all.end(), v.begin(), v.end());
     std::sort(all.begin(), all.end());
@@ -414,6 +418,17 @@ void drop_graph(flame_plan p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->graph_exec = nullptr;
   p->graph = nullptr;
+}
+
+// Destroy the persistent launch's graph (it bakes in the partition, the wait
+// limit and graph_steps), after draining the plan's stream.
+void drop_ens_graph(flame_plan p) {
+  if (!p->ens_graph_exec && !p->ens_graph) return;
+  (void)hipStreamSynchronize(p->stream);
+  if (p->ens_graph_exec) (void)hipGraphExecDestroy(p->ens_graph_exec);
+  if (p->ens_graph) (void)hipGraphDestroy(p->ens_graph);
+  p->ens_graph_exec = nullptr;
+  p->ens_graph = nullptr;
 }
 
 // graph_steps steps of every flame: for each grid-size group a chain
@@ -1097,7 +1112,8 @@ int ens_prepare(flame_plan p) {
   if (p->ens_wgs > 0) wgs = std::min(wgs, p->ens_wgs);
   const std::vector<int> sig = ens_signature(p, wgs);
   if (!p->ens_items.empty() && sig == p->ens_sig) return FLAME_OK;
-  // an earlier upload may still read the host table
+  // an earlier upload may still read the host table; the graph holds the old grid
+  drop_ens_graph(p);
   e = hipStreamSynchronize(p->stream);
   if (e != hipSuccess) return hip_fail(e, "stream synchronise");
   std::vector<flame::EnsembleItem> items;
@@ -1114,22 +1130,87 @@ int ens_prepare(flame_plan p) {
   return FLAME_OK;
 }
 
-// nsteps steps of every flame in persistent launches of at most kEnsMaxSteps
-// steps; waits for them and reports a wait that ran out.
+// The persistent launch as a graph: a node that zeroes the arrival counters,
+// then the ensemble kernel as a cooperative node for graph_steps steps from
+// the step index the replay reads from the workspace counter.
+int build_ens_graph(flame_plan p) {
+  drop_ens_graph(p);
+  hipError_t e = hipGraphCreate(&p->ens_graph, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate (persistent)");
+  const flame::KernelLaunch rk = flame::ensemble_reset_info(), ek = flame::ensemble_kernel_info();
+  unsigned* arrive = p->d_arrive;
+  int narrive = p->nfl * flame::kEnsArriveStride, clear = 0;
+  int* err = p->d_err;
+  void* rargs[] = {&arrive, &narrive, &err, &clear};
+  hipKernelNodeParams rp{};
+  rp.func = const_cast<void*>(rk.func);
+  rp.gridDim = dim3(std::min(1024, std::max(1, (narrive + 255) / 256)));
+  rp.blockDim = dim3(rk.threads);
+  rp.sharedMemBytes = 0;
+  rp.kernelParams = rargs;
+  hipGraphNode_t rn, en;
+  e = hipGraphAddKernelNode(&rn, p->ens_graph, nullptr, 0, &rp);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (persistent reset)");
+  const flame::FlameDev* fls = p->ddev;
+  const flame::EnsembleItem* items = p->d_items;
+  long long n0 = 0;
+  const long long* nbase = p->counter;
+  int steps = p->graph_steps;
+  unsigned long long limit = p->ens_limit;
+  void* eargs[] = {&fls, &items, &arrive, &err, &n0, &nbase, &steps, &limit};
+  hipKernelNodeParams ep{};
+  ep.func = const_cast<void*>(ek.func);
+  ep.gridDim = dim3((unsigned)p->ens_items.size());
+  ep.blockDim = dim3(ek.threads);
+  ep.sharedMemBytes = (unsigned)ek.lds;
+  ep.kernelParams = eargs;
+  e = hipGraphAddKernelNode(&en, p->ens_graph, &rn, 1, &ep);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphAddKernelNode (persistent)");
+  hipKernelNodeAttrValue coop{};
+  coop.cooperative = 1;
+  e = hipGraphKernelNodeSetAttribute(en, hipKernelNodeAttributeCooperative, &coop);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphKernelNodeSetAttribute (cooperative)");
+  e = hipGraphInstantiate(&p->ens_graph_exec, p->ens_graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate (persistent)");
+  return FLAME_OK;
+}
+
+// nsteps steps of every flame: replays of the persistent graph while
+// graph_steps (at most kEnsMaxSteps) steps remain, the rest as direct
+// cooperative launches of at most kEnsMaxSteps steps; then waits for them
+// and reports a wait that ran out.
 int ens_steps(flame_plan p, int nsteps) {
   int rc = ens_prepare(p);
   if (rc) return rc;
-  bool first = true;
+  const int narrive = p->nfl * flame::kEnsArriveStride;
+  flame::launch_ensemble_reset(p->stream, p->d_arrive, narrive, p->d_err, true);
+  rc = last_launch("persistent ensemble reset");
+  if (rc) return rc;
+  const int gs = p->graph_steps;
+  if (gs > 0 && gs <= kEnsMaxSteps && nsteps >= gs) {
+    if (!p->ens_graph_exec) {
+      rc = build_ens_graph(p);
+      if (rc) return rc;
+    }
+    while (nsteps >= gs) {
+      flame::launch_set_step(p->stream, p->counter, p->n);
+      {
+        Timed tm(p, KIND_GRAPH);
+        const hipError_t e = hipGraphLaunch(p->ens_graph_exec, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch (persistent)");
+      }
+      p->n += gs;
+      nsteps -= gs;
+    }
+  }
   while (nsteps > 0) {
     const int k = std::min(nsteps, kEnsMaxSteps);
     {
       Timed tm(p, KIND_GRAPH);
       const hipError_t e = flame::launch_ensemble(p->stream, p->ddev, p->d_items, (int)p->ens_items.size(),
-                                                  p->d_arrive, p->nfl * flame::kEnsArriveStride, p->d_err, first,
-                                                  p->n, k, p->ens_limit);
+                                                  p->d_arrive, narrive, p->d_err, p->n, k, p->ens_limit);
       if (e != hipSuccess) return hip_fail(e, "persistent ensemble launch");
     }
-    first = false;
     p->n += k;
     nsteps -= k;
   }
@@ -1741,6 +1822,7 @@ int flame_set_graph_steps(flame_plan p, int32_t steps) {
   if (steps != p->graph_steps) {
     DeviceGuard g(p->device);
     drop_graph(p);
+    drop_ens_graph(p);
     p->graph_steps = steps;
   }
   return FLAME_OK;
@@ -1752,13 +1834,14 @@ int flame_set_persistent(flame_plan p, int32_t enable, int32_t workgroups, int32
   if (enable != 0 && enable != 1) return fail(FLAME_ERR_INVALID_ARG, "enable must be 0 or 1");
   if (workgroups < 0) return fail(FLAME_ERR_INVALID_ARG, "workgroups must be >= 0");
   if (wait_limit_us < 0) return fail(FLAME_ERR_INVALID_ARG, "wait_limit_us must be >= 0");
+  DeviceGuard g(p->device);
+  drop_ens_graph(p);  // it bakes in the grid size and the wait limit
   if (!enable) {
     p->persistent = false;
     return FLAME_OK;
   }
   rc = ens_check(p);
   if (rc) return rc;
-  DeviceGuard g(p->device);
   int coop = 0, khz = 0;
   hipError_t e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device);

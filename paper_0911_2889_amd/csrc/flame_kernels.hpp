@@ -63,17 +63,21 @@ bool launch_circle_step(int logn, const CircleDev& d, long long n, int nsteps, h
 bool launch_circle_diag(int logn, const CircleDev& d, long long n, double* out, hipStream_t st);
 
 // Persistent ensemble kernel (EnsembleItem): whether it has the bodies for an
-// N1 x N2 flame, its function and shape, and how many of its workgroups fit
-// on one compute unit (0 if the query fails). launch_ensemble zeroes the
-// narrive arrival counters (and *err if clear_err), then launches nitems
-// workgroups cooperatively for steps n0 .. n0 + steps - 1; a bounded wait
-// that runs out (limit: wall-clock ticks) sets *err. It returns the launch's
-// error code.
+// N1 x N2 flame, its function and shape (arguments: fls, items, arrive, err,
+// n0, nbase, steps, limit), and how many of its workgroups fit on one
+// compute unit (0 if the query fails). launch_ensemble_reset zeroes the
+// narrive arrival counters (and *err if clear_err; function and shape from
+// ensemble_reset_info, arguments arrive, narrive, err, clear_err as int).
+// launch_ensemble zeroes the counters, then launches nitems workgroups
+// cooperatively for steps n0 .. n0 + steps - 1; a bounded wait that runs out
+// (limit: wall-clock ticks) sets *err. It returns the launch's error code.
 bool ensemble_supports(int logn1, int logn2);
 KernelLaunch ensemble_kernel_info();
+KernelLaunch ensemble_reset_info();
 int ensemble_blocks_per_cu();
+void launch_ensemble_reset(hipStream_t st, unsigned* arrive, int narrive, int* err, bool clear_err);
 hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleItem* items, int nitems,
-                           unsigned* arrive, int narrive, int* err, bool clear_err, long long n0, int steps,
+                           unsigned* arrive, int narrive, int* err, long long n0, int steps,
                            unsigned long long limit);
 
 void launch_set_spectrum(hipStream_t st, const FlameDev* fl, int flame, int total, const void* half);

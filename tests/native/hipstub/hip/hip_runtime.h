@@ -77,6 +77,13 @@ hipError_t hipGraphDestroy(hipGraph_t g);
 hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGraphNode_t* deps, size_t ndeps,
                                  const hipKernelNodeParams* p);
 hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, hipGraphNode_t* err_node, char* log, size_t n);
+enum hipKernelNodeAttrID { hipKernelNodeAttributeCooperative = 2 };
+union hipKernelNodeAttrValue {
+  char pad[64];
+  int cooperative;
+};
+hipError_t hipGraphKernelNodeSetAttribute(hipGraphNode_t node, hipKernelNodeAttrID attr,
+                                          const hipKernelNodeAttrValue* value);
 hipError_t hipGraphExecDestroy(hipGraphExec_t x);
 hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s);
 

@@ -204,17 +204,22 @@ hipError_t hipGraphAddKernelNode(hipGraphNode_t* node, hipGraph_t g, const hipGr
   for (size_t i = 0; i < ndeps; ++i)
     if (!deps || std::find(g_nodes.begin(), g_nodes.end(), deps[i]) == g_nodes.end())
       violation("kernel node depends on an unknown node");
-  // the runtime copies the arguments now: the step kernels take 4 or 5 arguments of 8 bytes
+  // the runtime copies the arguments now; every kernel the library puts in a
+  // graph takes a device pointer first (its sizes beyond that vary)
   std::vector<uint64_t> args;
-  for (int i = 0; i < 4; ++i) {
-    uint64_t v;
-    std::memcpy(&v, p->kernelParams[i], sizeof v);
-    args.push_back(v);
-  }
+  uint64_t v;
+  std::memcpy(&v, p->kernelParams[0], sizeof v);
+  args.push_back(v);
   g->nodes.push_back(args);
   *node = new hipGraphNode{g_next++};
   g->owned.push_back(*node);
   g_nodes.push_back(*node);
+  return hipSuccess;
+}
+hipError_t hipGraphKernelNodeSetAttribute(hipGraphNode_t node, hipKernelNodeAttrID attr,
+                                          const hipKernelNodeAttrValue* value) {
+  if (std::find(g_nodes.begin(), g_nodes.end(), node) == g_nodes.end()) violation("attribute of an unknown node");
+  if (attr != hipKernelNodeAttributeCooperative || !value) violation("unexpected kernel node attribute");
   return hipSuccess;
 }
 hipError_t hipGraphInstantiate(hipGraphExec_t* x, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
@@ -325,13 +330,18 @@ bool ensemble_supports(int logn1, int logn2) {
   return logn1 >= kEnsMinLog1 && logn1 <= kEnsMaxLog1 && logn2 >= kEnsMinLog2 && logn2 <= kEnsMaxLog2;
 }
 KernelLaunch ensemble_kernel_info() { return KernelLaunch{kDummyKernel, kEnsThreads, 1024}; }
+KernelLaunch ensemble_reset_info() { return KernelLaunch{kDummyKernel, 256, 0}; }
+void launch_ensemble_reset(hipStream_t st, unsigned* arrive, int narrive, int* err, bool clear_err) {
+  std::memset(arrive, 0, sizeof(unsigned) * (size_t)narrive);
+  if (clear_err) *err = 0;
+  hip_stub_launch(kDummyKernel, st);
+}
 int ensemble_blocks_per_cu() { return 2; }
 // Reads every item and the flames it names, and checks the partition: every
 // flame is stepped either whole by exactly one item or by parts 0 .. parts-1,
 // each exactly once, and its arrival counter lies inside the counter array.
 hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleItem* items, int nitems,
-                           unsigned* arrive, int narrive, int* err, bool clear_err, long long, int steps,
-                           unsigned long long) {
+                           unsigned* arrive, int narrive, int* err, long long, int steps, unsigned long long) {
   if (nitems <= 0 || nitems > 2 * 256) violation("persistent grid outside the co-resident capacity");
   if (steps <= 0) violation("persistent launch of no steps");
   if (narrive % kEnsArriveStride) violation("arrival counters not a whole number of flames");
@@ -361,7 +371,7 @@ hipError_t launch_ensemble(hipStream_t st, const FlameDev* fls, const EnsembleIt
       if (c != 1) violation("flame part stepped other than once");
   }
   std::memset(arrive, 0, sizeof(unsigned) * (size_t)narrive);
-  if (clear_err) *err = 0;
+  (void)err;
   hip_stub_launch(kDummyKernel, st);
   hip_stub_launch(kDummyKernel, st);
   return hipSuccess;

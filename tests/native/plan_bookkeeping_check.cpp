@@ -196,6 +196,13 @@ int main(int argc, char** argv) {
       CHECK(flame_set_persistent(pl.p, 1, w, 50));
       CHECK(flame_step(pl.p, 2));
     }
+    // graph replays of the persistent launch, rebuilt on every setting that bakes into them
+    for (int gs : {5, 3, 1000, 1001, 0, 7}) {
+      CHECK(flame_set_graph_steps(pl.p, gs));
+      CHECK(flame_step(pl.p, 11));
+      CHECK(flame_set_persistent(pl.p, 1, gs == 7 ? 100 : 0, 0));
+      CHECK(flame_step(pl.p, 7));
+    }
     // a configuration the persistent kernel lacks is refused, then restored
     CHECK(flame_set_points_per_thread(pl.p, 256, 512, 16, 16));
     if (flame_step(pl.p, 1) != FLAME_ERR_INVALID_ARG) return 6;

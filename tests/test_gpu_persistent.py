@@ -122,3 +122,32 @@ def test_persistent_refuses_configurations_it_has_no_kernel_for():
     with pytest.raises(native.FlameError) as exc:
         ok.step(1)  # a later change the persistent kernel lacks is refused at the step
     assert exc.value.code == native.FLAME_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("graph_steps", [1, 8, 50])
+def test_persistent_graph_replays_match_direct_launches_bit_for_bit(graph_steps):
+    """The persistent launch captured in a graph of graph_steps steps (reset
+    node, then the cooperative kernel node reading the step index from the
+    workspace), replayed with a direct launch for the remainder: 30 and then
+    23 steps, so replays start at several step indices, against per-group
+    launches bit for bit."""
+    members = [synth.Workload(f"g{i}", n1, n2, 30, 0.25, "disc", 1e-3, -1.0, 4300 + i, max_norm=16)
+               for i, (n1, n2) in enumerate(MIXED)]
+    halves = [synth.workload_spectrum(w) for w in members]
+    print(f"persistent case: graph replays of {graph_steps} steps", flush=True)
+    direct = make_ensemble(members, halves)
+    direct.step(53)
+    pers = make_ensemble(members, halves)
+    pers.set_persistent(True)
+    pers.set_graph_steps(graph_steps)
+    pers.step(30)
+    pers.step(23)
+    assert pers.step_index == 53
+    for f in range(len(members)):
+        assert np.array_equal(pers.spectrum(f).cpu().numpy(), direct.spectrum(f).cpu().numpy()), f
+    # a change of the wait bound rebuilds the graph; the plan keeps stepping
+    pers.set_persistent(True, wait_limit_us=500000)
+    pers.step(8)
+    direct.step(8)
+    for f in (0, 8, 12):
+        assert np.array_equal(pers.spectrum(f).cpu().numpy(), direct.spectrum(f).cpu().numpy()), f
