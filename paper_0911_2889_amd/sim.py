@@ -248,8 +248,9 @@ class FlameEnsemble:
         native.check(self.lib.flame_set_graph_steps(self.plan, int(steps)))
 
     def set_persistent(self, enable=True, workgroups=0, wait_limit_us=0):
-        """Step every flame in one persistent (cooperative) launch per call
-        (workgroups 0: all that fit; wait_limit_us 0: 2 s per wait)."""
+        """Step every flame in one persistent (cooperative) launch per call, or,
+        with set_graph_steps(k), in replays of a graph holding that launch for k
+        steps (workgroups 0: all that fit; wait_limit_us 0: 2 s per wait)."""
         native.check(self.lib.flame_set_persistent(self.plan, int(bool(enable)), int(workgroups),
                                                    int(wait_limit_us)))
 
