@@ -621,7 +621,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU slab decomposition is a design note, not part of this build)", file=sys.stderr)
+              f"(the multi-GPU slab decomposition is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
