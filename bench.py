@@ -546,8 +546,8 @@ def ensemble_leg(steps, graph_steps):
     # configuration (product grid, 12 column and 16 row points per thread,
     # plain stores), against graph replays of the same kernels' bodies
     for n1, n2 in grids:
+        ens.set_product_grid(n1, n2, True)  # first: 12 column points per thread need the product grid
         ens.set_points_per_thread(n1, n2, 12, 16)
-        ens.set_product_grid(n1, n2, True)
         ens.set_streaming_stores(n1, n2, False)
     ens.set_graph_steps(graph_steps)
     out["graph_persistent_config"] = timed(graph_steps)
