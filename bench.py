@@ -488,6 +488,17 @@ def circle_long_run_leg(n=8192, count=64, t_end=4000.0, dt=0.1, every_t=5.0, fit
     }
 
 
+def use_persistent_config(ens, grids):
+    """Put every grid group of an ensemble on the persistent kernel's
+    configuration: product grid, 12 column and 16 row points per thread, plain
+    stores, whatever the autotuner chose before (the product grid first: the
+    12-point column kernels need it)."""
+    for n1, n2 in grids:
+        ens.set_product_grid(n1, n2, True)
+        ens.set_points_per_thread(n1, n2, 12, 16)
+        ens.set_streaming_stores(n1, n2, False)
+
+
 def ensemble_leg(steps, graph_steps):
     """The batched ensemble (256 flames of three grids) stepped in graphs of
     graph_steps steps, and with direct launches, timed with HIP events."""
@@ -545,10 +556,7 @@ def ensemble_leg(steps, graph_steps):
     # A/B of the persistent launch: every group on the persistent kernel's
     # configuration (product grid, 12 column and 16 row points per thread,
     # plain stores), against graph replays of the same kernels' bodies
-    for n1, n2 in grids:
-        ens.set_product_grid(n1, n2, True)  # first: 12 column points per thread need the product grid
-        ens.set_points_per_thread(n1, n2, 12, 16)
-        ens.set_streaming_stores(n1, n2, False)
+    use_persistent_config(ens, grids)
     ens.set_graph_steps(graph_steps)
     out["graph_persistent_config"] = timed(graph_steps)
     ens.set_graph_steps(0)

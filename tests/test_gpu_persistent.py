@@ -151,3 +151,35 @@ def test_persistent_graph_replays_match_direct_launches_bit_for_bit(graph_steps)
     direct.step(8)
     for f in (0, 8, 12):
         assert np.array_equal(pers.spectrum(f).cpu().numpy(), direct.spectrum(f).cpu().numpy()), f
+
+
+def test_persistent_configuration_from_any_autotuned_choice():
+    """The benchmark's switch to the persistent kernel's configuration works from
+    every choice the autotuner can leave a group in (N1 rows with 8 or 16 column
+    points per thread, non-temporal stores), and the persistent launch then
+    matches per-group launches on the same configuration bit for bit."""
+    import bench
+    members = [synth.Workload(f"c{i}", n1, n2, 30, 0.25, "disc", 1e-3, -1.0, 4400 + i, max_norm=16)
+               for i, (n1, n2) in enumerate([(128, 256), (128, 256), (256, 512), (512, 1024)])]
+    halves = [synth.workload_spectrum(w) for w in members]
+    grids = sorted({(w.n1, w.n2) for w in members})
+    from paper_0911_2889_amd import FlameEnsemble
+    outs = []
+    for persistent in (False, True):
+        ens = FlameEnsemble(member_descs(members))
+        for (n1, n2), (cp, stores) in zip(grids, ((8, 1), (16, 3), (16, 0))):
+            ens.set_product_grid(n1, n2, False)
+            ens.set_points_per_thread(n1, n2, cp, 16)
+            ens.set_streaming_stores(n1, n2, stores)
+        print(f"persistent case: configuration switch, persistent {persistent}", flush=True)
+        bench.use_persistent_config(ens, grids)
+        for n1, n2 in grids:
+            assert ens.points_per_thread(n1, n2) == (12, 16) and ens.product_grid(n1, n2)
+        for f, h in enumerate(halves):
+            ens.set_spectrum(h, flame=f)
+        if persistent:
+            ens.set_persistent(True)
+        ens.step(12)
+        outs.append([ens.spectrum(f).cpu().numpy() for f in range(len(members))])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
