@@ -642,7 +642,7 @@ def main():
     import torch
 
     import synth
-    from paper_0911_2889_amd import FlameSim
+    from paper_0911_2889_amd import FlameSim, native
 
     w = synth.WORKLOADS[args.workload]
     half = synth.workload_spectrum(w)
@@ -779,27 +779,35 @@ def main():
         "dominant_kernel_frac": achieved / copy_gbs,
     }
 
+    # The other legs: a refusal by the library (FlameError, raised before any
+    # launch) is recorded under the leg's key instead of ending the run, so the
+    # line above is never lost to an optional leg.
+    def leg(key, fn, *a, **kw):
+        try:
+            result[key] = fn(*a, **kw)
+        except native.FlameError as e:
+            result[key] = {"error": str(e)}
+
     if args.forcing_steps > 0:
-        result["forced"] = forced_leg(sim, w, half, args.forcing_steps, graph_steps, run_steps,
-                                      ms / args.steps, rows)
+        leg("forced", forced_leg, sim, w, half, args.forcing_steps, graph_steps, run_steps, ms / args.steps, rows)
 
     if args.heun_steps > 0:
-        result["heun"] = heun_leg(w, half, args.heun_steps, graph_steps, args.diag_every, ms / args.steps)
+        leg("heun", heun_leg, w, half, args.heun_steps, graph_steps, args.diag_every, ms / args.steps)
 
     if not args.no_long_run:
-        result["long_run"] = long_run_leg(t_end=args.long_run_t_end)
+        leg("long_run", long_run_leg, t_end=args.long_run_t_end)
 
     if args.circle_steps > 0:
         rec = circle_record()
-        result["circles"] = circle_leg(steps=args.circle_steps,
-                                       valu_per_wave_step=rec.get("valu_per_wave_step") if rec else None)
+        leg("circles", circle_leg, steps=args.circle_steps,
+            valu_per_wave_step=rec.get("valu_per_wave_step") if rec else None)
     if not args.no_circle_long_run:
-        result["circle_long_run"] = circle_long_run_leg()
+        leg("circle_long_run", circle_long_run_leg)
 
     if args.adjoint_steps > 0:
-        result["adjoint"] = adjoint_leg(args.adjoint_steps, 50)
+        leg("adjoint", adjoint_leg, args.adjoint_steps, 50)
     if args.ensemble_steps > 0:
-        result["ensemble"] = ensemble_leg(args.ensemble_steps, 50)
+        leg("ensemble", ensemble_leg, args.ensemble_steps, 50)
 
     if not args.no_cpu:
         base, nref, ref = cpu_oracle_baseline(w, half, args.cpu_seconds)
