@@ -1039,6 +1039,10 @@ int flame_step_index(flame_plan p, int64_t* n) {
   return FLAME_OK;
 }
 
+}  // extern "C"
+
+// Persistent ensemble launch: partition, graph and launches (C++ helpers of
+// the entry points below).
 namespace {
 
 // Why the flames of group gr cannot run in the persistent ensemble kernel
@@ -1227,6 +1231,8 @@ int ens_steps(flame_plan p, int nsteps) {
 }
 
 }  // namespace
+
+extern "C" {
 
 int flame_step(flame_plan p, int32_t nsteps) {
   int rc = check_plan(p);
