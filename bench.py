@@ -525,20 +525,21 @@ def ensemble_leg(steps, graph_steps):
     nbytes = sum(sum(algorithmic_bytes(w.n1, w.n2, 3 * w.n1 // 4 if ens.product_grid(w.n1, w.n2) else w.n1).values())
                  for w in members)
     out = {"flames": len(members), "grids": "128 x 128x256, 96 x 256x512, 32 x 512x1024", "steps": steps,
-           "timing": "median of 3 timed runs of `steps` steps from the initial states",
+           "timing": "median of 3 back-to-back timed runs of `steps` steps after 200 untimed ones",
+           "warmup_steps": 200,
            "points": points, "step_bytes": nbytes, "points_per_thread": tuned}
 
     def timed(warm, runs=3):
-        # the median of `runs` timed runs of `steps` steps, each from the initial states
+        # steady state: the initial states, `warm` untimed steps (they build the
+        # graph or the persistent partition; the first hundreds of steps after a
+        # pause run ~6 % slower), then the median of `runs` back-to-back timed
+        # runs of `steps` steps
         for f, h in enumerate(halves):
             ens.set_spectrum(h, flame=f)
-        ens.step(warm)  # warm-up (builds the graph, or the persistent partition)
+        ens.step(warm)
+        torch.cuda.synchronize()
         per_run = []
         for _ in range(runs):
-            for f, h in enumerate(halves):
-                ens.set_spectrum(h, flame=f)
-            ens.step(0)
-            torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             ens.step(steps)
@@ -552,18 +553,18 @@ def ensemble_leg(steps, graph_steps):
 
     for mode, gs in (("graph", graph_steps), ("direct", 0)):
         ens.set_graph_steps(gs)
-        out[mode] = timed(gs if gs else 10)
+        out[mode] = timed(200)
     # A/B of the persistent launch: every group on the persistent kernel's
     # configuration (product grid, 12 column and 16 row points per thread,
     # plain stores), against graph replays of the same kernels' bodies
     use_persistent_config(ens, grids)
     ens.set_graph_steps(graph_steps)
-    out["graph_persistent_config"] = timed(graph_steps)
+    out["graph_persistent_config"] = timed(200)
     ens.set_graph_steps(0)
     runs = {}
     for wgs in (0, 256):
         ens.set_persistent(True, workgroups=wgs)
-        r = timed(10)
+        r = timed(200)
         r["workgroups"] = ens.persistent()[1]
         runs[wgs] = r
     best = min(runs.values(), key=lambda r: r["ms_per_step"])
@@ -572,7 +573,7 @@ def ensemble_leg(steps, graph_steps):
     # node + cooperative kernel node), replayed
     ens.set_persistent(True, workgroups=best["workgroups"])
     ens.set_graph_steps(graph_steps)
-    out["persistent_graph"] = dict(timed(graph_steps), workgroups=ens.persistent()[1], graph_steps=graph_steps)
+    out["persistent_graph"] = dict(timed(200), workgroups=ens.persistent()[1], graph_steps=graph_steps)
     ens.set_persistent(False)
     return out
 

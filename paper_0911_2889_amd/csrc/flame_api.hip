@@ -477,8 +477,17 @@ int build_graph(flame_plan p) {
     last[gi] = cn;
     return FLAME_OK;
   };
+  // groups with more points per step first: their chains are the longest, and
+  // the replay starts them first (on the 256-flame ensemble 2-3 % faster than
+  // the order of first appearance)
+  std::vector<size_t> order(p->groups.size());
+  for (size_t gi = 0; gi < order.size(); ++gi) order[gi] = gi;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    const Group &ga = p->groups[a], &gb = p->groups[b];
+    return (long long)ga.count << (ga.logn1 + ga.logn2) > (long long)gb.count << (gb.logn1 + gb.logn2);
+  });
   for (int s = 0; s < p->graph_steps; ++s)
-    for (size_t gi = 0; gi < p->groups.size(); ++gi)
+    for (const size_t gi : order)
       for (int pass = 0; pass < p->groups[gi].passes(); ++pass) {
         const int rc = add_pass(gi, s, pass);
         if (rc) return rc;
