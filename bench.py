@@ -12,6 +12,7 @@ before the timed region starts. Prints one JSON line.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -20,6 +21,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X FP32 vector peak (256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2
+# for packed FP32 x 2.4 GHz); without packed FP32 instructions half of it
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 CIRCLE_SOURCES = ("paper_0911_2889_amd/csrc/circle_kernels.hip", "paper_0911_2889_amd/csrc/fft_engine.hpp",
                   "paper_0911_2889_amd/csrc/flame_dev.hpp",
                   "paper_0911_2889_amd/csrc/kernel_common.hpp")
@@ -44,6 +48,15 @@ def algorithmic_bytes(n1, n2, rows=None, forcing=False):
     row = 8 * (rows * (2 * k2 + 1) + rows * (k2 + 1))
     col = 8 * (rows * (k2 + 1) + (3 if forcing else 2) * (2 * k1 + 1) * (k2 + 1) + rows * (2 * k2 + 1))
     return {"row": row, "col": col}
+
+
+def row_pass_flops(rows, cols):
+    """Nominal flops of one row pass (the row kernel's launch): per grid row the
+    inverse complex transform of the packed gradient (5 L log2 L on L = cols
+    points), |z|^2 (3 per point) and half of the forward complex transform that
+    serves two real rows (2.5 L log2 L)."""
+    lg = math.log2(cols)
+    return rows * (5.0 * cols * lg + 3.0 * cols + 2.5 * cols * lg)
 
 
 # store kinds of flame_set_streaming_stores: names on the command line and in the record
@@ -400,9 +413,10 @@ def long_run_leg(n=8192, t_end=2600.0, dt=0.1, every_t=5.0, fits_from=(1500.0,))
 
 # One wave-instruction per CU per clock (4 SIMDs x 16 lanes, wave64, FP32
 # not packed): the vector-ALU issue peak of 256 CUs at 2.4 GHz, and its FP32
-# rate (an FMA is 2 flops per lane).
+# rate (an FMA is 2 flops per lane), half of the packed FP32 peak above; the
+# kernels here are built without packed FP32 instructions.
 VALU_PEAK_INSTR_S = 256 * 2.4e9
-FP32_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def circle_leg(n=4096, count=2048, steps=200, valu_per_wave_step=None):
@@ -437,7 +451,8 @@ def circle_leg(n=4096, count=2048, steps=200, valu_per_wave_step=None):
            "point_steps_per_s": n * count * steps / (ms * 1e-3),
            "nominal_fft_tflops": flops / (ms * 1e-3) / 1e12,
            "fp32_vector_peak_tflops": FP32_VECTOR_PEAK_TFLOPS,
-           "nominal_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS}
+           "nominal_frac": flops / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+           "nominal_frac_of_unpacked_peak": flops / (ms * 1e-3) / 1e12 / FP32_UNPACKED_PEAK_TFLOPS}
     if valu_per_wave_step:
         g = n // 16
         per_wg = max(1, 256 // g)  # circle pairs per workgroup
@@ -729,9 +744,16 @@ def main():
 
     nbytes = algorithmic_bytes(w.n1, w.n2, rows)
     per_launch = {k: kt[k][0] / max(1, kt[k][1]) for k in ("row", "col")}
-    dom = max(per_launch, key=per_launch.get)
+    # The roofline object is the column kernel's: it moves most of the step's
+    # bytes (54.5 of 92.2 MB at 2048x4096) and is HBM-bound, while the row kernel
+    # is bound by its vector ALU (its own figures follow under roofline_row). The
+    # two take about the same time; which is longer changes from box to box.
+    dom = "col"
     achieved = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
     traffic = measured_traffic(dom, w.name, pts[0] if dom == "col" else pts[1], rows, streaming)
+    row_cols = 3 * w.n2 // 4 if pts[1] == 12 else w.n2
+    row_flops = row_pass_flops(rows, row_cols)
+    row_tflops = row_flops / (per_launch["row"] * 1e-3) / 1e12
     result = {
         "metric": "flame point-steps/s fwd & adjoint, FP32 vs FP64 oracle at 1e-5; % HBM roofline",
         "value": w.points * args.steps / (ms * 1e-3),
@@ -763,6 +785,19 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": nbytes[dom],
             "ms_per_launch": per_launch[dom],
+        },
+        "roofline_row": {
+            "bound": "alu",
+            "kernel": "row_kernel",
+            "achieved": row_tflops,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": row_tflops / FP32_VECTOR_PEAK_TFLOPS,
+            "frac_of_unpacked_peak": row_tflops / FP32_UNPACKED_PEAK_TFLOPS,
+            "flops_per_launch": row_flops,
+            "ms_per_launch": per_launch["row"],
+            "hbm_GB_s": nbytes["row"] / (per_launch["row"] * 1e-3) / 1e9,
+            "hbm_frac": nbytes["row"] / (per_launch["row"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
         "kernels_ms_per_step": {k: kt[k][0] / max(1, args.steps) for k in ("row", "col", "diag")},
         "step_bytes": nbytes["row"] + nbytes["col"],

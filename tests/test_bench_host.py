@@ -84,3 +84,10 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_row_pass_flops_is_the_nominal_count():
+    # per row: 5 L log2 L (inverse complex transform) + 3 L (|z|^2) + 2.5 L log2 L
+    # (half of the forward complex transform of two real rows)
+    assert bench.row_pass_flops(2, 16) == 2 * (5 * 16 * 4 + 3 * 16 + 2.5 * 16 * 4)
+    assert bench.row_pass_flops(1536, 4096) == 1536 * 4096 * (7.5 * 12 + 3)
